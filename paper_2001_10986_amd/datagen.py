@@ -1,0 +1,92 @@
+"""Seeded synthetic inputs: Gaussian-blob image pairs and eps schedules.
+
+This module holds none of the method's arithmetic.  It draws the test images
+(the paper's are random Gaussian mixtures, Sec. 7.1 "Test data"; they are not
+published, so these stand in for them) and writes out the stage lists that the
+driver runs.  Both the GPU path and the oracle take their inputs from here.
+
+Recipe for one image of H x W pixels with n blobs (seed s):
+  rng = numpy.random.default_rng(s); for each blob draw, in this order,
+  centre x ~ U[0,1], centre y ~ U[0,1], std ~ U[0.03,0.15], amplitude ~ U[0.5,1];
+  density(p) = sum_blobs a * exp(-|p - c|^2 / (2 std^2)) at the pixel centres
+  p = ((col+1/2) h, (row+1/2) h), h = 1/max(H,W); then either add a floor of
+  floor*max (default 1e-3) or i.i.d. noise U[0, noise]*max per pixel; finally
+  normalise to total mass 1.
+"""
+import numpy as np
+
+
+def blob_image(H, W, n_blobs, seed, floor=1e-3, noise=0.0):
+    rng = np.random.default_rng(seed)
+    h = 1.0 / max(H, W)
+    yy = (np.arange(H) + 0.5) * h
+    xx = (np.arange(W) + 0.5) * h
+    img = np.zeros((H, W))
+    for _ in range(n_blobs):
+        cx, cy, sd, a = rng.uniform(0, 1), rng.uniform(0, 1), rng.uniform(0.03, 0.15), \
+            rng.uniform(0.5, 1.0)
+        img += a * np.exp(-((xx[None, :] - cx) ** 2 + (yy[:, None] - cy) ** 2) / (2 * sd * sd))
+    mx = img.max()
+    if noise > 0:
+        img += rng.uniform(0.0, noise, size=(H, W)) * mx
+    else:
+        img += floor * mx
+    return img / img.sum()
+
+
+def eps_schedule(N, n_levels, eps_start=1.0, final_eps=None):
+    """Stage list [(level, eps, n_half_iterations)] of the multi-scale eps-scaling driver.
+
+    Follows Sec. 7.1 ("Multi-scale and eps-scaling") in unit coordinates: on
+    level l (pixel spacing h_l) eps halves from stage to stage while
+    eps >= h_l^2/2; the first stage of a level runs 4 half-iterations
+    (A,B,A,B), later ones 2; the next level starts at the last eps of the
+    previous one (h_l^2/2 = 2 h_{l+1}^2).  On the finest level eps stops at
+    final_eps (default h^2) and 2 more half-iterations run there.
+    """
+    if final_eps is None:
+        final_eps = (1.0 / N) ** 2
+    stages = []
+    eps = float(eps_start)
+    for lev in range(n_levels):
+        Nl = N >> (n_levels - 1 - lev)
+        lo = 0.5 / Nl ** 2 if lev < n_levels - 1 else final_eps
+        first = True
+        while eps >= lo * (1 - 1e-12):
+            stages.append([lev, eps, 4 if first else 2])
+            first = False
+            eps *= 0.5
+        eps *= 2.0
+        if first:  # eps already below this level's range: run one stage at it
+            stages.append([lev, eps, 4])
+    stages[-1][2] += 2
+    return [tuple(s) for s in stages]
+
+
+# --- the benchmark configurations (image k of config c uses seed 1000*c + k) ---
+
+def config1_pair():
+    """32x32 pair, 4 blobs, floor 1e-3*max; single level, eps = 4/32^2, 40 half-iterations."""
+    mu = blob_image(32, 32, 4, 1000)
+    nu = blob_image(32, 32, 4, 1001)
+    return mu, nu, dict(s=4, n_levels=1, stages=[(0, 4.0 / 32 ** 2, 40)])
+
+
+def config2_pair(i=0, j=1):
+    """256x256 pair (images i, j of 10), 8 blobs; levels 64->128->256, eps 1 -> (1/256)^2."""
+    mu = blob_image(256, 256, 8, 2000 + i)
+    nu = blob_image(256, 256, 8, 2000 + j)
+    return mu, nu, dict(s=4, n_levels=3, stages=eps_schedule(256, 3))
+
+
+def config3_pair(seed0=3000):
+    """1024x1024 pair, 16 blobs + U[0,0.1]*max noise; 5 levels 64->1024, eps 1 -> (1/1024)^2."""
+    mu = blob_image(1024, 1024, 16, seed0, noise=0.1)
+    nu = blob_image(1024, 1024, 16, seed0 + 1, noise=0.1)
+    return mu, nu, dict(s=4, n_levels=5, stages=eps_schedule(1024, 5))
+
+
+def small_pair(N, n_blobs=4, seed=7, n_levels=1):
+    mu = blob_image(N, N, n_blobs, seed)
+    nu = blob_image(N, N, n_blobs, seed + 1)
+    return mu, nu

@@ -1,0 +1,195 @@
+"""Pins of the sparse FP64 C oracle against the dense references and against
+the exact invariants of the paper (CPU only)."""
+import numpy as np
+import pytest
+
+from oracle import dense, ddo
+from paper_2001_10986_amd import datagen
+
+
+def _basic_marg_dense(plan, basic):
+    return np.stack([plan[xs, :].sum(0) for xs in basic])
+
+
+def test_cell_solve_matches_newton():
+    # one composite cell of 8x8 pixels against a random 5x7 patch of Y points
+    rng = np.random.default_rng(1)
+    xr, xc = np.divmod(np.arange(64), 8)
+    yr = rng.integers(0, 12, 35)
+    yc = rng.integers(0, 12, 35)
+    key = np.unique(yr * 12 + yc)
+    yr, yc = np.divmod(key, 12)
+    mu = rng.uniform(0.5, 1, 64)
+    nu = rng.uniform(0.5, 1, len(key))
+    mu /= mu.sum()
+    nu /= nu.sum()
+    h, eps = 1.0 / 16, 2.0 / 256
+    r = ddo.cell_solve(xr, xc, mu, yr, yc, nu, h * h / eps, 1e-13, 100000)
+    C = ((xr[:, None] - yr[None, :]) ** 2 + (xc[:, None] - yc[None, :]) ** 2) * h * h
+    P = dense.entropic_ot_newton(C, mu, nu, eps)[2]
+    assert r["rc"] == 0
+    assert np.abs(r["plan"] - P).max() < 1e-12
+    assert np.allclose(r["plan"].sum(0), nu, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("N,s,epsf", [(8, 2, 2.0), (16, 4, 4.0)])
+def test_half_iterations_match_dense_algorithm1(N, s, epsf):
+    mu, nu = datagen.small_pair(N, 3, seed=21)
+    eps = epsf / N ** 2
+    o = ddo.Oracle(mu, nu, s=s, n_levels=1, eps=eps, err_tol=1e-12, trunc=0.0, max_iter=100000)
+    basic, ca, cb = dense.grid_partitions(N, N, s)
+    C = dense.grid_cost(N, N, 1.0 / N)
+    m, n = mu.ravel(), nu.ravel()
+    pi0 = np.zeros((N * N, N * N))
+    for xs in basic:
+        pi0[xs, :] = np.outer(m[xs], n)
+    n_half = 6
+    plans = dense.dd_dense(C, m, n, eps, ca, cb, basic, pi0, n_half)
+    K = dense.kernel(C, m, n, eps)
+    prev_obj = np.inf
+    for ell in range(n_half):
+        st = o.half_iterate(ell % 2)
+        bm = o.basic_marginals()
+        assert np.abs(bm - _basic_marg_dense(plans[ell + 1], basic)).max() < 1e-11
+        # reported transport cost and objective against the dense plan
+        assert abs(st["cost"] - (C * plans[ell + 1]).sum()) < 1e-11
+        obj_dense = eps * dense.kl(plans[ell + 1], K) - eps * K.sum()
+        assert abs(st["obj"] - obj_dense) < 1e-10
+        # the entropic objective never increases (proof of Proposition "SimpleConvergence")
+        assert st["obj"] <= prev_obj + 1e-12
+        prev_obj = st["obj"]
+
+
+def test_converges_to_global_entropic_optimum():
+    # the DD fixed point is the full-grid entropic optimum (Thm. "Linear convergence")
+    N, s = 8, 2
+    mu, nu = datagen.small_pair(N, 2, seed=31)
+    eps = 32.0 / N ** 2
+    o = ddo.Oracle(mu, nu, s=s, n_levels=1, eps=eps, err_tol=1e-12, trunc=0.0, max_iter=100000)
+    C = dense.grid_cost(N, N, 1.0 / N)
+    P = dense.entropic_ot_newton(C, mu.ravel(), nu.ravel(), eps)[2]
+    basic, _, _ = dense.grid_partitions(N, N, s)
+    target = _basic_marg_dense(P, basic)
+    errs = []
+    for ell in range(100):
+        o.half_iterate(ell % 2)
+        errs.append(np.abs(o.basic_marginals() - target).max())
+    assert errs[-1] < 1e-9
+    assert errs[-1] < errs[10] < errs[0]
+
+
+def test_feasibility_invariants_with_truncation():
+    mu, nu, cfg = datagen.config1_pair()
+    o = ddo.Oracle(mu, nu, s=4, n_levels=1, eps=cfg["stages"][0][1], err_tol=1e-5, trunc=1e-15)
+    for ell in range(6):
+        st = o.half_iterate(ell % 2)
+        r = o.cost()
+        # |nu_i| = |mu_i| after BalanceMeasures, sum_i nu_i = nu (Algorithm 2 input
+        # conditions) up to the truncated mass, X-error bounded by Err
+        assert r["mass_drift"] <= 1e-13 + 1e-15 * r["nnz"]
+        assert r["err_y"] <= 1e-13 + 1e-15 * r["nnz"] * 4
+        assert st["err_x"] <= 1e-5 + 1e-15
+        e = o.export()
+        assert np.all(e["val"] >= 1e-15)
+        for b in range(len(e["row_ptr"]) - 1):
+            c = e["col"][e["row_ptr"][b]:e["row_ptr"][b + 1]]
+            assert np.all(np.diff(c) > 0)
+
+
+def test_balance_restores_masses_with_loose_tolerance():
+    # a loose Sinkhorn tolerance leaves |nu_i| != |mu_i| after the split; the
+    # balancing step must restore the masses without changing sum_i nu_i
+    mu, nu = datagen.small_pair(16, 3, seed=41)
+    o = ddo.Oracle(mu, nu, s=4, n_levels=1, eps=2.0 / 256, err_tol=1e-2, trunc=0.0)
+    for ell in range(4):
+        o.half_iterate(ell % 2)
+        r = o.cost()
+        assert r["mass_drift"] < 1e-15 * 64
+        assert r["err_y"] < 1e-15 * 256
+        assert np.all(o.export()["val"] > 0)
+
+
+def test_refinement_invariants():
+    # Proposition "FineBasicMarginals": sum_i nu_i^0 = nu and |nu_i^0| = mu(X_i)
+    mu, nu = datagen.small_pair(32, 4, seed=51)
+    o = ddo.Oracle(mu, nu, s=4, n_levels=2, eps=0.01, err_tol=1e-5, trunc=0.0)
+    for ell in range(4):
+        o.half_iterate(ell % 2)
+    rc = o.cost()
+    o.refine()
+    info = o.level_info()
+    assert (info["H"], info["level"]) == (32, 1)
+    r = o.cost()
+    # exact up to FP64 rounding (about 1e-16 per pixel) and what the coarse state carried
+    assert r["err_y"] < 2 * rc["err_y"] + 1e-15 * 32 * 32
+    assert r["mass_drift"] < 2 * rc["mass_drift"] + 1e-15 * 64
+    e = o.export()
+    assert e["val"].min() > 0
+
+
+def test_refinement_glues_and_interpolates_potentials():
+    # a globally consistent linear potential is reproduced exactly on the fine
+    # grid, and arbitrary per-A-cell constants are removed by the gluing
+    N, s = 32, 4
+    mu, nu = datagen.small_pair(N, 4, seed=61)
+    o = ddo.Oracle(mu, nu, s=s, n_levels=2, eps=0.01, err_tol=1e-5, trunc=1e-15)
+    e = o.export()
+    Hc = e["alpha_a"].shape[0]
+    h = 1.0 / Hc
+    rr, cc = np.meshgrid((np.arange(Hc) + 0.5) * h, (np.arange(Hc) + 0.5) * h, indexing="ij")
+    f = 0.3 * rr - 0.7 * cc
+    rng = np.random.default_rng(3)
+    offs = rng.normal(size=(Hc // (2 * s), Hc // (2 * s))) * 0.05
+    fa = f + np.kron(offs, np.ones((2 * s, 2 * s)))
+    o.import_state(0, 0.01, e["row_ptr"], e["col"], e["val"], fa, f)
+    o.refine()
+    e2 = o.export()
+    hf = 1.0 / (2 * Hc)
+    rf, cf = np.meshgrid((np.arange(2 * Hc) + 0.5) * hf, (np.arange(2 * Hc) + 0.5) * hf,
+                         indexing="ij")
+    ff = 0.3 * rf - 0.7 * cf
+    d = e2["alpha_a"] - ff
+    assert np.abs(d - d.mean()).max() < 1e-12
+    assert np.array_equal(e2["alpha_a"], e2["alpha_b"])
+
+
+def test_eps_change_keeps_potentials():
+    mu, nu, cfg = datagen.config1_pair()
+    o = ddo.Oracle(mu, nu, s=4, n_levels=1, eps=0.01)
+    o.half_iterate(0)
+    a = o.export()["alpha_a"].copy()
+    o.set_eps(0.005)
+    assert np.array_equal(o.export()["alpha_a"], a)
+
+
+def test_iteration_cap_is_reported():
+    mu, nu, cfg = datagen.config1_pair()
+    o = ddo.Oracle(mu, nu, s=4, n_levels=1, eps=cfg["stages"][0][1], max_iter=1, safeguard=1)
+    st = o.half_iterate(0)
+    assert st["n_failed"] > 0 and st["n_safeguard"] == st["n_failed"]
+    res = o.cell_results(0)
+    assert np.all(res["status"][res["status"] != 0] & 4)
+
+
+def test_deterministic():
+    mu, nu, cfg = datagen.config1_pair()
+    outs = []
+    for _ in range(2):
+        o = ddo.Oracle(mu, nu, s=4, n_levels=1, eps=cfg["stages"][0][1], n_threads=3)
+        for ell in range(4):
+            o.half_iterate(ell % 2)
+        outs.append(o.export())
+    for k in ("row_ptr", "col", "val", "alpha_a", "alpha_b"):
+        assert np.array_equal(outs[0][k], outs[1][k])
+
+
+def test_invalid_inputs_rejected():
+    mu, nu = datagen.small_pair(32, 3, seed=5)
+    with pytest.raises(ValueError):
+        ddo.Oracle(mu, nu * 2, s=4)
+    bad = mu.copy()
+    bad[0, 0] = -1e-3
+    with pytest.raises(ValueError):
+        ddo.Oracle(bad / bad.sum(), nu, s=4)
+    with pytest.raises(ValueError):
+        ddo.Oracle(mu[:, :30] / mu[:, :30].sum(), nu[:, :30] / nu[:, :30].sum(), s=4)
