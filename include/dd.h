@@ -1,0 +1,199 @@
+/*
+ * dd.h -- C-ABI of the MI355X (gfx950) library for entropic domain
+ * decomposition of W2 optimal transport between images, after Bonafini &
+ * Schmitzer, "Domain decomposition for entropy regularized optimal transport".
+ *
+ * The problem (eq. "Problem", Sec. 3): for probability images mu, nu on the
+ * same H x W pixel grid and c(x,y) = |x-y|^2 (Sec. 7.1), minimise
+ * eps*KL(pi | exp(-c/eps) mu (x) nu) over couplings pi of mu and nu.
+ *
+ * The state of a problem is the one of Algorithm 2: the Y-marginals nu_i of
+ * the plan on every basic cell X_i (s x s pixel blocks) and the X-potentials
+ * of the last solve on each composite partition, A (2x2 blocks of basic
+ * cells) and B (the same blocks shifted by one basic cell, Sec. 7.1).  One
+ * call of dd_half_iterate is one sweep of Algorithm 2 over all cells of one
+ * partition: for every composite cell J the cell Y-marginal is assembled from
+ * its basic cells, a stabilised Sinkhorn solve (Sec. 6.2) is run from the
+ * stored potential, the cell plan is split back into basic-cell marginals,
+ * BalanceMeasures and truncation are applied, and the potential is stored.
+ *
+ * Conventions shared by every call:
+ *  - arrays are row-major H x W; level 0 is the coarsest grid (H, W divided
+ *    by 2^(n_levels-1)), coarser levels are 2x2 block sums (Sec. 6.4);
+ *  - pixel (r,c) of a level with spacing h sits at ((c+1/2)h, (r+1/2)h) in the
+ *    unit square, h = 1/max(H,W) on the finest level; eps is in those units;
+ *  - potentials are exported as f = eps*log u (absolute units), which is what
+ *    an eps change keeps fixed (end of Sec. 6.4);
+ *  - basic cells are numbered row-major on the level's basic-cell grid; the
+ *    Y-marginal rows hold linear pixel indices r*W+c in increasing order.
+ *
+ * Ownership and streams: the library copies what it needs at dd_init and
+ * owns all device state of a context; export calls write only into buffers
+ * the caller provides.  All GPU work of a context is enqueued on
+ * dd_options.stream (a hipStream_t, NULL = default stream); calls that return
+ * host values synchronise that stream.  A context is not thread-safe.
+ *
+ * Errors: every call returns a dd_status; negative values are errors and
+ * leave a message readable with dd_last_error(ctx).  No exception crosses the
+ * ABI.  DD_ENOTCONV (positive) is a warning: some cell hit the Sinkhorn
+ * iteration cap even after the safeguard; the iteration still completed.
+ */
+#ifndef DD_H
+#define DD_H
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dd_ctx dd_ctx;
+
+typedef enum {
+  DD_OK = 0,
+  DD_ENOTCONV = 1,
+  DD_EINVAL = -1,
+  DD_ENOMEM = -2,
+  DD_EHIP = -3,
+  DD_ECAPACITY = -4,
+  DD_ESTATE = -5
+} dd_status;
+
+/* One row of the multi-scale eps schedule (Sec. 7.1 "Multi-scale and
+ * eps-scaling"): on `level`, set eps, then run n_half_iters half-iterations
+ * starting with partition A.  A stage on a finer level than the current one
+ * refines first (dd_refine). */
+typedef struct {
+  int level;
+  double eps;
+  int n_half_iters;
+} dd_stage;
+
+typedef struct {
+  double err_tol;          /* Sinkhorn stop: L1 X-marginal error <= err_tol*|mu_J| (Sec. 6.2); default 1e-5 */
+  double trunc_threshold;  /* truncation threshold of the basic marginals (Sec. 6.1 (ii)); default 1e-15 */
+  int max_sinkhorn_iter;   /* Sinkhorn loop cap per cell solve; default 10000 */
+  int safeguard;           /* 1: re-solve failed cells at 2*eps, then eps (Sec. 7.4); default 1 */
+  int inputs_on_device;    /* 1: mu, nu passed to dd_init are device pointers; default 0 */
+  void* stream;            /* hipStream_t for all work of the context; default NULL */
+} dd_options;
+
+typedef struct {
+  int n_cells;             /* composite cells solved */
+  int loops_max;           /* largest Sinkhorn loop count of a cell */
+  int64_t loops_total;     /* sum of Sinkhorn loop counts */
+  int n_failed;            /* cells still over the iteration cap after the safeguard */
+  int n_safeguard;         /* cells that needed the safeguard */
+  int64_t nnz;             /* entries of the basic Y-marginals after truncation */
+  int64_t entry_evals;     /* sum over cells of loops * |X_J| * |Y_J| (kernel entries touched per loop) */
+  double cost;             /* sum over cells of <c, pi_J> (plans before balancing) */
+  double obj;              /* sum over cells of eps*KL(pi_J|K_J) - eps*|K_J| */
+  double err_x;            /* sum over cells of the L1 X-marginal error */
+  double ms;               /* device time of the half-iteration (ms) */
+} dd_iter_stats;
+
+typedef struct {
+  int n_half_iters;
+  int n_cell_solves;
+  int64_t loops_total;
+  int64_t entry_evals;
+  int n_failed;
+  int n_safeguard;
+  int64_t nnz_max;
+  double ms_total;         /* wall time of the whole schedule (ms) */
+} dd_run_stats;
+
+typedef struct {
+  double cost;             /* <c, pi> of the last half-iteration's cell plans (W2^2 estimate) */
+  double obj;              /* eps*KL(pi|K) - eps*|K| of those plans */
+  double err_x;            /* L1 error of the X-marginal of those plans */
+  double err_y;            /* L1 error of sum_i nu_i against nu (current state) */
+  double mass_drift;       /* sum_i | |nu_i| - |mu_i| | (current state) */
+  int64_t nnz;
+  int level;
+  int last_partition;      /* -1 if no half-iteration ran on this level yet */
+  double eps;
+} dd_cost_report;
+
+/* Export view (two-call protocol): the caller sets the pointers; NULL
+ * pointers are skipped.  row_ptr has n_basic+1 entries, col/val nnz,
+ * alpha_a/alpha_b H*W of the current level.  Scalar fields are filled by
+ * dd_export_plan and read by dd_import_state. */
+typedef struct {
+  int level;
+  int H, W;
+  double eps;
+  int64_t n_basic;
+  int64_t nnz;
+  int64_t* row_ptr;
+  int32_t* col;
+  double* val;
+  double* alpha_a;
+  double* alpha_b;
+} dd_plan_view;
+
+/* Fill *opt with the defaults listed above. */
+void dd_options_default(dd_options* opt);
+
+/* Create a problem (eq. "Problem", Algorithm 2 inputs).
+ * mu, nu: H x W row-major FP64 probability images (host pointers unless
+ *   opt->inputs_on_device); copied, the caller keeps ownership.
+ * basic_cell: s (only 4 is supported by the GPU kernels); H and W must be
+ *   divisible by 2*s*2^(n_levels-1).
+ * schedule: n_stages >= 1 rows, copied; schedule[0].eps is the initial eps.
+ * The state starts on level 0 with the product coupling nu_i = |mu_i| nu and
+ * zero potentials (Sec. 6.4).  Rejects with DD_EINVAL: non-finite or
+ * negative masses, total masses off 1 by more than 1e-9, a basic cell of zero
+ * mass, indivisible sizes, eps <= 0, a schedule whose levels decrease.  On
+ * success *out owns the context (release with dd_free). */
+dd_status dd_init(const double* mu, const double* nu, int height, int width, int basic_cell,
+                  int n_levels, const dd_stage* schedule, int n_stages, const dd_options* opt,
+                  dd_ctx** out);
+
+/* One sweep of Algorithm 2 over all composite cells of partition 0 (A) or
+ * 1 (B) on the current level.  stats (nullable) receives the per-sweep
+ * counters; the call synchronises the context stream. */
+dd_status dd_half_iterate(dd_ctx* ctx, int partition, dd_iter_stats* stats);
+
+/* Change eps; the potentials f = eps*log u stay as they are (end of Sec. 6.4). */
+dd_status dd_set_eps(dd_ctx* ctx, double eps);
+
+/* Coarse-to-fine step (Sec. 6.4): the basic marginals of the next level by
+ * eq. (FineBasicMarginals); the potentials of partition A are glued with the
+ * help of those of B (least squares of Sec. 6.3), bilinearly interpolated to
+ * the fine pixels and used for both partitions.  DD_ESTATE on the finest level. */
+dd_status dd_refine(dd_ctx* ctx);
+
+/* Run the whole schedule given at dd_init from the current state. */
+dd_status dd_run_schedule(dd_ctx* ctx, dd_run_stats* stats);
+
+/* FP64 diagnostics of the current state and of the last half-iteration. */
+dd_status dd_cost(dd_ctx* ctx, dd_cost_report* report);
+
+/* Export the state (Algorithm 2 outputs) into caller buffers; fills the
+ * scalar fields of *view first, so a call with NULL pointers returns sizes. */
+dd_status dd_export_plan(dd_ctx* ctx, dd_plan_view* view);
+
+/* Replace the state by view (same level geometry as the context's level
+ * view->level; rows sorted, no duplicates); for resume and tests. */
+dd_status dd_import_state(dd_ctx* ctx, const dd_plan_view* view);
+
+/* Per-cell results of the last half-iteration (arrays of that partition's
+ * cell count, cells numbered row-major; nullable): transport cost, objective,
+ * X-marginal error, Sinkhorn loops, status (1 cap, 2 non-finite, 4 safeguard). */
+dd_status dd_cell_results(dd_ctx* ctx, double* cost, double* obj, double* err_x, int* loops,
+                          int* status);
+
+/* Geometry of the current level (all outputs nullable). */
+dd_status dd_level_info(const dd_ctx* ctx, int* level, int* height, int* width, int* n_basic,
+                        int* n_cells_a, int* n_cells_b, double* eps);
+
+void dd_free(dd_ctx* ctx);
+
+/* Message of the last error on ctx (or of the last failed dd_init when ctx is NULL). */
+const char* dd_last_error(const dd_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

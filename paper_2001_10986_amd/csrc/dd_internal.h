@@ -1,0 +1,95 @@
+// Internal interface between the host runtime (dd_runtime.hip) and the
+// gfx950 kernels (dd_kernels.hip).  Not part of the public C-ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ddk {
+
+constexpr int kS = 4;          // basic cell edge in pixels (the only supported value)
+constexpr int kCellPx = 64;    // a composite cell is a virtual 8x8 pixel block
+constexpr int kNRegBins = 5;   // register-resident solver bins: 1,2,4,8,16 waves
+constexpr int kRegMaxU = 1024; // largest Y-support kept in registers (16 waves x 64)
+constexpr int kNBins = kNRegBins + 1;
+
+// Everything one sweep over one partition needs.  Device pointers.
+struct HalfParams {
+  int H, W, bh, bw;
+  int n_cells, n_basic;
+  int part;
+  double h, eps, lam;          // lam = h^2 / eps (cost in units of eps per pixel^2)
+  double err_tol, trunc;
+  int max_iter, safeguard;
+  const double* mu;            // level mu, H*W
+  const double* nu;            // level nu, H*W
+  double* alpha;               // potentials f of partition `part`, H*W (in/out)
+  const int4* cell_q;          // basic-cell id per virtual quadrant (row-major), -1 if absent
+  const int2* cell_org;        // virtual pixel origin (row, col) of the 8x8 block
+  int64_t* row_off;            // per basic cell: first entry (in/out)
+  int* row_len;                // per basic cell: entry count (in/out)
+  int* ent_col;                // entries: linear Y pixel index
+  double* ent_val;             // entries: mass
+  int64_t* cell_toff;          // per cell: offset of its union in the union buffer
+  int* cell_U;                 // per cell: union size
+  int64_t* cell_ooff;          // per cell: offset of its output region in the entry buffer
+  int* bin_count;              // kNBins counters
+  int* bin_list;               // kNBins * n_cells cell ids
+  int* uni_key;                // union: keys
+  double* uni_nu;              // union: nu_J
+  double* uni_G;               // union: scratch Y potential (big-cell solver)
+  double* r_cost;
+  double* r_obj;
+  double* r_err;
+  int* r_loops;
+  int* r_status;
+  long long* r_evals;
+  long long* misc;             // [0] nnz_in, [1] out entries, [2] bad-row flag
+  long long capE;              // entry buffer capacity (rows are checked against it)
+};
+
+struct IterStatsDev {
+  double cost, obj, err;
+  long long loops_total, evals, nnz;
+  int loops_max, n_failed, n_safeguard, n_cells;
+};
+
+// Kernel launchers (all asynchronous on `st`).
+void launch_sweep(const HalfParams& p, hipStream_t st, int grid_cap);
+void launch_stats(const HalfParams& p, IterStatsDev* out, hipStream_t st);
+size_t sweep_max_static_lds();
+
+void launch_validate(const double* mu, const double* nu, int H, int W, double* out4,
+                     hipStream_t st);
+void launch_pyramid(const double* fine, double* coarse, int Hc, int Wc, hipStream_t st);
+void launch_product_init(const int* ypos, int nzy, const double* nu, const double* bmass,
+                         int n_basic, int* col, double* val, int64_t* row_off, int* row_len,
+                         hipStream_t st);
+
+// Diagnostics: out[0] = sum |sum_i nu_i - nu|, out[1] = sum_i | |nu_i| - |mu_i| |, out[2] = nnz
+void launch_diag(const int64_t* row_off, const int* row_len, const int* col, const double* val,
+                 const double* mu, const double* nu, int H, int W, int bw, int n_basic,
+                 double* scratch_px, double* out3, hipStream_t st);
+
+// Export: dense CSR from the gapped rows.
+void launch_export(const int64_t* row_off, const int* row_len, const int* col, const double* val,
+                   int n_basic, int64_t* row_ptr_dev, int* col_out, double* val_out,
+                   hipStream_t st);
+void launch_scan_rows(const int* row_len, int n, int64_t* row_ptr, hipStream_t st);
+
+// Refinement.
+struct RefineParams {
+  int Hc, Wc, bwc, Hf, Wf, bwf, n_basic_f;
+  double eps;
+  const double* mu_c; const double* nu_c; const double* mu_f; const double* nu_f;
+  const double* alpha_a_c; const double* alpha_b_c;
+  const int64_t* row_off_c; const int* row_len_c; const int* col_c; const double* val_c;
+  int64_t* row_off_f; int* row_len_f; int* col_f; double* val_f;
+};
+void launch_refine_rows(const RefineParams& r, hipStream_t st);
+// log q for every (A,B) overlap: per basic cell b: out[2b] = log mean_b exp((fA-fB)/eps),
+// out[2b+1] = log mean_b exp((fB-fA)/eps) (mu-weighted)
+void launch_glue_ratios(const RefineParams& r, double* out, hipStream_t st);
+void launch_interp(const double* fglued_c, int Hc, int Wc, double* fa, double* fb, int Hf,
+                   int Wf, hipStream_t st);
+
+}  // namespace ddk

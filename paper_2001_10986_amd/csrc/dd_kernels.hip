@@ -1,0 +1,1494 @@
+// gfx950 kernels of one domain-decomposition sweep (Algorithm 2 of Bonafini &
+// Schmitzer) and of the coarse-to-fine refinement (Sec. 6.4).
+//
+// One sweep over a partition is, per composite cell J:
+//   union    : Y_J = union of the supports of nu_i (i in J), nu_J = sum nu_i
+//              (Algorithm 2, "compute Y-marginal on cell");
+//   solve    : stabilised Sinkhorn between mu_J and nu_J from the stored
+//              potential, stopped on the L1 X-marginal error after a
+//              Y-iteration (Sec. 6.2);
+//   split    : nu_i(y) = plan restricted to X_i x {y} (Algorithm 2, "extract
+//              new basic partial marginals");
+//   balance  : BalanceMeasures (Sec. 6.2), truncation (Sec. 6.1 (ii)) and
+//              compaction into the basic-cell rows.
+#include "dd_internal.h"
+
+#include <float.h>
+#include <math.h>
+
+namespace ddk {
+
+#define DEVI __device__ __forceinline__
+
+static constexpr double kLog2e = 1.4426950408889634;
+static constexpr double kLn2 = 0.6931471805599453;
+
+// ------------------------------------------------------------ primitives
+
+DEVI void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+DEVI float fast_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+DEVI float fast_log2(float x) { return __builtin_amdgcn_logf(x); }
+
+template <typename T>
+DEVI T wave_sum(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+template <typename T>
+DEVI T wave_max(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    T u = __shfl_xor(v, o, 64);
+    v = u > v ? u : v;
+  }
+  return v;
+}
+template <typename T>
+DEVI T wave_min(T v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    T u = __shfl_xor(v, o, 64);
+    v = u < v ? u : v;
+  }
+  return v;
+}
+template <typename T>
+DEVI T wave_incl_scan(T v, int lane) {
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    T u = __shfl_up(v, o, 64);
+    if (lane >= o) v += u;
+  }
+  return v;
+}
+
+// Block exclusive scan of one value per thread; returns the prefix and the
+// block total.  `sh` needs nwaves entries.  Contains barriers.
+template <typename T>
+DEVI T block_excl_scan(T v, T* sh, T* total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  T inc = wave_incl_scan(v, lane);
+  __syncthreads();
+  if (lane == 63) sh[wave] = inc;
+  __syncthreads();
+  T off = 0, tot = 0;
+  for (int w = 0; w < nw; w++) {
+    T s = sh[w];
+    if (w < wave) off += s;
+    tot += s;
+  }
+  *total = tot;
+  return off + inc - v;
+}
+
+// Deterministic block sum (fixed tree) of a double; result valid in all threads.
+DEVI double block_sum_d(double v, double* sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) sh[wave] = v;
+  __syncthreads();
+  double t = 0;
+  for (int w = 0; w < nw; w++) t += sh[w];
+  return t;
+}
+
+DEVI void split_key(int key, int W, double invW, int* r, int* c) {
+  int rr = (int)(((double)key + 0.5) * invW);
+  *r = rr;
+  *c = key - rr * W;
+}
+
+// ------------------------------------------------------------ scans over cells
+
+// cell_toff = exclusive scan of T_J = sum of the row lengths of J's basic cells
+__global__ __launch_bounds__(1024) void k_scan_T(HalfParams p) {
+  __shared__ long long sh[16];
+  long long carry = 0;
+  for (int base = 0; base < p.n_cells; base += 1024) {
+    int i = base + threadIdx.x;
+    long long t = 0;
+    if (i < p.n_cells) {
+      int4 q = p.cell_q[i];
+      if (q.x >= 0) t += p.row_len[q.x];
+      if (q.y >= 0) t += p.row_len[q.y];
+      if (q.z >= 0) t += p.row_len[q.z];
+      if (q.w >= 0) t += p.row_len[q.w];
+    }
+    long long tot;
+    long long ex = block_excl_scan(t, sh, &tot);
+    if (i < p.n_cells) p.cell_toff[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) p.misc[0] = carry;
+}
+
+DEVI int bin_of(int U) {
+  if (U <= 64) return 0;
+  if (U <= 128) return 1;
+  if (U <= 256) return 2;
+  if (U <= 512) return 3;
+  if (U <= kRegMaxU) return 4;
+  return 5;
+}
+
+// cell_ooff = exclusive scan of |J| * U_J; stable lists of cells per size bin
+__global__ __launch_bounds__(1024) void k_scan_out(HalfParams p) {
+  __shared__ long long sh[16];
+  __shared__ int swc[16][kNBins];
+  __shared__ int srun[kNBins];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x < kNBins) srun[threadIdx.x] = 0;
+  long long carry = 0;
+  for (int base = 0; base < p.n_cells; base += 1024) {
+    int i = base + threadIdx.x;
+    long long t = 0;
+    int b = -1;
+    if (i < p.n_cells) {
+      int4 q = p.cell_q[i];
+      int nq = (q.x >= 0) + (q.y >= 0) + (q.z >= 0) + (q.w >= 0);
+      int U = p.cell_U[i];
+      t = (long long)nq * U;
+      b = bin_of(U);
+    }
+    long long tot;
+    long long ex = block_excl_scan(t, sh, &tot);
+    if (i < p.n_cells) p.cell_ooff[i] = carry + ex;
+    carry += tot;
+    unsigned long long lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    unsigned long long mine = 0;
+    for (int bb = 0; bb < kNBins; bb++) {
+      unsigned long long m = __ballot(b == bb);
+      if (lane == 0) swc[wave][bb] = __popcll(m);
+      if (b == bb) mine = m;
+    }
+    __syncthreads();
+    if (b >= 0) {
+      int off = srun[b];
+      for (int w = 0; w < wave; w++) off += swc[w][b];
+      off += __popcll(mine & lt);
+      p.bin_list[b * p.n_cells + off] = i;
+    }
+    __syncthreads();
+    if (threadIdx.x < kNBins) {
+      int s = 0;
+      for (int w = 0; w < 16; w++) s += swc[w][threadIdx.x];
+      srun[threadIdx.x] += s;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < kNBins) p.bin_count[threadIdx.x] = srun[threadIdx.x];
+  if (threadIdx.x == 0) p.misc[1] = carry;
+}
+
+// ------------------------------------------------------------ union (gather)
+
+// Sorted union of up to four sorted rows and the summed masses.  The keys are
+// marked in a bitmap over the 2D bounding box of the support (row-major, so
+// bit order is key order), processed in bands of rows when the box is large;
+// a popcount prefix gives every key its rank.  Masses of equal keys are summed
+// in basic-cell order, so the result is deterministic.
+constexpr int kUnionThreads = 256;
+constexpr int kBitWords = 2048;  // 65536 bits per band
+
+__global__ __launch_bounds__(kUnionThreads) void k_union(HalfParams p) {
+  __shared__ uint32_t bits[kBitWords];
+  __shared__ int wpre[kBitWords];
+  __shared__ int shi[8];
+  __shared__ long long shl[8];
+  const int tid = threadIdx.x;
+  const double invW = 1.0 / p.W;
+  for (int cell = blockIdx.x; cell < p.n_cells; cell += gridDim.x) {
+    int4 q4 = p.cell_q[cell];
+    int bq[4] = {q4.x, q4.y, q4.z, q4.w};
+    int64_t off[4];
+    int len[4], pre[5];
+    int nr = 0;
+    pre[0] = 0;
+    for (int a = 0; a < 4; a++)
+      if (bq[a] >= 0) {
+        off[nr] = p.row_off[bq[a]];
+        len[nr] = p.row_len[bq[a]];
+        if (off[nr] < 0 || len[nr] < 0 || off[nr] + len[nr] > p.capE) {
+          if (tid == 0) atomicOr((unsigned long long*)&p.misc[2], 1ull);
+          len[nr] = 0;
+          off[nr] = 0;
+        }
+        pre[nr + 1] = pre[nr] + len[nr];
+        nr++;
+      }
+    const int T = pre[nr];
+    const int64_t base = p.cell_toff[cell];
+    if (T == 0) {
+      if (tid == 0) p.cell_U[cell] = 0;
+      continue;
+    }
+    int rmin = INT_MAX, rmax = -1;
+    for (int a = 0; a < nr; a++)
+      if (len[a] > 0) {
+        int r0, c0, r1, c1;
+        split_key(min(max(p.ent_col[off[a]], 0), p.H * p.W - 1), p.W, invW, &r0, &c0);
+        split_key(min(max(p.ent_col[off[a] + len[a] - 1], 0), p.H * p.W - 1), p.W, invW, &r1, &c1);
+        rmin = min(rmin, r0);
+        rmax = max(rmax, r1);
+      }
+    int cmn = INT_MAX, cmx = -1;
+    for (int e = tid; e < T; e += kUnionThreads) {
+      int a = 0;
+      while (e >= pre[a + 1]) a++;
+      int r, c;
+      split_key(p.ent_col[off[a] + (e - pre[a])], p.W, invW, &r, &c);
+      cmn = min(cmn, c);
+      cmx = max(cmx, c);
+    }
+    cmn = wave_min(cmn);
+    cmx = wave_max(cmx);
+    __syncthreads();
+    if ((tid & 63) == 0) {
+      shi[tid >> 6] = cmn;
+      shi[4 + (tid >> 6)] = cmx;
+    }
+    __syncthreads();
+    const int cmin = min(min(shi[0], shi[1]), min(shi[2], shi[3]));
+    const int cmax = max(max(shi[4], shi[5]), max(shi[6], shi[7]));
+    const int bwid = cmax - cmin + 1;
+    const int rows_per_band = max(1, (kBitWords * 32) / bwid);
+    int U = 0;
+    for (int r0 = rmin; r0 <= rmax; r0 += rows_per_band) {
+      const int r1 = min(rmax, r0 + rows_per_band - 1);
+      const int nw = ((r1 - r0 + 1) * bwid + 31) >> 5;
+      __syncthreads();
+      for (int w = tid; w < nw; w += kUnionThreads) bits[w] = 0u;
+      __syncthreads();
+      for (int e = tid; e < T; e += kUnionThreads) {
+        int a = 0;
+        while (e >= pre[a + 1]) a++;
+        int r, c;
+        split_key(p.ent_col[off[a] + (e - pre[a])], p.W, invW, &r, &c);
+        if (r >= r0 && r <= r1) {
+          int b = (r - r0) * bwid + (c - cmin);
+          atomicOr(&bits[b >> 5], 1u << (b & 31));
+        }
+      }
+      __syncthreads();
+      // exclusive popcount prefix over the band's words (8 words per thread)
+      int loc = 0;
+      const int w0 = tid * 8;
+      for (int k = 0; k < 8; k++)
+        if (w0 + k < nw) loc += __popc(bits[w0 + k]);
+      long long tot;
+      long long ex = block_excl_scan((long long)loc, shl, &tot);
+      int run = (int)ex;
+      for (int k = 0; k < 8; k++)
+        if (w0 + k < nw) {
+          wpre[w0 + k] = run;
+          run += __popc(bits[w0 + k]);
+        }
+      const int cnt = (int)tot;
+      for (int i = tid; i < cnt; i += kUnionThreads) p.uni_nu[base + U + i] = 0.0;
+      __syncthreads();
+      for (int a = 0; a < nr; a++) {
+        for (int e = tid; e < len[a]; e += kUnionThreads) {
+          int key = p.ent_col[off[a] + e];
+          int r, c;
+          split_key(key, p.W, invW, &r, &c);
+          if (r >= r0 && r <= r1) {
+            int b = (r - r0) * bwid + (c - cmin);
+            uint32_t wd = bits[b >> 5];
+            int pos = U + wpre[b >> 5] + __popc(wd & ((1u << (b & 31)) - 1u));
+            p.uni_key[base + pos] = key;
+            p.uni_nu[base + pos] += p.ent_val[off[a] + e];
+          }
+        }
+        __syncthreads();
+      }
+      U += cnt;
+    }
+    if (tid == 0) p.cell_U[cell] = U;
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ cell geometry
+
+struct CellGeo {
+  int R0, C0;      // virtual origin of the 8x8 block
+  int bq[4];       // basic id per virtual quadrant or -1
+  int nq;          // valid quadrants
+  int qidx[4];     // index of the quadrant among the valid ones (segment number)
+};
+
+DEVI CellGeo load_geo(const HalfParams& p, int cell) {
+  CellGeo g;
+  int4 q = p.cell_q[cell];
+  int2 o = p.cell_org[cell];
+  g.R0 = o.x;
+  g.C0 = o.y;
+  g.bq[0] = q.x;
+  g.bq[1] = q.y;
+  g.bq[2] = q.z;
+  g.bq[3] = q.w;
+  g.nq = 0;
+  for (int a = 0; a < 4; a++) {
+    g.qidx[a] = g.bq[a] >= 0 ? g.nq : -1;
+    if (g.bq[a] >= 0) g.nq++;
+  }
+  return g;
+}
+
+// Balancing, truncation and compaction of the basic marginals of one cell
+// (BalanceMeasures of Sec. 6.2; truncation of Sec. 6.1 (ii)).  Each thread
+// owns at most one support point y (index yi < U) and holds the four
+// basic-cell values nq[0..3] for it.  READING (balance rule): with
+// d_i = |mu_i| - |nu_i|, E = sum of -d_i over d_i < 0, D = sum of d_i over
+// d_i > 0, T = min(E, D), every excess cell a loses the fraction
+// T(-d_a)/(E |nu_a|) of its mass at every y and the freed mass R(y) goes to
+// the deficit cells b in the proportions d_b/D.
+struct CellOutSh {
+  double red[16];
+  long long scan[16];
+  double dq[4], tq[4], E, D;
+  long long cnt[4];
+};
+
+DEVI void balance_truncate_write(const HalfParams& p, const CellGeo& g, int64_t obase, int U,
+                                 bool own, int yi, int key, double v[4], const double massmu[4],
+                                 CellOutSh& sh) {
+  // norms of the basic marginals
+  double nrm[4];
+#pragma unroll
+  for (int a = 0; a < 4; a++) nrm[a] = block_sum_d(own ? v[a] : 0.0, sh.red);
+  if (threadIdx.x == 0) {
+    double E = 0, D = 0;
+    for (int a = 0; a < 4; a++) {
+      double d = g.bq[a] >= 0 ? massmu[a] - nrm[a] : 0.0;
+      sh.dq[a] = d;
+      if (d < 0) E += -d;
+      if (d > 0) D += d;
+    }
+    double T = E < D ? E : D;
+    for (int a = 0; a < 4; a++) sh.tq[a] = (T > 0 && sh.dq[a] < 0) ? T * (-sh.dq[a]) / (E * nrm[a]) : 0.0;
+    sh.E = T > 0 ? E : 0.0;
+    sh.D = T > 0 ? D : 0.0;
+  }
+  __syncthreads();
+  if (own && sh.D > 0) {
+    double R = 0;
+    for (int a = 0; a < 4; a++)
+      if (sh.dq[a] < 0 && g.bq[a] >= 0) {
+        double r = v[a] * sh.tq[a];
+        v[a] -= r;
+        R += r;
+      }
+    for (int a = 0; a < 4; a++)
+      if (sh.dq[a] > 0 && g.bq[a] >= 0) v[a] += R * sh.dq[a] / sh.D;
+  }
+  // truncation flags, packed 16 bits per quadrant
+  unsigned long long flags = 0;
+  if (own)
+    for (int a = 0; a < 4; a++)
+      if (g.bq[a] >= 0 && v[a] >= p.trunc && v[a] > 0.0) flags |= 1ull << (16 * a);
+  // block scan (U may exceed the block size only in the big-cell solver,
+  // which calls this once per chunk with a running carry in sh.cnt)
+  long long tot;
+  long long ex = block_excl_scan((long long)flags, sh.scan, &tot);
+  if (own) {
+    for (int a = 0; a < 4; a++)
+      if ((flags >> (16 * a)) & 1ull) {
+        long long pos = sh.cnt[a] + ((ex >> (16 * a)) & 0xffffll);
+        if (pos < U) {
+          int64_t at = obase + (int64_t)g.qidx[a] * U + pos;
+          p.ent_col[at] = key;
+          p.ent_val[at] = v[a];
+        }
+      }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int a = 0; a < 4; a++) sh.cnt[a] += (tot >> (16 * a)) & 0xffffll;
+  __syncthreads();
+}
+
+// ------------------------------------------------------------ register solver
+
+// Stabilised Sinkhorn for cells whose union fits NW*64 support points.
+// Layout: a composite cell is a virtual 8x8 block of pixels x (absent pixels
+// carry mu = 0).  Lane (wave w, xg = lane&7, yg = lane>>3) owns the 8 pixels
+// of block row xg and the 8 support points y = w*64 + yg*8 + t, and keeps the
+// 8x8 tile of the absorbed kernel
+//     P(x,y) = exp(F0(x) + log mu(x) - C(x,y) - m(y)),  C = lam*|x-y|^2,
+// in registers (m(y) = max_x of the exponent, so every column peaks at 1).
+// The exponent is formed in FP64, the tile and the scaling iterations run in
+// FP32, sums that decide stopping, masses and costs run in FP64.
+//   Y-iteration:  S(y) = sum_x P(x,y) u(x),   w(y) = nu_J(y) / S(y)
+//   X-marginal :  r(x) = sum_y P(x,y) w(y),   P_X pi(x) = u(x) r(x)
+//   X-iteration:  u(x) = mu(x) / r(x)
+// which is the Sinkhorn iteration of Remark "Sinkhorn algorithm" written in
+// scalings relative to the absorbed potential F0 (plan pi = P u w).  When u
+// leaves [e^-30, e^30] (or underflows) the X-iteration is done exactly in
+// the log domain instead and F0 absorbs it (P is rebuilt).
+template <int NW>
+struct RegShared {
+  double F0[64], Fmu[64], mu[64], F0orig[64], mx[64];
+  float u[64], r[64];
+  float red[NW][512];         // per-wave transposition scratch (also FP64 scratch)
+  float wred[NW][64];         // per-wave X partials
+  float w[NW * 64];
+  float S[NW * 64];
+  float nuf[NW * 64];
+  int yrc[NW * 64];           // support point (row << 16 | col)
+  double err;
+  int flag;
+  CellOutSh out;
+};
+
+// Transposition through the per-wave scratch: lane (yg, xg) provides v[t]
+// for its 8 support points; returns, in lane (yg, xg), the sum over the 8
+// lanes of its support group of v[t = xg], split into the block rows xg' < 4
+// and xg' >= 4.  Element (yg, xg', t) lives at yg*64 + ((xg'^yg)&7)*8 + t:
+// the xor swizzle spreads the 8 support groups over the LDS banks.
+DEVI int tsw(int yg, int x, int t) { return yg * 64 + (((x ^ yg) & 7) << 3) + t; }
+
+DEVI void transpose_y(float* rd, int xg, int yg, const float v[8], float* top, float* bot) {
+  wave_sync();
+#pragma unroll
+  for (int t = 0; t < 8; t++) rd[tsw(yg, xg, t)] = v[t];
+  wave_sync();
+  float a = 0.f, b = 0.f;
+#pragma unroll
+  for (int k = 0; k < 8; k++) {
+    const float x = rd[tsw(yg, k, xg)];
+    if (k < 4) a += x; else b += x;
+  }
+  *top = a;
+  *bot = b;
+}
+
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
+  __shared__ RegShared<NW> sh;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int xg = lane & 7, yg = lane >> 3;
+  const int ybase = wave * 64 + yg * 8;  // first of the lane's 8 support points
+  const int count = p.bin_count[bin];
+  const double invW = 1.0 / p.W;
+  float* rd = sh.red[wave];
+  for (int ci = blockIdx.x; ci < count; ci += gridDim.x) {
+    const int cell = p.bin_list[bin * p.n_cells + ci];
+    const CellGeo g = load_geo(p, cell);
+    const int U = p.cell_U[cell];
+    const int64_t ub = p.cell_toff[cell];
+    const int64_t obase = p.cell_ooff[cell];
+    double* mbuf = p.uni_G + ub;  // m(y) of the absorbed tile, one per support point
+    // ---- pixel data (pixel k = 8i + j of the block)
+    if (tid < 64) {
+      const int i = tid >> 3, j = tid & 7;
+      const int qa = (i >> 2) * 2 + (j >> 2);
+      const int bq = qa == 0 ? g.bq[0] : qa == 1 ? g.bq[1] : qa == 2 ? g.bq[2] : g.bq[3];
+      const int r = g.R0 + i, c = g.C0 + j;
+      double mu = 0, F0 = 0;
+      if (bq >= 0) {
+        mu = p.mu[(int64_t)r * p.W + c];
+        F0 = p.alpha[(int64_t)r * p.W + c] / p.eps;
+      }
+      sh.mu[tid] = mu;
+      sh.F0orig[tid] = F0;
+      sh.F0[tid] = F0;
+    }
+    // ---- support data, one point per thread
+    for (int yi = tid; yi < NW * 64; yi += NW * 64) {
+      int r = 0, c = 0;
+      double nu = 0;
+      if (yi < U) {
+        split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
+        nu = p.uni_nu[ub + yi];
+      }
+      sh.yrc[yi] = (r << 16) | c;
+      sh.nuf[yi] = (float)nu;
+    }
+    __syncthreads();
+    double massmu[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 64; k++) massmu[((k >> 3) >> 2) * 2 + ((k & 7) >> 2)] += sh.mu[k];
+    const double muJ = (massmu[0] + massmu[1]) + (massmu[2] + massmu[3]);
+    const double tol = p.err_tol * muJ;
+
+    float P[8][8];
+    int status = 0, loops_all = 0;
+    double lam = p.lam;
+    const int phases = p.safeguard ? 3 : 1;
+    bool converged = false;
+    const int xr = g.R0 + xg;  // pixel row of the lane's 8 pixels
+
+    for (int phase = 0; phase < phases; phase++) {
+      if (phase == 1) {  // safeguard: 2*eps from the stored potential
+        lam = p.lam * 0.5;
+        if (tid < 64) sh.F0[tid] = sh.F0orig[tid] * 0.5;
+      } else if (phase == 2) {  // back to eps from the 2*eps solution
+        lam = p.lam;
+        if (tid < 64 && sh.mu[tid] > 0) sh.F0[tid] = (sh.F0[tid] + log((double)sh.u[tid])) * 2.0;
+      }
+      __syncthreads();
+      bool rebuild = true;
+      int it = 0;
+      converged = false;
+      for (;;) {
+        if (rebuild) {
+          // ---- absorb: P = exp(Fmu - lam d2 - m(y)) with Fmu = F0 + log mu
+          if (tid < 64) {
+            sh.Fmu[tid] = sh.mu[tid] > 0 ? sh.F0[tid] + log(sh.mu[tid]) : -INFINITY;
+            sh.u[tid] = sh.mu[tid] > 0 ? 1.0f : 0.0f;
+          }
+          __syncthreads();
+#pragma unroll
+          for (int t = 0; t < 8; t++) {
+            const int yi = ybase + t;
+            const int rc = sh.yrc[yi];
+            const int dr = (rc >> 16) - xr;
+            const int dc0 = (rc & 0xffff) - g.C0;
+            const double ldr = lam * (double)(dr * dr);
+            double mloc = -INFINITY;
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+              const int dc = dc0 - j;
+              const double e = sh.Fmu[xg * 8 + j] - (ldr + lam * (double)(dc * dc));
+              mloc = e > mloc ? e : mloc;
+            }
+#pragma unroll
+            for (int o = 1; o < 8; o <<= 1) {
+              const double v = __shfl_xor(mloc, o, 64);
+              mloc = v > mloc ? v : mloc;
+            }
+            const bool valid = yi < U;
+            if (!valid) mloc = 0.0;
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+              const int dc = dc0 - j;
+              const double e = sh.Fmu[xg * 8 + j] - (ldr + lam * (double)(dc * dc)) - mloc;
+              P[j][t] = valid ? fast_exp2((float)(e * kLog2e)) : 0.0f;
+            }
+            if (xg == 0 && valid) mbuf[yi] = mloc;
+          }
+          rebuild = false;
+          __syncthreads();
+        }
+        it++;
+        // ---- Y-iteration: S(y) = sum_x P u, w = nu_J / S
+        {
+          float uu[8], Sp[8];
+#pragma unroll
+          for (int j = 0; j < 8; j++) uu[j] = sh.u[xg * 8 + j];
+#pragma unroll
+          for (int t = 0; t < 8; t++) {
+            float s = 0.f;
+#pragma unroll
+            for (int j = 0; j < 8; j++) s = fmaf(P[j][t], uu[j], s);
+            Sp[t] = s;
+          }
+          float a, b;
+          transpose_y(rd, xg, yg, Sp, &a, &b);
+          const float s = a + b;
+          const int yi = ybase + xg;
+          sh.S[yi] = s;
+          sh.w[yi] = s > 0.f ? sh.nuf[yi] / s : 0.f;
+        }
+        wave_sync();
+        // ---- X-marginal: r(x) = sum_y P w
+        {
+          float wv[8], rx[8];
+#pragma unroll
+          for (int t = 0; t < 8; t++) wv[t] = sh.w[ybase + t];
+#pragma unroll
+          for (int j = 0; j < 8; j++) {
+            float s = 0.f;
+#pragma unroll
+            for (int t = 0; t < 8; t++) s = fmaf(P[j][t], wv[t], s);
+            rx[j] = s;
+          }
+          wave_sync();
+#pragma unroll
+          for (int j = 0; j < 8; j++) rd[tsw(xg, yg, j)] = rx[j];
+          wave_sync();
+          float s = 0.f;
+#pragma unroll
+          for (int k = 0; k < 8; k++) s += rd[tsw(xg, k, yg)];
+          sh.wred[wave][xg * 8 + yg] = s;
+        }
+        __syncthreads();
+        if (wave == 0) {
+          float r = 0.f;
+#pragma unroll
+          for (int w = 0; w < NW; w++) r += sh.wred[w][lane];
+          const double mu = sh.mu[lane];
+          const float u = sh.u[lane];
+          double e = mu > 0 ? fabs((double)u * (double)r - mu) : 0.0;
+          e = wave_sum(e);
+          sh.r[lane] = r;
+          const float un = mu > 0 ? (float)(mu / (double)r) : 0.f;
+          const bool bad = mu > 0 && !(un > 9.357623e-14f && un < 1.0686475e13f);
+          const unsigned long long anyb = __ballot(bad);
+          const bool go_on = !(e <= tol) && it < p.max_iter && (e == e);
+          if (go_on && anyb == 0ull) sh.u[lane] = un;
+          if (lane == 0) {
+            sh.err = e;
+            sh.flag = go_on && anyb != 0ull;
+          }
+        }
+        __syncthreads();
+        const double err = sh.err;
+        if (err <= tol) {
+          converged = true;
+          break;
+        }
+        if (!(err == err) || it >= p.max_iter) break;
+        if (sh.flag) {
+          // exact X-iteration in the log domain:
+          //   F0(x) = -LSE_y[G(y) + log nu_J(y) - C(x,y)],  G(y) = -(m(y) + log S(y))
+          double* dr8 = reinterpret_cast<double*>(rd);  // 288 doubles per wave
+#pragma unroll
+          for (int j = 0; j < 8; j++) {
+            double mm = -INFINITY;
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+              const int yi = ybase + t;
+              const float S = sh.S[yi], nf = sh.nuf[yi];
+              if (yi < U && S > 0.f && nf > 0.f) {
+                const int rc = sh.yrc[yi];
+                const int dr = (rc >> 16) - xr, dc = (rc & 0xffff) - (g.C0 + j);
+                const double e = -(mbuf[yi] + log((double)S)) + log((double)nf) -
+                                 lam * (double)(dr * dr + dc * dc);
+                mm = e > mm ? e : mm;
+              }
+            }
+#pragma unroll
+            for (int o = 8; o < 64; o <<= 1) {
+              const double v = __shfl_xor(mm, o, 64);
+              mm = v > mm ? v : mm;
+            }
+            if (yg == 0) dr8[xg * 8 + j] = mm;
+          }
+          __syncthreads();
+          if (tid < 64) {
+            double mm = -INFINITY;
+            for (int w = 0; w < NW; w++) {
+              const double v = reinterpret_cast<double*>(sh.red[w])[tid];
+              mm = v > mm ? v : mm;
+            }
+            sh.mx[tid] = mm;
+          }
+          __syncthreads();
+#pragma unroll
+          for (int j = 0; j < 8; j++) {
+            const double mm = sh.mx[xg * 8 + j];
+            double s = 0;
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+              const int yi = ybase + t;
+              const float S = sh.S[yi], nf = sh.nuf[yi];
+              if (yi < U && S > 0.f && nf > 0.f) {
+                const int rc = sh.yrc[yi];
+                const int dr = (rc >> 16) - xr, dc = (rc & 0xffff) - (g.C0 + j);
+                const double e = -(mbuf[yi] + log((double)S)) + log((double)nf) -
+                                 lam * (double)(dr * dr + dc * dc) - mm;
+                s += (double)fast_exp2((float)(e * kLog2e));
+              }
+            }
+#pragma unroll
+            for (int o = 8; o < 64; o <<= 1) s += __shfl_xor(s, o, 64);
+            if (yg == 0) dr8[64 + xg * 8 + j] = s;
+          }
+          __syncthreads();
+          if (tid < 64 && sh.mu[tid] > 0) {
+            double s = 0;
+            for (int w = 0; w < NW; w++) s += reinterpret_cast<double*>(sh.red[w])[64 + tid];
+            sh.F0[tid] = -(sh.mx[tid] + log(s));
+          }
+          rebuild = true;
+          __syncthreads();
+        }
+      }
+      loops_all += it;
+      if (phase == 0) {
+        if (converged) break;
+        if (phases > 1) status |= 4;
+        continue;
+      }
+      if (phase == 1 && sh.err == sh.err) continue;  // always return to eps
+      break;
+    }
+    if (!converged) status |= (sh.err == sh.err) ? 1 : 2;
+
+    // ---- final: split of the last Y-iteration by basic cell, cost, objective
+    float sl_t, sl_b, sr_t, sr_b, cp;
+    {
+      float uu[8], v[8];
+#pragma unroll
+      for (int j = 0; j < 8; j++) uu[j] = sh.u[xg * 8 + j];
+#pragma unroll
+      for (int t = 0; t < 8; t++) {
+        float s = 0.f;
+#pragma unroll
+        for (int j = 0; j < 4; j++) s = fmaf(P[j][t], uu[j], s);
+        v[t] = s;
+      }
+      transpose_y(rd, xg, yg, v, &sl_t, &sl_b);
+#pragma unroll
+      for (int t = 0; t < 8; t++) {
+        float s = 0.f;
+#pragma unroll
+        for (int j = 4; j < 8; j++) s = fmaf(P[j][t], uu[j], s);
+        v[t] = s;
+      }
+      transpose_y(rd, xg, yg, v, &sr_t, &sr_b);
+#pragma unroll
+      for (int t = 0; t < 8; t++) {
+        const int yi = ybase + t;
+        const int rc = sh.yrc[yi];
+        const int dr = (rc >> 16) - xr, dc0 = (rc & 0xffff) - g.C0;
+        float s = 0.f;
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+          const int dc = dc0 - j;
+          s = fmaf((float)(dr * dr + dc * dc), P[j][t] * uu[j], s);
+        }
+        v[t] = s;
+      }
+      float c1, c2;
+      transpose_y(rd, xg, yg, v, &c1, &c2);
+      cp = c1 + c2;
+    }
+    const int yi = ybase + xg;
+    const bool own = yi < U;
+    int key = 0;
+    double vq[4] = {0, 0, 0, 0}, cost_y = 0, obj_y = 0, nuJ = 0;
+    if (own) {
+      key = p.uni_key[ub + yi];
+      nuJ = p.uni_nu[ub + yi];
+      const double s0 = sl_t, s1 = sr_t, s2 = sl_b, s3 = sr_b;
+      const double S = (s0 + s1) + (s2 + s3);
+      vq[0] = nuJ * (s0 / S);
+      vq[1] = nuJ * (s1 / S);
+      vq[2] = nuJ * (s2 / S);
+      vq[3] = nuJ * (s3 / S);
+      cost_y = nuJ * ((double)cp / S) * (p.h * p.h);
+      // nu_J(y) (G(y) + log(nu_J(y)/nu(y))) - nu_J(y),  G(y) = -(m(y) + log S(y))
+      const bool key_ok = (unsigned)key < (unsigned)(p.H * p.W);
+      if (nuJ > 0 && key_ok) obj_y = nuJ * (-(mbuf[yi] + log(S)) + log(nuJ) - log(p.nu[key])) - nuJ;
+    }
+    const double cost = block_sum_d(cost_y, sh.out.red);
+    double objx = 0;
+    if (tid < 64 && sh.mu[tid] > 0) {
+      const double F = sh.F0[tid] + log((double)sh.u[tid]);
+      objx = (double)sh.u[tid] * (double)sh.r[tid] * F;
+    }
+    const double obj = block_sum_d(obj_y + objx, sh.out.red);
+    if (tid < 4) sh.out.cnt[tid] = 0;
+    __syncthreads();
+    balance_truncate_write(p, g, obase, U, own, yi, key, vq, massmu, sh.out);
+    if (tid == 0) {
+#pragma unroll
+      for (int a = 0; a < 4; a++)
+        if (g.bq[a] >= 0) {
+          p.row_off[g.bq[a]] = obase + (int64_t)g.qidx[a] * U;
+          p.row_len[g.bq[a]] = (int)min((long long)U, sh.out.cnt[a]);
+        }
+      p.r_cost[cell] = cost;
+      p.r_obj[cell] = p.eps * obj;
+      p.r_err[cell] = sh.err;
+      p.r_loops[cell] = loops_all;
+      p.r_status[cell] = status;
+      p.r_evals[cell] = (long long)loops_all * 16 * g.nq * U;
+    }
+    if (tid < 64 && sh.mu[tid] > 0) {
+      const int i = tid >> 3, j = tid & 7;
+      p.alpha[(int64_t)(g.R0 + i) * p.W + g.C0 + j] = p.eps * (sh.F0[tid] + log((double)sh.u[tid]));
+    }
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ big-cell solver
+
+// Cells whose union exceeds the register capacity: the same Sinkhorn
+// iteration evaluated in the log domain on every pass (FP64 exponents, FP32
+// exponentials, FP64 sums), potentials G(y) kept in the union scratch.
+constexpr int kBigThreads = 1024;
+struct BigShared {
+  double F[64], Fmu[64], mu[64], Fh[64], F0orig[64];
+  int xr[64], xc[64];
+  double pm[16][64], ps[16][64];
+  double err;
+  CellOutSh out;
+};
+
+__global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int bin) {
+  __shared__ BigShared sh;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int count = p.bin_count[bin];
+  const double invW = 1.0 / p.W;
+  for (int ci = blockIdx.x; ci < count; ci += gridDim.x) {
+    const int cell = p.bin_list[bin * p.n_cells + ci];
+    const CellGeo g = load_geo(p, cell);
+    const int U = p.cell_U[cell];
+    const int64_t ub = p.cell_toff[cell];
+    const int64_t obase = p.cell_ooff[cell];
+    if (tid < 64) {
+      const int i = tid >> 3, j = tid & 7;
+      const int qa = (i >> 2) * 2 + (j >> 2);
+      const int r = g.R0 + i, c = g.C0 + j;
+      double mu = 0, F = 0;
+      const int bq = qa == 0 ? g.bq[0] : qa == 1 ? g.bq[1] : qa == 2 ? g.bq[2] : g.bq[3];
+      if (bq >= 0) {
+        mu = p.mu[(int64_t)r * p.W + c];
+        F = p.alpha[(int64_t)r * p.W + c] / p.eps;
+      }
+      sh.mu[tid] = mu;
+      sh.F[tid] = F;
+      sh.F0orig[tid] = F;
+      sh.xr[tid] = r;
+      sh.xc[tid] = c;
+    }
+    __syncthreads();
+    double massmu[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 64; k++) massmu[((k >> 3) >> 2) * 2 + ((k & 7) >> 2)] += sh.mu[k];
+    const double tol = p.err_tol * (massmu[0] + massmu[1] + massmu[2] + massmu[3]);
+    double* G = p.uni_G + ub;
+    int status = 0, loops_all = 0;
+    bool converged = false;
+    double lam = p.lam;
+    const int phases = p.safeguard ? 3 : 1;
+    for (int phase = 0; phase < phases; phase++) {
+      if (phase == 1) {
+        lam = p.lam * 0.5;
+        if (tid < 64) sh.F[tid] = sh.F0orig[tid] * 0.5;
+      } else if (phase == 2) {
+        lam = p.lam;
+        if (tid < 64) sh.F[tid] *= 2.0;
+      }
+      __syncthreads();
+      if (tid < 64) sh.Fmu[tid] = sh.mu[tid] > 0 ? sh.F[tid] + log(sh.mu[tid]) : -INFINITY;
+      __syncthreads();
+      int it = 0;
+      for (;;) {
+        it++;
+        // Y-iteration
+        for (int yi = tid; yi < U; yi += kBigThreads) {
+          int r, c;
+          split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
+          double m = -INFINITY;
+          for (int k = 0; k < 64; k++) {
+            const int dr = r - sh.xr[k], dc = c - sh.xc[k];
+            const double e = sh.Fmu[k] - lam * (double)(dr * dr + dc * dc);
+            m = e > m ? e : m;
+          }
+          double s = 0;
+          for (int k = 0; k < 64; k++) {
+            const int dr = r - sh.xr[k], dc = c - sh.xc[k];
+            const double e = sh.Fmu[k] - lam * (double)(dr * dr + dc * dc) - m;
+            s += (double)fast_exp2((float)(e * kLog2e));
+          }
+          const double nu = p.uni_nu[ub + yi];
+          G[yi] = -(m + log(s)) + (nu > 0 ? log(nu) : -INFINITY);  // G(y) + log nu_J(y)
+        }
+        __syncthreads();
+        // X-marginal: Fh(x) = -LSE_y[G(y) + log nu_J(y) - C(x,y)], online per thread
+        {
+          const int x = lane;
+          double m = -INFINITY, s = 0;
+          for (int yi = wave; yi < U; yi += 16) {
+            int r, c;
+            split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
+            const int dr = r - sh.xr[x], dc = c - sh.xc[x];
+            const double e = G[yi] - lam * (double)(dr * dr + dc * dc);
+            if (e == -INFINITY) continue;
+            if (e > m) {
+              s = s * (double)fast_exp2((float)((m - e) * kLog2e)) + 1.0;
+              m = e;
+            } else {
+              s += (double)fast_exp2((float)((e - m) * kLog2e));
+            }
+          }
+          sh.pm[wave][x] = m;
+          sh.ps[wave][x] = s;
+        }
+        __syncthreads();
+        if (wave == 0) {
+          double m = -INFINITY;
+          for (int w = 0; w < 16; w++) m = sh.pm[w][lane] > m ? sh.pm[w][lane] : m;
+          double s = 0;
+          for (int w = 0; w < 16; w++)
+            if (sh.ps[w][lane] > 0) s += sh.ps[w][lane] * exp(sh.pm[w][lane] - m);
+          const double Fh = -(m + log(s));
+          sh.Fh[lane] = Fh;
+          const double mu = sh.mu[lane];
+          double e = mu > 0 ? mu * fabs(exp(sh.F[lane] - Fh) - 1.0) : 0.0;
+          e = wave_sum(e);
+          if (lane == 0) sh.err = e;
+        }
+        __syncthreads();
+        const double err = sh.err;
+        if (err <= tol) {
+          converged = true;
+          break;
+        }
+        if (!(err == err) || it >= p.max_iter) break;
+        if (tid < 64 && sh.mu[tid] > 0) {
+          sh.F[tid] = sh.Fh[tid];
+          sh.Fmu[tid] = sh.F[tid] + log(sh.mu[tid]);
+        }
+        __syncthreads();
+      }
+      loops_all += it;
+      if (phase == 0) {
+        if (converged) break;
+        if (phases > 1) status |= 4;
+        continue;
+      }
+      if (phase == 1 && sh.err == sh.err) continue;  // always return to eps
+      break;
+    }
+    if (!converged) status |= (sh.err == sh.err) ? 1 : 2;
+    // final split / cost / objective, chunked over the support
+    if (tid < 4) sh.out.cnt[tid] = 0;
+    __syncthreads();
+    double cost_acc = 0, obj_acc = 0;
+    for (int y0 = 0; y0 < U; y0 += kBigThreads) {
+      const int yi = y0 + tid;
+      const bool own = yi < U;
+      double vq[4] = {0, 0, 0, 0};
+      int key = 0;
+      if (own) {
+        key = p.uni_key[ub + yi];
+        int r, c;
+        split_key(key, p.W, invW, &r, &c);
+        const double gl = G[yi];
+        double sq[4] = {0, 0, 0, 0}, cs = 0;
+        // plan column: pi(x,y) = exp(F(x) + log mu(x) + G(y) + log nu_J(y) - C(x,y))
+        double m = -INFINITY;
+        for (int k = 0; k < 64; k++) {
+          const int dr = r - sh.xr[k], dc = c - sh.xc[k];
+          const double e = sh.Fmu[k] - lam * (double)(dr * dr + dc * dc);
+          m = e > m ? e : m;
+        }
+        for (int k = 0; k < 64; k++) {
+          const int dr = r - sh.xr[k], dc = c - sh.xc[k];
+          const int d2 = dr * dr + dc * dc;
+          const double e = sh.Fmu[k] - lam * (double)d2 - m;
+          const double v = (double)fast_exp2((float)(e * kLog2e));
+          const int qa = ((k >> 5) << 1) | ((k & 7) >> 2);
+          sq[0] += qa == 0 ? v : 0.0;
+          sq[1] += qa == 1 ? v : 0.0;
+          sq[2] += qa == 2 ? v : 0.0;
+          sq[3] += qa == 3 ? v : 0.0;
+          cs += v * (double)d2;
+        }
+        const double nuJ = p.uni_nu[ub + yi];
+        const double S = sq[0] + sq[1] + sq[2] + sq[3];
+        _Pragma("unroll") for (int a = 0; a < 4; a++) vq[a] = nuJ * (sq[a] / S);
+        cost_acc += nuJ * (cs / S) * (p.h * p.h);
+        const double Gy = gl - (nuJ > 0 ? log(nuJ) : 0.0);
+        const bool key_ok = (unsigned)key < (unsigned)(p.H * p.W);
+        obj_acc += (nuJ > 0 && key_ok) ? nuJ * (Gy + log(nuJ) - log(p.nu[key])) - nuJ : 0.0;
+      }
+      // chunk-wise norms are accumulated by the balancing helper only for one
+      // chunk; large cells therefore balance in a second pass below
+      if (own) {
+        // stash the unbalanced split in the output region (segment per quadrant)
+        _Pragma("unroll") for (int a = 0; a < 4; a++)
+          if (g.bq[a] >= 0) {
+            const int64_t at = obase + (int64_t)g.qidx[a] * U + yi;
+            p.ent_val[at] = vq[a];
+            p.ent_col[at] = key;
+          }
+      }
+    }
+    __syncthreads();
+    // balance: norms over the whole support, then per-y update and compaction
+    double nrm[4];
+    _Pragma("unroll") for (int a = 0; a < 4; a++) {
+      double s = 0;
+      if (g.bq[a] >= 0)
+        for (int yi = tid; yi < U; yi += kBigThreads) s += p.ent_val[obase + (int64_t)g.qidx[a] * U + yi];
+      nrm[a] = block_sum_d(s, sh.out.red);
+    }
+    if (tid == 0) {
+      double E = 0, D = 0;
+      _Pragma("unroll") for (int a = 0; a < 4; a++) {
+        double d = g.bq[a] >= 0 ? massmu[a] - nrm[a] : 0.0;
+        sh.out.dq[a] = d;
+        if (d < 0) E += -d;
+        if (d > 0) D += d;
+      }
+      double T = E < D ? E : D;
+      _Pragma("unroll") for (int a = 0; a < 4; a++)
+        sh.out.tq[a] = (T > 0 && sh.out.dq[a] < 0) ? T * (-sh.out.dq[a]) / (E * nrm[a]) : 0.0;
+      sh.out.E = T > 0 ? E : 0.0;
+      sh.out.D = T > 0 ? D : 0.0;
+    }
+    __syncthreads();
+    for (int y0 = 0; y0 < U; y0 += kBigThreads) {
+      const int yi = y0 + tid;
+      const bool own = yi < U;
+      double v[4] = {0, 0, 0, 0};
+      int key = 0;
+      if (own) {
+        _Pragma("unroll") for (int a = 0; a < 4; a++)
+          if (g.bq[a] >= 0) {
+            const int64_t at = obase + (int64_t)g.qidx[a] * U + yi;
+            v[a] = p.ent_val[at];
+            key = p.ent_col[at];
+          }
+        if (sh.out.D > 0) {
+          double R = 0;
+          _Pragma("unroll") for (int a = 0; a < 4; a++)
+            if (g.bq[a] >= 0 && sh.out.dq[a] < 0) {
+              const double rr = v[a] * sh.out.tq[a];
+              v[a] -= rr;
+              R += rr;
+            }
+          _Pragma("unroll") for (int a = 0; a < 4; a++)
+            if (g.bq[a] >= 0 && sh.out.dq[a] > 0) v[a] += R * sh.out.dq[a] / sh.out.D;
+        }
+      }
+      unsigned long long flags = 0;
+      if (own)
+        _Pragma("unroll") for (int a = 0; a < 4; a++)
+          if (g.bq[a] >= 0 && v[a] >= p.trunc && v[a] > 0.0) flags |= 1ull << (16 * a);
+      long long tot;
+      long long ex = block_excl_scan((long long)flags, sh.out.scan, &tot);
+      __syncthreads();  // every thread has read its chunk before any compacted write
+      if (own)
+        _Pragma("unroll") for (int a = 0; a < 4; a++)
+          if ((flags >> (16 * a)) & 1ull) {
+            const long long pos = sh.out.cnt[a] + ((ex >> (16 * a)) & 0xffffll);
+            if (pos < U) {
+              const int64_t at = obase + (int64_t)g.qidx[a] * U + pos;
+              p.ent_col[at] = key;
+              p.ent_val[at] = v[a];
+            }
+          }
+      __syncthreads();
+      if (tid == 0)
+        _Pragma("unroll") for (int a = 0; a < 4; a++) sh.out.cnt[a] += (tot >> (16 * a)) & 0xffffll;
+      __syncthreads();
+    }
+    const double cost = block_sum_d(cost_acc, sh.out.red);
+    double objx = 0;
+    if (tid < 64 && sh.mu[tid] > 0) {
+      // X-marginal of the final plan is mu(x) exp(F - Fh)
+      objx = sh.mu[tid] * exp(sh.F[tid] - sh.Fh[tid]) * sh.F[tid];
+    }
+    const double obj = block_sum_d(obj_acc + objx, sh.out.red);
+    if (tid == 0) {
+      _Pragma("unroll") for (int a = 0; a < 4; a++)
+        if (g.bq[a] >= 0) {
+          p.row_off[g.bq[a]] = obase + (int64_t)g.qidx[a] * U;
+          p.row_len[g.bq[a]] = (int)min((long long)U, sh.out.cnt[a]);
+        }
+      p.r_cost[cell] = cost;
+      p.r_obj[cell] = p.eps * obj;
+      p.r_err[cell] = sh.err;
+      p.r_loops[cell] = loops_all;
+      p.r_status[cell] = status;
+      int nx = 0;
+      _Pragma("unroll") for (int a = 0; a < 4; a++) nx += g.bq[a] >= 0 ? 16 : 0;
+      p.r_evals[cell] = (long long)loops_all * nx * U;
+    }
+    if (tid < 64 && sh.mu[tid] > 0)
+      p.alpha[sh.xr[tid] * p.W + sh.xc[tid]] = p.eps * sh.F[tid] * (lam / p.lam);
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------ stats
+
+__global__ __launch_bounds__(1024) void k_stats(HalfParams p, IterStatsDev* out) {
+  __shared__ double shd[16];
+  __shared__ long long shl[16];
+  double c = 0, o = 0, e = 0;
+  long long lt = 0, ev = 0, nnz = 0;
+  int lmax = 0, nf = 0, ns = 0;
+  for (int i = threadIdx.x; i < p.n_cells; i += 1024) {
+    c += p.r_cost[i];
+    o += p.r_obj[i];
+    e += p.r_err[i];
+    lt += p.r_loops[i];
+    ev += p.r_evals[i];
+    lmax = max(lmax, p.r_loops[i]);
+    nf += (p.r_status[i] & 3) != 0;
+    ns += (p.r_status[i] & 4) != 0;
+  }
+  for (int b = threadIdx.x; b < p.n_basic; b += 1024) nnz += p.row_len[b];
+  c = block_sum_d(c, shd);
+  o = block_sum_d(o, shd);
+  e = block_sum_d(e, shd);
+  long long tot;
+  block_excl_scan(lt, shl, &tot);
+  lt = tot;
+  block_excl_scan(ev, shl, &tot);
+  ev = tot;
+  block_excl_scan(nnz, shl, &tot);
+  nnz = tot;
+  block_excl_scan((long long)nf, shl, &tot);
+  nf = (int)tot;
+  block_excl_scan((long long)ns, shl, &tot);
+  ns = (int)tot;
+  int lm = wave_max(lmax);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) shl[threadIdx.x >> 6] = lm;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long m = 0;
+    for (int w = 0; w < 16; w++) m = max(m, shl[w]);
+    out->cost = c;
+    out->obj = o;
+    out->err = e;
+    out->loops_total = lt;
+    out->evals = ev;
+    out->nnz = nnz;
+    out->loops_max = (int)m;
+    out->n_failed = nf;
+    out->n_safeguard = ns;
+    out->n_cells = p.n_cells;
+  }
+}
+
+// ------------------------------------------------------------ launchers
+
+void launch_sweep(const HalfParams& p, hipStream_t st, int grid_cap) {
+  hipLaunchKernelGGL(k_scan_T, dim3(1), dim3(1024), 0, st, p);
+  const int gu = p.n_cells < grid_cap ? p.n_cells : grid_cap;
+  hipLaunchKernelGGL(k_union, dim3(gu), dim3(kUnionThreads), 0, st, p);
+  hipLaunchKernelGGL(k_scan_out, dim3(1), dim3(1024), 0, st, p);
+  const int g = gu;
+  hipLaunchKernelGGL(k_solve_reg<1>, dim3(g), dim3(64), 0, st, p, 0);
+  hipLaunchKernelGGL(k_solve_reg<2>, dim3(g), dim3(128), 0, st, p, 1);
+  hipLaunchKernelGGL(k_solve_reg<4>, dim3(g), dim3(256), 0, st, p, 2);
+  hipLaunchKernelGGL(k_solve_reg<8>, dim3(g), dim3(512), 0, st, p, 3);
+  hipLaunchKernelGGL(k_solve_reg<16>, dim3(g), dim3(1024), 0, st, p, 4);
+  hipLaunchKernelGGL(k_solve_big, dim3(g), dim3(kBigThreads), 0, st, p, 5);
+}
+
+size_t sweep_max_static_lds() {
+  const void* ks[] = {(const void*)k_union, (const void*)k_solve_reg<1>, (const void*)k_solve_reg<2>,
+                      (const void*)k_solve_reg<4>, (const void*)k_solve_reg<8>,
+                      (const void*)k_solve_reg<16>, (const void*)k_solve_big};
+  size_t mx = 0;
+  for (const void* k : ks) {
+    hipFuncAttributes a;
+    if (hipFuncGetAttributes(&a, k) == hipSuccess && a.sharedSizeBytes > mx) mx = a.sharedSizeBytes;
+  }
+  return mx;
+}
+
+void launch_stats(const HalfParams& p, IterStatsDev* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_stats, dim3(1), dim3(1024), 0, st, p, out);
+}
+
+// ------------------------------------------------------------ setup kernels
+
+__global__ __launch_bounds__(1024) void k_validate(const double* mu, const double* nu, int H,
+                                                   int W, double* out4) {
+  __shared__ double sh[16];
+  double sm = 0, sn = 0, bad = 0;
+  for (long long i = threadIdx.x; i < (long long)H * W; i += 1024) {
+    double a = mu[i], b = nu[i];
+    if (!(a >= 0) || !(b >= 0) || !isfinite(a) || !isfinite(b)) bad += 1;
+    sm += a;
+    sn += b;
+  }
+  // smallest basic-cell mass of mu
+  const int bh = H / kS, bw = W / kS;
+  double mn = INFINITY;
+  for (int b = threadIdx.x; b < bh * bw; b += 1024) {
+    int br = b / bw, bc = b % bw;
+    double m = 0;
+    for (int i = 0; i < kS; i++)
+      for (int j = 0; j < kS; j++) m += mu[(long long)(br * kS + i) * W + bc * kS + j];
+    mn = m < mn ? m : mn;
+  }
+  sm = block_sum_d(sm, sh);
+  sn = block_sum_d(sn, sh);
+  bad = block_sum_d(bad, sh);
+  double mw = wave_min(mn);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = mw;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = INFINITY;
+    for (int w = 0; w < 16; w++) m = sh[w] < m ? sh[w] : m;
+    out4[0] = sm;
+    out4[1] = sn;
+    out4[2] = bad;
+    out4[3] = m;
+  }
+}
+
+void launch_validate(const double* mu, const double* nu, int H, int W, double* out4,
+                     hipStream_t st) {
+  hipLaunchKernelGGL(k_validate, dim3(1), dim3(1024), 0, st, mu, nu, H, W, out4);
+}
+
+__global__ void k_pyramid(const double* fine, double* coarse, int Hc, int Wc) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= (long long)Hc * Wc) return;
+  int r = (int)(i / Wc), c = (int)(i % Wc);
+  const int Wf = 2 * Wc;
+  coarse[i] = (fine[(2LL * r) * Wf + 2 * c] + fine[(2LL * r) * Wf + 2 * c + 1]) +
+              (fine[(2LL * r + 1) * Wf + 2 * c] + fine[(2LL * r + 1) * Wf + 2 * c + 1]);
+}
+
+void launch_pyramid(const double* fine, double* coarse, int Hc, int Wc, hipStream_t st) {
+  long long n = (long long)Hc * Wc;
+  hipLaunchKernelGGL(k_pyramid, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, fine, coarse,
+                     Hc, Wc);
+}
+
+__global__ void k_product_init(const int* ypos, int nzy, const double* nu, const double* bmass,
+                               int n_basic, int* col, double* val, int64_t* row_off,
+                               int* row_len) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i < n_basic) {
+    row_off[i] = i * (long long)nzy;
+    row_len[i] = nzy;
+  }
+  if (i >= (long long)n_basic * nzy) return;
+  int b = (int)(i / nzy), k = (int)(i % nzy);
+  col[i] = ypos[k];
+  val[i] = bmass[b] * nu[ypos[k]];
+}
+
+void launch_product_init(const int* ypos, int nzy, const double* nu, const double* bmass,
+                         int n_basic, int* col, double* val, int64_t* row_off, int* row_len,
+                         hipStream_t st) {
+  long long n = (long long)n_basic * nzy;
+  if (n < n_basic) n = n_basic;
+  hipLaunchKernelGGL(k_product_init, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, ypos,
+                     nzy, nu, bmass, n_basic, col, val, row_off, row_len);
+}
+
+// ------------------------------------------------------------ diagnostics
+
+__global__ void k_diag_scatter(const int64_t* row_off, const int* row_len, const int* col,
+                               const double* val, int n_basic, double* acc) {
+  int b = blockIdx.x;
+  if (b >= n_basic) return;
+  const int64_t o = row_off[b];
+  for (int k = threadIdx.x; k < row_len[b]; k += blockDim.x) atomicAdd(&acc[col[o + k]], val[o + k]);
+}
+
+__global__ __launch_bounds__(1024) void k_diag_reduce(const int64_t* row_off, const int* row_len,
+                                                      const double* val, const double* mu,
+                                                      const double* nu, const double* acc, int H,
+                                                      int W, int bw, int n_basic, double* out3) {
+  __shared__ double sh[16];
+  double ey = 0, dm = 0, nnz = 0;
+  for (long long i = threadIdx.x; i < (long long)H * W; i += 1024) ey += fabs(acc[i] - nu[i]);
+  for (int b = threadIdx.x; b < n_basic; b += 1024) {
+    double m = 0, mm = 0;
+    for (int k = 0; k < row_len[b]; k++) m += val[row_off[b] + k];
+    int br = b / bw, bc = b % bw;
+    for (int i = 0; i < kS; i++)
+      for (int j = 0; j < kS; j++) mm += mu[(long long)(br * kS + i) * W + bc * kS + j];
+    dm += fabs(m - mm);
+    nnz += row_len[b];
+  }
+  ey = block_sum_d(ey, sh);
+  dm = block_sum_d(dm, sh);
+  nnz = block_sum_d(nnz, sh);
+  if (threadIdx.x == 0) {
+    out3[0] = ey;
+    out3[1] = dm;
+    out3[2] = nnz;
+  }
+}
+
+void launch_diag(const int64_t* row_off, const int* row_len, const int* col, const double* val,
+                 const double* mu, const double* nu, int H, int W, int bw, int n_basic,
+                 double* scratch_px, double* out3, hipStream_t st) {
+  hipMemsetAsync(scratch_px, 0, sizeof(double) * (size_t)H * W, st);
+  hipLaunchKernelGGL(k_diag_scatter, dim3(n_basic), dim3(64), 0, st, row_off, row_len, col, val,
+                     n_basic, scratch_px);
+  hipLaunchKernelGGL(k_diag_reduce, dim3(1), dim3(1024), 0, st, row_off, row_len, val, mu, nu,
+                     scratch_px, H, W, bw, n_basic, out3);
+}
+
+// ------------------------------------------------------------ export
+
+__global__ __launch_bounds__(1024) void k_scan_rows(const int* row_len, int n, int64_t* row_ptr) {
+  __shared__ long long sh[16];
+  long long carry = 0;
+  for (int base = 0; base < n; base += 1024) {
+    int i = base + threadIdx.x;
+    long long v = i < n ? row_len[i] : 0;
+    long long tot;
+    long long ex = block_excl_scan(v, sh, &tot);
+    if (i < n) row_ptr[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) row_ptr[n] = carry;
+}
+
+void launch_scan_rows(const int* row_len, int n, int64_t* row_ptr, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(1024), 0, st, row_len, n, row_ptr);
+}
+
+__global__ void k_export(const int64_t* row_off, const int* row_len, const int* col,
+                         const double* val, int n_basic, const int64_t* row_ptr, int* col_out,
+                         double* val_out) {
+  int b = blockIdx.x;
+  if (b >= n_basic) return;
+  const int64_t o = row_off[b], d = row_ptr[b];
+  for (int k = threadIdx.x; k < row_len[b]; k += blockDim.x) {
+    col_out[d + k] = col[o + k];
+    val_out[d + k] = val[o + k];
+  }
+}
+
+void launch_export(const int64_t* row_off, const int* row_len, const int* col, const double* val,
+                   int n_basic, int64_t* row_ptr_dev, int* col_out, double* val_out,
+                   hipStream_t st) {
+  launch_scan_rows(row_len, n_basic, row_ptr_dev, st);
+  hipLaunchKernelGGL(k_export, dim3(n_basic), dim3(64), 0, st, row_off, row_len, col, val,
+                     n_basic, row_ptr_dev, col_out, val_out);
+}
+
+// ------------------------------------------------------------ refinement
+
+// Fine basic marginals by eq. (FineBasicMarginals):
+//   nu_i(y) = nu(y) * nuhat_{Pa(i)}(pa(y)) / nuhat(pa(y)) * mu(X_i) / muhat(Xhat_{Pa(i)}).
+// Every coarse support point has four children; the fine row is written in
+// increasing linear index: for each run of parent points on one coarse row,
+// first the children on the upper fine row, then those on the lower one.
+__global__ __launch_bounds__(64) void k_refine_fill(RefineParams r) {
+  const int b = blockIdx.x;
+  if (b >= r.n_basic_f) return;
+  const int br = b / r.bwf, bc = b % r.bwf;
+  const int P = (br >> 1) * r.bwc + (bc >> 1);
+  const int pr = P / r.bwc, pc = P % r.bwc;
+  double mi = 0, mP = 0;
+  for (int i = 0; i < kS; i++)
+    for (int j = 0; j < kS; j++) {
+      mi += r.mu_f[(long long)(br * kS + i) * r.Wf + bc * kS + j];
+      mP += r.mu_c[(long long)(pr * kS + i) * r.Wc + pc * kS + j];
+    }
+  const double ratio_mu = mi / mP;
+  const int64_t po = r.row_off_c[P];
+  const int L = r.row_len_c[P];
+  const int64_t fo = r.row_off_f[b];
+  const int* key = r.col_c + po;
+  for (int k = threadIdx.x; k < L; k += 64) {
+    const int y = key[k];
+    const int yr = y / r.Wc, yc = y - (y / r.Wc) * r.Wc;
+    // run of parent points on coarse row yr: [s, e)
+    int lo = 0, hi = L;
+    const int k0 = yr * r.Wc;
+    while (lo < hi) {
+      int m = (lo + hi) >> 1;
+      if (key[m] < k0) lo = m + 1; else hi = m;
+    }
+    const int s = lo;
+    lo = s;
+    hi = L;
+    const int k1 = k0 + r.Wc;
+    while (lo < hi) {
+      int m = (lo + hi) >> 1;
+      if (key[m] < k1) lo = m + 1; else hi = m;
+    }
+    const int e = lo;
+    const double f = r.val_c[po + k] / r.nu_c[y] * ratio_mu;
+    for (int u = 0; u < 2; u++)
+      for (int v = 0; v < 2; v++) {
+        const int64_t idx = 4LL * s + (int64_t)u * 2 * (e - s) + 2LL * (k - s) + v;
+        const int yf = (2 * yr + u) * r.Wf + 2 * yc + v;
+        r.col_f[fo + idx] = yf;
+        r.val_f[fo + idx] = r.nu_f[yf] * f;
+      }
+  }
+}
+
+__global__ void k_refine_rows_len(RefineParams r) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= r.n_basic_f) return;
+  const int br = b / r.bwf, bc = b % r.bwf;
+  const int P = (br >> 1) * r.bwc + (bc >> 1);
+  r.row_len_f[b] = 4 * r.row_len_c[P];
+}
+
+void launch_refine_rows(const RefineParams& r, hipStream_t st) {
+  hipLaunchKernelGGL(k_refine_rows_len, dim3((r.n_basic_f + 255) / 256), dim3(256), 0, st, r);
+  launch_scan_rows(r.row_len_f, r.n_basic_f, r.row_off_f, st);
+  hipLaunchKernelGGL(k_refine_fill, dim3(r.n_basic_f), dim3(64), 0, st, r);
+}
+
+__global__ void k_glue_ratios(RefineParams r, double* out) {
+  int b = blockIdx.x * blockDim.x + threadIdx.x;
+  const int bh = r.Hc / kS;
+  if (b >= bh * r.bwc) return;
+  const int br = b / r.bwc, bc = b % r.bwc;
+  for (int sgn = 0; sgn < 2; sgn++) {
+    const double sg = sgn == 0 ? 1.0 : -1.0;
+    double m = -INFINITY;
+    for (int i = 0; i < kS; i++)
+      for (int j = 0; j < kS; j++) {
+        long long px = (long long)(br * kS + i) * r.Wc + bc * kS + j;
+        if (r.mu_c[px] > 0) {
+          double v = sg * (r.alpha_a_c[px] - r.alpha_b_c[px]) / r.eps;
+          m = v > m ? v : m;
+        }
+      }
+    double acc = 0, tot = 0;
+    for (int i = 0; i < kS; i++)
+      for (int j = 0; j < kS; j++) {
+        long long px = (long long)(br * kS + i) * r.Wc + bc * kS + j;
+        if (r.mu_c[px] > 0) {
+          acc += r.mu_c[px] * exp(sg * (r.alpha_a_c[px] - r.alpha_b_c[px]) / r.eps - m);
+          tot += r.mu_c[px];
+        }
+      }
+    out[2 * b + sgn] = m + log(acc / tot);
+  }
+}
+
+void launch_glue_ratios(const RefineParams& r, double* out, hipStream_t st) {
+  int n = (r.Hc / kS) * r.bwc;
+  hipLaunchKernelGGL(k_glue_ratios, dim3((n + 127) / 128), dim3(128), 0, st, r, out);
+}
+
+__device__ double interp_w(int n, double t, int* i0) {
+  int i = (int)floor(t);
+  if (i < 0) i = 0;
+  if (i > n - 2) i = n - 2;
+  *i0 = i;
+  return t - i;
+}
+
+__global__ void k_interp(const double* fc, int Hc, int Wc, double* fa, double* fb, int Hf,
+                         int Wf) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= (long long)Hf * Wf) return;
+  int r = (int)(i / Wf), c = (int)(i % Wf);
+  int r0, c0;
+  double tr = interp_w(Hc, r * 0.5 - 0.25, &r0);
+  double tc = interp_w(Wc, c * 0.5 - 0.25, &c0);
+  double v00 = fc[(long long)r0 * Wc + c0], v01 = fc[(long long)r0 * Wc + c0 + 1];
+  double v10 = fc[(long long)(r0 + 1) * Wc + c0], v11 = fc[(long long)(r0 + 1) * Wc + c0 + 1];
+  double v = (1 - tr) * ((1 - tc) * v00 + tc * v01) + tr * ((1 - tc) * v10 + tc * v11);
+  fa[i] = v;
+  fb[i] = v;
+}
+
+void launch_interp(const double* fglued_c, int Hc, int Wc, double* fa, double* fb, int Hf,
+                   int Wf, hipStream_t st) {
+  long long n = (long long)Hf * Wf;
+  hipLaunchKernelGGL(k_interp, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, fglued_c, Hc,
+                     Wc, fa, fb, Hf, Wf);
+}
+
+}  // namespace ddk

@@ -1,0 +1,247 @@
+"""ctypes binding of the HIP library (include/dd.h).
+
+Argument marshalling only: every step of the method runs in the library's
+kernels.  Importing this module loads ``libdd.so`` (built in-tree by
+``paper_2001_10986_amd/csrc/build.py``) and raises if it is missing; there is
+no CPU fallback.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdd.so")
+
+DD_OK, DD_ENOTCONV = 0, 1
+DD_EINVAL, DD_ENOMEM, DD_EHIP, DD_ECAPACITY, DD_ESTATE = -1, -2, -3, -4, -5
+
+EXPORTED = ["dd_options_default", "dd_init", "dd_half_iterate", "dd_set_eps", "dd_refine",
+            "dd_run_schedule", "dd_cost", "dd_export_plan", "dd_import_state",
+            "dd_cell_results", "dd_level_info", "dd_free", "dd_last_error"]
+
+
+class Stage(C.Structure):
+    _fields_ = [("level", C.c_int), ("eps", C.c_double), ("n_half_iters", C.c_int)]
+
+
+class Options(C.Structure):
+    _fields_ = [("err_tol", C.c_double), ("trunc_threshold", C.c_double),
+                ("max_sinkhorn_iter", C.c_int), ("safeguard", C.c_int),
+                ("inputs_on_device", C.c_int), ("stream", C.c_void_p)]
+
+
+class IterStats(C.Structure):
+    _fields_ = [("n_cells", C.c_int), ("loops_max", C.c_int), ("loops_total", C.c_int64),
+                ("n_failed", C.c_int), ("n_safeguard", C.c_int), ("nnz", C.c_int64),
+                ("entry_evals", C.c_int64), ("cost", C.c_double), ("obj", C.c_double),
+                ("err_x", C.c_double), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class RunStats(C.Structure):
+    _fields_ = [("n_half_iters", C.c_int), ("n_cell_solves", C.c_int),
+                ("loops_total", C.c_int64), ("entry_evals", C.c_int64), ("n_failed", C.c_int),
+                ("n_safeguard", C.c_int), ("nnz_max", C.c_int64), ("ms_total", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class CostReport(C.Structure):
+    _fields_ = [("cost", C.c_double), ("obj", C.c_double), ("err_x", C.c_double),
+                ("err_y", C.c_double), ("mass_drift", C.c_double), ("nnz", C.c_int64),
+                ("level", C.c_int), ("last_partition", C.c_int), ("eps", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class PlanView(C.Structure):
+    _fields_ = [("level", C.c_int), ("H", C.c_int), ("W", C.c_int), ("eps", C.c_double),
+                ("n_basic", C.c_int64), ("nnz", C.c_int64), ("row_ptr", C.c_void_p),
+                ("col", C.c_void_p), ("val", C.c_void_p), ("alpha_a", C.c_void_p),
+                ("alpha_b", C.c_void_p)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with "
+                          "`python paper_2001_10986_amd/csrc/build.py`")
+    lib = C.CDLL(LIB_PATH)
+    P = C.POINTER
+    lib.dd_options_default.argtypes = [P(Options)]
+    lib.dd_options_default.restype = None
+    lib.dd_init.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int,
+                            P(Stage), C.c_int, P(Options), P(C.c_void_p)]
+    lib.dd_half_iterate.argtypes = [C.c_void_p, C.c_int, P(IterStats)]
+    lib.dd_set_eps.argtypes = [C.c_void_p, C.c_double]
+    lib.dd_refine.argtypes = [C.c_void_p]
+    lib.dd_run_schedule.argtypes = [C.c_void_p, P(RunStats)]
+    lib.dd_cost.argtypes = [C.c_void_p, P(CostReport)]
+    lib.dd_export_plan.argtypes = [C.c_void_p, P(PlanView)]
+    lib.dd_import_state.argtypes = [C.c_void_p, P(PlanView)]
+    lib.dd_cell_results.argtypes = [C.c_void_p] + [C.c_void_p] * 5
+    lib.dd_level_info.argtypes = [C.c_void_p] + [P(C.c_int)] * 6 + [P(C.c_double)]
+    lib.dd_free.argtypes = [C.c_void_p]
+    lib.dd_free.restype = None
+    lib.dd_last_error.argtypes = [C.c_void_p]
+    lib.dd_last_error.restype = C.c_char_p
+    for name in ("dd_init", "dd_half_iterate", "dd_set_eps", "dd_refine", "dd_run_schedule",
+                 "dd_cost", "dd_export_plan", "dd_import_state", "dd_cell_results",
+                 "dd_level_info"):
+        getattr(lib, name).restype = C.c_int
+    return lib
+
+
+lib = _load()
+
+
+class DDError(RuntimeError):
+    pass
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+class Problem:
+    """One transport problem on the GPU (a dd_ctx).
+
+    mu, nu: H x W float64 arrays (numpy on the host, or torch CUDA tensors,
+    which are read in place); schedule: rows (level, eps, n_half_iters).
+    """
+
+    def __init__(self, mu, nu, schedule, s=4, n_levels=1, err_tol=1e-5, trunc=1e-15,
+                 max_iter=10000, safeguard=1, stream=None):
+        opt = Options()
+        lib.dd_options_default(C.byref(opt))
+        opt.err_tol, opt.trunc_threshold = err_tol, trunc
+        opt.max_sinkhorn_iter, opt.safeguard = max_iter, safeguard
+        on_dev = hasattr(mu, "data_ptr") and getattr(mu, "is_cuda", False)
+        if on_dev:
+            import torch
+            assert mu.dtype == torch.float64 and nu.dtype == torch.float64
+            mu_c, nu_c = mu.contiguous(), nu.contiguous()
+            self._keep = (mu_c, nu_c)
+            H, W = mu_c.shape
+            pm, pn = C.c_void_p(mu_c.data_ptr()), C.c_void_p(nu_c.data_ptr())
+            opt.inputs_on_device = 1
+            if stream is None:
+                stream = torch.cuda.current_stream().cuda_stream
+        else:
+            mu_c = np.ascontiguousarray(mu, dtype=np.float64)
+            nu_c = np.ascontiguousarray(nu, dtype=np.float64)
+            self._keep = (mu_c, nu_c)
+            H, W = mu_c.shape
+            pm, pn = _p(mu_c), _p(nu_c)
+        opt.stream = stream
+        self.H, self.W, self.s, self.n_levels = H, W, s, n_levels
+        self.schedule = [tuple(x) for x in schedule]
+        arr = (Stage * len(schedule))(*[Stage(int(l), float(e), int(n))
+                                        for l, e, n in schedule])
+        h = C.c_void_p()
+        rc = lib.dd_init(pm, pn, H, W, s, n_levels, arr, len(schedule), C.byref(opt),
+                         C.byref(h))
+        if rc != 0:
+            raise DDError(f"dd_init: {lib.dd_last_error(None).decode()} ({rc})")
+        self._h = h
+
+    def _chk(self, rc, what):
+        if rc < 0:
+            raise DDError(f"{what}: {lib.dd_last_error(self._h).decode()} ({rc})")
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.dd_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def half_iterate(self, partition):
+        st = IterStats()
+        rc = self._chk(lib.dd_half_iterate(self._h, partition, C.byref(st)), "dd_half_iterate")
+        d = st.as_dict()
+        d["status"] = rc
+        return d
+
+    def set_eps(self, eps):
+        self._chk(lib.dd_set_eps(self._h, eps), "dd_set_eps")
+
+    def refine(self):
+        self._chk(lib.dd_refine(self._h), "dd_refine")
+
+    def run_schedule(self):
+        st = RunStats()
+        rc = self._chk(lib.dd_run_schedule(self._h, C.byref(st)), "dd_run_schedule")
+        d = st.as_dict()
+        d["status"] = rc
+        return d
+
+    def cost(self):
+        r = CostReport()
+        self._chk(lib.dd_cost(self._h, C.byref(r)), "dd_cost")
+        return r.as_dict()
+
+    def level_info(self):
+        v = [C.c_int() for _ in range(6)]
+        e = C.c_double()
+        self._chk(lib.dd_level_info(self._h, *[C.byref(x) for x in v], C.byref(e)),
+                  "dd_level_info")
+        keys = ["level", "H", "W", "n_basic", "n_cells_a", "n_cells_b"]
+        out = {k: x.value for k, x in zip(keys, v)}
+        out["eps"] = e.value
+        return out
+
+    def export(self):
+        v = PlanView()
+        self._chk(lib.dd_export_plan(self._h, C.byref(v)), "dd_export_plan")
+        nb, nnz, H, W = v.n_basic, v.nnz, v.H, v.W
+        rp = np.empty(nb + 1, dtype=np.int64)
+        col = np.empty(max(nnz, 1), dtype=np.int32)
+        val = np.empty(max(nnz, 1), dtype=np.float64)
+        aA = np.empty(H * W, dtype=np.float64)
+        aB = np.empty(H * W, dtype=np.float64)
+        v.row_ptr, v.col, v.val = rp.ctypes.data, col.ctypes.data, val.ctypes.data
+        v.alpha_a, v.alpha_b = aA.ctypes.data, aB.ctypes.data
+        self._chk(lib.dd_export_plan(self._h, C.byref(v)), "dd_export_plan")
+        return {"row_ptr": rp, "col": col[:nnz], "val": val[:nnz], "alpha_a": aA.reshape(H, W),
+                "alpha_b": aB.reshape(H, W), "level": v.level, "eps": v.eps}
+
+    def import_state(self, level, eps, row_ptr, col, val, alpha_a, alpha_b):
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        vl = np.ascontiguousarray(val, dtype=np.float64)
+        aA = np.ascontiguousarray(alpha_a, dtype=np.float64)
+        aB = np.ascontiguousarray(alpha_b, dtype=np.float64)
+        v = PlanView()
+        v.level, v.eps = level, eps
+        v.H, v.W = aA.shape
+        v.n_basic = len(rp) - 1
+        v.nnz = int(rp[-1])
+        v.row_ptr, v.col, v.val = rp.ctypes.data, cl.ctypes.data, vl.ctypes.data
+        v.alpha_a, v.alpha_b = aA.ctypes.data, aB.ctypes.data
+        self._chk(lib.dd_import_state(self._h, C.byref(v)), "dd_import_state")
+
+    def cell_results(self):
+        info = self.level_info()
+        last = self.cost()["last_partition"]
+        n = info["n_cells_a"] if last == 0 else info["n_cells_b"]
+        cost, obj, err = (np.empty(n) for _ in range(3))
+        loops, status = np.empty(n, dtype=np.int32), np.empty(n, dtype=np.int32)
+        self._chk(lib.dd_cell_results(self._h, _p(cost), _p(obj), _p(err), _p(loops),
+                                      _p(status)), "dd_cell_results")
+        return {"cost": cost, "obj": obj, "err_x": err, "loops": loops, "status": status}
+
+    def basic_marginals(self):
+        e = self.export()
+        info = self.level_info()
+        out = np.zeros((info["n_basic"], info["H"] * info["W"]))
+        rp = e["row_ptr"]
+        for b in range(info["n_basic"]):
+            out[b, e["col"][rp[b]:rp[b + 1]]] = e["val"][rp[b]:rp[b + 1]]
+        return out
