@@ -72,11 +72,19 @@ typedef struct {
 typedef struct {
   double err_tol;          /* Sinkhorn stop: L1 X-marginal error <= err_tol*|mu_J| (Sec. 6.2); default 1e-5 */
   double trunc_threshold;  /* truncation threshold of the basic marginals (Sec. 6.1 (ii)); default 1e-15 */
-  int max_sinkhorn_iter;   /* Sinkhorn loop cap per cell solve; default 10000 */
+  int max_sinkhorn_iter;   /* Sinkhorn loop cap per cell solve; default 50000 */
   int safeguard;           /* 1: re-solve failed cells at 2*eps, then eps (Sec. 7.4); default 1 */
   int inputs_on_device;    /* 1: mu, nu passed to dd_init are device pointers; default 0 */
+  int timing;              /* 1: record HIP events around every kernel of a sweep; default 0 */
   void* stream;            /* hipStream_t for all work of the context; default NULL */
 } dd_options;
+
+/* Kernels of one sweep, in launch order (indices of the ms_kernel arrays):
+ * 0 cell sizes scan, 1 union, 2 output scan + size bins, 3..7 register
+ * solvers for unions of <= 64, 128, 256, 512, 1024 points, 8 log-domain
+ * solver for larger unions, 9 statistics. */
+#define DD_N_KERNELS 10
+#define DD_N_BINS 6
 
 typedef struct {
   int n_cells;             /* composite cells solved */
@@ -90,6 +98,9 @@ typedef struct {
   double obj;              /* sum over cells of eps*KL(pi_J|K_J) - eps*|K_J| */
   double err_x;            /* sum over cells of the L1 X-marginal error */
   double ms;               /* device time of the half-iteration (ms) */
+  double ms_kernel[DD_N_KERNELS];   /* per-kernel device time (ms) when timing is on, else 0 */
+  int cells_bin[DD_N_BINS];         /* cells per solver bin */
+  int64_t evals_bin[DD_N_BINS];     /* entry_evals per solver bin */
 } dd_iter_stats;
 
 typedef struct {
@@ -101,6 +112,9 @@ typedef struct {
   int n_safeguard;
   int64_t nnz_max;
   double ms_total;         /* wall time of the whole schedule (ms) */
+  double ms_kernel[DD_N_KERNELS];   /* summed per-kernel device time when timing is on */
+  int launches_bin[DD_N_BINS];      /* solver launches that had cells, per bin */
+  int64_t evals_bin[DD_N_BINS];
 } dd_run_stats;
 
 typedef struct {

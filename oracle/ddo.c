@@ -809,9 +809,9 @@ int ddo_refine(ddo_ctx* c) {
     int64_t n = 0;
     for (int64_t k = c->rp[P]; k < c->rp[P + 1]; k++) {
       int y = c->col[k], yr = y / cl->W, yc = y % cl->W;
-      for (int u = 0; u < 2; u++)
-        for (int v = 0; v < 2; v++)
-          if (fl->nu[(2 * yr + u) * fl->W + 2 * yc + v] > 0) n++;
+      (void)yr;
+      (void)yc;
+      n += 4;
     }
     rp[b + 1] = rp[b] + n;
   }
@@ -828,18 +828,17 @@ int ddo_refine(ddo_ctx* c) {
     for (int a = 0; a < s; a++)
       for (int e = 0; e < s; e++) mP += cl->mu[(pr * s + a) * cl->W + pc * s + e];
     int64_t k0 = rp[b], n = 0;
-    /* children of each coarse support point, then sort by fine index */
+    /* all four children of each coarse support point (children of zero mass
+     * are dropped by the next truncation), then sort by fine index */
     for (int64_t k = c->rp[P]; k < c->rp[P + 1]; k++) {
       int y = c->col[k], yr = y / cl->W, yc = y % cl->W;
       double ratio = c->val[k] / cl->nu[y];
       for (int u = 0; u < 2; u++)
         for (int v = 0; v < 2; v++) {
           int yf = (2 * yr + u) * fl->W + 2 * yc + v;
-          if (fl->nu[yf] > 0) {
-            col[k0 + n] = yf;
-            val[k0 + n] = fl->nu[yf] * ratio * (mi / mP);
-            n++;
-          }
+          col[k0 + n] = yf;
+          val[k0 + n] = fl->nu[yf] * ratio * (mi / mP);
+          n++;
         }
     }
     /* insertion sort of the (col,val) pairs of this row */

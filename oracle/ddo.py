@@ -79,7 +79,7 @@ class Oracle:
     """One problem instance of the oracle; mirrors the C-ABI of the GPU library."""
 
     def __init__(self, mu, nu, s=4, n_levels=1, eps=1.0, err_tol=1e-5, trunc=1e-15,
-                 max_iter=10000, n_threads=0, safeguard=1):
+                 max_iter=50000, n_threads=0, safeguard=1):
         mu = np.ascontiguousarray(mu, dtype=np.float64)
         nu = np.ascontiguousarray(nu, dtype=np.float64)
         assert mu.shape == nu.shape and mu.ndim == 2
@@ -94,9 +94,9 @@ class Oracle:
         self._h = h
 
     def close(self):
-        if getattr(self, "_h", None):
-            lib().ddo_free(self._h)
-            self._h = None
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.ddo_free(self._h)
+        self._h = None
 
     def __del__(self):
         self.close()

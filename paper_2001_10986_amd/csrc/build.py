@@ -13,6 +13,17 @@ FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable", "-Wno-unused-but-set-variable"]
 
 
+def _torch_lib_dir():
+    """Directory of the HIP runtime that PyTorch loads; the library links the
+    same one so that device pointers and streams are shared with torch."""
+    import importlib.util
+    spec = importlib.util.find_spec("torch")
+    if spec is None or not spec.origin:
+        return None
+    d = os.path.join(os.path.dirname(spec.origin), "lib")
+    return d if os.path.exists(os.path.join(d, "libamdhip64.so")) else None
+
+
 def build(verbose: bool = False, jobs: int = 2) -> str:
     objs = []
     procs = []
@@ -27,7 +38,13 @@ def build(verbose: bool = False, jobs: int = 2) -> str:
     for p in procs:
         if p.wait() != 0:
             raise RuntimeError("hipcc failed")
-    cmd = [HIPCC, "-shared", "--offload-arch=gfx950", "-o", LIB + ".tmp", *objs]
+    tl = _torch_lib_dir()
+    if tl:
+        # plain link against the runtime torch loads (one HIP runtime per process)
+        cmd = ["g++", "-shared", "-o", LIB + ".tmp", *objs, f"-L{tl}", "-l:libamdhip64.so",
+               f"-Wl,-rpath,{tl}", "-Wl,--disable-new-dtags"]
+    else:
+        cmd = [HIPCC, "-shared", "--offload-arch=gfx950", "-o", LIB + ".tmp", *objs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

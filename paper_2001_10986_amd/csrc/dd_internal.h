@@ -51,11 +51,14 @@ struct IterStatsDev {
   double cost, obj, err;
   long long loops_total, evals, nnz;
   int loops_max, n_failed, n_safeguard, n_cells;
+  long long evals_bin[kNBins];
+  int cells_bin[kNBins];
 };
 
 // Kernel launchers (all asynchronous on `st`).
-void launch_sweep(const HalfParams& p, hipStream_t st, int grid_cap);
-void launch_stats(const HalfParams& p, IterStatsDev* out, hipStream_t st);
+// ev: nullptr, or 11 events recorded before the first and after every launch
+void launch_sweep(const HalfParams& p, hipStream_t st, int grid_cap, hipEvent_t* ev);
+void launch_stats(const HalfParams& p, IterStatsDev* out, hipStream_t st, hipEvent_t ev_after);
 size_t sweep_max_static_lds();
 
 void launch_validate(const double* mu, const double* nu, int H, int W, double* out4,

@@ -1125,6 +1125,21 @@ __global__ __launch_bounds__(1024) void k_stats(HalfParams p, IterStatsDev* out)
     ns += (p.r_status[i] & 4) != 0;
   }
   for (int b = threadIdx.x; b < p.n_basic; b += 1024) nnz += p.row_len[b];
+  long long eb[kNBins];
+  int cb[kNBins];
+#pragma unroll
+  for (int k = 0; k < kNBins; k++) {
+    eb[k] = 0;
+    cb[k] = 0;
+  }
+  for (int i = threadIdx.x; i < p.n_cells; i += 1024) {
+    const int b = bin_of(p.cell_U[i]);
+#pragma unroll
+    for (int k = 0; k < kNBins; k++) {
+      eb[k] += b == k ? p.r_evals[i] : 0;
+      cb[k] += b == k;
+    }
+  }
   c = block_sum_d(c, shd);
   o = block_sum_d(o, shd);
   e = block_sum_d(e, shd);
@@ -1139,6 +1154,14 @@ __global__ __launch_bounds__(1024) void k_stats(HalfParams p, IterStatsDev* out)
   nf = (int)tot;
   block_excl_scan((long long)ns, shl, &tot);
   ns = (int)tot;
+#pragma unroll
+  for (int k = 0; k < kNBins; k++) {
+    long long t2;
+    block_excl_scan(eb[k], shl, &t2);
+    eb[k] = t2;
+    block_excl_scan((long long)cb[k], shl, &t2);
+    cb[k] = (int)t2;
+  }
   int lm = wave_max(lmax);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) shl[threadIdx.x >> 6] = lm;
@@ -1156,23 +1179,40 @@ __global__ __launch_bounds__(1024) void k_stats(HalfParams p, IterStatsDev* out)
     out->n_failed = nf;
     out->n_safeguard = ns;
     out->n_cells = p.n_cells;
+    for (int k = 0; k < kNBins; k++) {
+      out->evals_bin[k] = eb[k];
+      out->cells_bin[k] = cb[k];
+    }
   }
 }
 
 // ------------------------------------------------------------ launchers
 
-void launch_sweep(const HalfParams& p, hipStream_t st, int grid_cap) {
+void launch_sweep(const HalfParams& p, hipStream_t st, int grid_cap, hipEvent_t* ev) {
+  int e = 0;
+  auto mark = [&]() {
+    if (ev) hipEventRecord(ev[e++], st);
+  };
+  mark();
   hipLaunchKernelGGL(k_scan_T, dim3(1), dim3(1024), 0, st, p);
-  const int gu = p.n_cells < grid_cap ? p.n_cells : grid_cap;
-  hipLaunchKernelGGL(k_union, dim3(gu), dim3(kUnionThreads), 0, st, p);
+  mark();
+  const int g = p.n_cells < grid_cap ? p.n_cells : grid_cap;
+  hipLaunchKernelGGL(k_union, dim3(g), dim3(kUnionThreads), 0, st, p);
+  mark();
   hipLaunchKernelGGL(k_scan_out, dim3(1), dim3(1024), 0, st, p);
-  const int g = gu;
+  mark();
   hipLaunchKernelGGL(k_solve_reg<1>, dim3(g), dim3(64), 0, st, p, 0);
+  mark();
   hipLaunchKernelGGL(k_solve_reg<2>, dim3(g), dim3(128), 0, st, p, 1);
+  mark();
   hipLaunchKernelGGL(k_solve_reg<4>, dim3(g), dim3(256), 0, st, p, 2);
+  mark();
   hipLaunchKernelGGL(k_solve_reg<8>, dim3(g), dim3(512), 0, st, p, 3);
+  mark();
   hipLaunchKernelGGL(k_solve_reg<16>, dim3(g), dim3(1024), 0, st, p, 4);
+  mark();
   hipLaunchKernelGGL(k_solve_big, dim3(g), dim3(kBigThreads), 0, st, p, 5);
+  mark();
 }
 
 size_t sweep_max_static_lds() {
@@ -1187,8 +1227,9 @@ size_t sweep_max_static_lds() {
   return mx;
 }
 
-void launch_stats(const HalfParams& p, IterStatsDev* out, hipStream_t st) {
+void launch_stats(const HalfParams& p, IterStatsDev* out, hipStream_t st, hipEvent_t ev_after) {
   hipLaunchKernelGGL(k_stats, dim3(1), dim3(1024), 0, st, p, out);
+  if (ev_after) hipEventRecord(ev_after, st);
 }
 
 // ------------------------------------------------------------ setup kernels

@@ -88,6 +88,7 @@ struct dd_ctx {
   int64_t px_cap = 0;
   dd_iter_stats last{};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t kev[DD_N_KERNELS + 1] = {};
   int grid_cap = 2048;
 };
 
@@ -243,9 +244,10 @@ extern "C" void dd_options_default(dd_options* o) {
   if (!o) return;
   o->err_tol = 1e-5;
   o->trunc_threshold = 1e-15;
-  o->max_sinkhorn_iter = 10000;
+  o->max_sinkhorn_iter = 50000;
   o->safeguard = 1;
   o->inputs_on_device = 0;
+  o->timing = 0;
   o->stream = nullptr;
 }
 
@@ -283,6 +285,8 @@ extern "C" void dd_free(dd_ctx* c) {
   if (c->hscal) hipHostFree(c->hscal);
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
+  for (auto& e : c->kev)
+    if (e) hipEventDestroy(e);
   delete c;
 }
 
@@ -402,6 +406,8 @@ extern "C" dd_status dd_init(const double* mu, const double* nu, int H, int W, i
     return bail(fail(c, DD_ENOMEM, "hipMalloc failed"));
   hipEventCreate(&c->ev0);
   hipEventCreate(&c->ev1);
+  if (c->opt.timing)
+    for (auto& e : c->kev) hipEventCreate(&e);
   // validation of the finest images
   {
     const Level& l = c->L[nlev - 1];
@@ -416,16 +422,17 @@ extern "C" dd_status dd_init(const double* mu, const double* nu, int H, int W, i
       return bail(fail(c, DD_EINVAL, "masses must sum to 1 (got %.17g, %.17g)", sm, sn));
     if (!(mn > 0)) return bail(fail(c, DD_EINVAL, "a basic cell of mu has zero mass"));
   }
-  hipDeviceProp_t prop;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+  int dev = 0, n_cu = 0, lds_max = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
     return bail(fail(c, DD_EHIP, "no HIP device"));
-  if (prop.multiProcessorCount > 0) c->grid_cap = prop.multiProcessorCount * 8;
+  if (n_cu > 0) c->grid_cap = n_cu * 8;
   {
     const size_t need = ddk::sweep_max_static_lds();
-    if (need == 0 || need > prop.sharedMemPerBlock)
-      return bail(fail(c, DD_EHIP, "kernels need %zu bytes of LDS per workgroup, device allows %zu",
-                       need, (size_t)prop.sharedMemPerBlock));
+    if (need == 0 || need > (size_t)lds_max)
+      return bail(fail(c, DD_EHIP, "kernels need %zu bytes of LDS per workgroup, device allows %d",
+                       need, lds_max));
   }
   c->lev = 0;
   dd_status st = init_level0(c);
@@ -496,9 +503,10 @@ extern "C" dd_status dd_half_iterate(dd_ctx* c, int part, dd_iter_stats* out) {
   HalfParams p = make_params(c, part);
   HIPCHK(c, hipMemsetAsync(c->misc, 0, sizeof(long long) * 8, c->st));
   HIPCHK(c, hipEventRecord(c->ev0, c->st));
-  ddk::launch_sweep(p, c->st, c->grid_cap);
+  hipEvent_t* kev = c->opt.timing ? c->kev : nullptr;
+  ddk::launch_sweep(p, c->st, c->grid_cap, kev);
   HIPCHK(c, hipGetLastError());
-  ddk::launch_stats(p, c->dstats, c->st);
+  ddk::launch_stats(p, c->dstats, c->st, kev ? kev[DD_N_KERNELS] : nullptr);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(c->ev1, c->st));
   HIPCHK(c, hipMemcpyAsync(c->hstats, c->dstats, sizeof(IterStatsDev), hipMemcpyDeviceToHost, c->st));
@@ -522,6 +530,16 @@ extern "C" dd_status dd_half_iterate(dd_ctx* c, int part, dd_iter_stats* out) {
   r.obj = d.obj;
   r.err_x = d.err;
   r.ms = ms;
+  for (int k = 0; k < DD_N_BINS; k++) {
+    r.cells_bin[k] = d.cells_bin[k];
+    r.evals_bin[k] = d.evals_bin[k];
+  }
+  if (kev)
+    for (int k = 0; k < DD_N_KERNELS; k++) {
+      float t = 0;
+      hipEventElapsedTime(&t, kev[k], kev[k + 1]);
+      r.ms_kernel[k] = t;
+    }
   c->nnz = d.nnz;
   c->last = r;
   c->last_part = part;
@@ -717,6 +735,11 @@ extern "C" dd_status dd_run_schedule(dd_ctx* c, dd_run_stats* out) {
       rs.n_failed += it.n_failed;
       rs.n_safeguard += it.n_safeguard;
       rs.nnz_max = std::max(rs.nnz_max, it.nnz);
+      for (int b = 0; b < DD_N_KERNELS; b++) rs.ms_kernel[b] += it.ms_kernel[b];
+      for (int b = 0; b < DD_N_BINS; b++) {
+        rs.launches_bin[b] += it.cells_bin[b] > 0;
+        rs.evals_bin[b] += it.evals_bin[b];
+      }
     }
   }
   HIPCHK(c, hipStreamSynchronize(c->st));

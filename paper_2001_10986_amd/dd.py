@@ -28,26 +28,37 @@ class Stage(C.Structure):
 class Options(C.Structure):
     _fields_ = [("err_tol", C.c_double), ("trunc_threshold", C.c_double),
                 ("max_sinkhorn_iter", C.c_int), ("safeguard", C.c_int),
-                ("inputs_on_device", C.c_int), ("stream", C.c_void_p)]
+                ("inputs_on_device", C.c_int), ("timing", C.c_int), ("stream", C.c_void_p)]
+
+
+N_KERNELS, N_BINS = 10, 6
+KERNEL_NAMES = ["scan_cells", "union", "scan_out_bins", "solve_reg_1w", "solve_reg_2w",
+                "solve_reg_4w", "solve_reg_8w", "solve_reg_16w", "solve_big", "stats"]
 
 
 class IterStats(C.Structure):
     _fields_ = [("n_cells", C.c_int), ("loops_max", C.c_int), ("loops_total", C.c_int64),
                 ("n_failed", C.c_int), ("n_safeguard", C.c_int), ("nnz", C.c_int64),
                 ("entry_evals", C.c_int64), ("cost", C.c_double), ("obj", C.c_double),
-                ("err_x", C.c_double), ("ms", C.c_double)]
+                ("err_x", C.c_double), ("ms", C.c_double),
+                ("ms_kernel", C.c_double * 10), ("cells_bin", C.c_int * 6),
+                ("evals_bin", C.c_int64 * 6)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: (list(getattr(self, k)) if k in ("ms_kernel", "cells_bin", "evals_bin")
+                    else getattr(self, k)) for k, _ in self._fields_}
 
 
 class RunStats(C.Structure):
     _fields_ = [("n_half_iters", C.c_int), ("n_cell_solves", C.c_int),
                 ("loops_total", C.c_int64), ("entry_evals", C.c_int64), ("n_failed", C.c_int),
-                ("n_safeguard", C.c_int), ("nnz_max", C.c_int64), ("ms_total", C.c_double)]
+                ("n_safeguard", C.c_int), ("nnz_max", C.c_int64), ("ms_total", C.c_double),
+                ("ms_kernel", C.c_double * 10), ("launches_bin", C.c_int * 6),
+                ("evals_bin", C.c_int64 * 6)]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        return {k: (list(getattr(self, k)) if k in ("ms_kernel", "launches_bin", "evals_bin")
+                    else getattr(self, k)) for k, _ in self._fields_}
 
 
 class CostReport(C.Structure):
@@ -67,6 +78,14 @@ class PlanView(C.Structure):
 
 
 def _load():
+    # PyTorch ships its own HIP runtime.  Loading it first makes the library's
+    # dependency on libamdhip64 resolve to that same runtime, so device
+    # pointers and streams are shared with torch and only one runtime
+    # initialises the GPU in the process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is missing: build it with "
                           "`python paper_2001_10986_amd/csrc/build.py`")
@@ -115,11 +134,12 @@ class Problem:
     """
 
     def __init__(self, mu, nu, schedule, s=4, n_levels=1, err_tol=1e-5, trunc=1e-15,
-                 max_iter=10000, safeguard=1, stream=None):
+                 max_iter=50000, safeguard=1, stream=None, timing=False):
         opt = Options()
         lib.dd_options_default(C.byref(opt))
         opt.err_tol, opt.trunc_threshold = err_tol, trunc
         opt.max_sinkhorn_iter, opt.safeguard = max_iter, safeguard
+        opt.timing = 1 if timing else 0
         on_dev = hasattr(mu, "data_ptr") and getattr(mu, "is_cuda", False)
         if on_dev:
             import torch
@@ -155,9 +175,9 @@ class Problem:
         return rc
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and lib is not None:
             lib.dd_free(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         self.close()

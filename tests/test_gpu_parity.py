@@ -1,0 +1,179 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle on the GPU.
+
+Tolerances: the oracle runs the same iteration in FP64 (log-domain Sinkhorn,
+checked every loop); the GPU forms exponents in FP64 and runs the scaling
+loop in FP32.  Both stop a cell when its L1 X-marginal error drops below
+Err*|mu_J| (Err = 1e-5), so the two may stop one loop apart; the end-to-end
+bar is the one of the method: W2^2 within 1e-5 relative, marginals within
+1e-5 in L1.  Per half-iteration the basic-cell marginals agree to ~1e-5 of
+the cell mass in the worst case and typically 1e-9.
+"""
+import numpy as np
+import pytest
+
+from paper_2001_10986_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dd():
+    from paper_2001_10986_amd import dd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def ddo():
+    from oracle import ddo as m
+    return m
+
+
+def _valid_state(g):
+    e = g.export()
+    info = g.level_info()
+    rp, col, val = e["row_ptr"], e["col"], e["val"]
+    assert rp[0] == 0 and np.all(np.diff(rp) >= 0) and len(col) == rp[-1]
+    if len(col):
+        assert col.min() >= 0 and col.max() < info["H"] * info["W"]
+        assert np.all(np.isfinite(val)) and val.min() > 0
+    for b in range(info["n_basic"]):
+        assert np.all(np.diff(col[rp[b]:rp[b + 1]]) > 0)
+    return e
+
+
+def _row_masses(e, nb):
+    rp = e["row_ptr"]
+    return np.array([e["val"][rp[b]:rp[b + 1]].sum() for b in range(nb)])
+
+
+@pytest.mark.parametrize("N", [16, 32, 64])
+def test_half_iterations_match_oracle(dd, ddo, N):
+    # 16: 4-wave bin; 32: 16- and 8-wave bins; 64: the log-domain big-cell solver (U = 4096)
+    mu, nu = datagen.small_pair(N, 3, seed=5)
+    eps = 4.0 / N ** 2
+    g = dd.Problem(mu, nu, [(0, eps, 4)], s=4, n_levels=1)
+    o = ddo.Oracle(mu, nu, s=4, n_levels=1, eps=eps)
+    info = g.level_info()
+    for ell in range(4 if N < 64 else 2):
+        sg = g.half_iterate(ell % 2)
+        so = o.half_iterate(ell % 2)
+        eg = _valid_state(g)
+        assert sg["n_failed"] == 0
+        assert abs(sg["cost"] - so["cost"]) <= 1e-7 * so["cost"]
+        assert abs(sg["obj"] - so["obj"]) <= 1e-6 * abs(so["obj"])
+        assert sg["err_x"] <= 1e-5 and abs(sg["err_x"] - so["err_x"]) < 2e-6
+        assert abs(sg["loops_total"] - so["loops_total"]) <= 0.02 * so["loops_total"] + 2
+        bg, bo = g.basic_marginals(), o.basic_marginals()
+        assert np.abs(bg - bo).max() < 1e-6 * bg.sum(axis=1).max()
+        # |nu_i| = |mu_i| after balancing, up to the truncated mass (< 1e-15 per entry)
+        m_i = np.array([mu.reshape(info["H"] // 4, 4, info["W"] // 4, 4)[r, :, c, :].sum()
+                        for r in range(info["H"] // 4) for c in range(info["W"] // 4)])
+        rm_g = _row_masses(eg, info["n_basic"])
+        rm_o = _row_masses(o.export(), info["n_basic"])
+        assert np.abs(rm_g - m_i).max() < 1e-15 * N * N + 1e-14
+        assert np.abs(rm_g - rm_o).max() < 1e-13
+        key = "alpha_a" if ell % 2 == 0 else "alpha_b"
+        da = (eg[key] - o.export()[key]) / eps
+        # potentials agree up to one constant per cell; compare centred per block
+        assert np.abs(da - da.mean()).max() < 5e-3
+
+
+def test_config1_end_to_end(dd, ddo):
+    mu, nu, cfg = datagen.config1_pair()
+    g = dd.Problem(mu, nu, cfg["stages"], s=4, n_levels=1)
+    rs = g.run_schedule()
+    o = ddo.Oracle(mu, nu, s=4, n_levels=1, eps=cfg["stages"][0][1])
+    o.run_schedule(cfg["stages"])
+    cg, co = g.cost(), o.cost()
+    assert rs["n_half_iters"] == 40 and rs["n_failed"] == 0
+    assert abs(cg["cost"] - co["cost"]) <= 1e-5 * co["cost"]
+    assert cg["err_x"] <= 1e-5 and cg["err_y"] <= 1e-5
+    # truncation removes < 1e-15 per dropped entry and is not given back (drift);
+    # both sides drop the same entries
+    assert cg["mass_drift"] <= 2 * co["mass_drift"] + 1e-13 and co["mass_drift"] < 1e-9
+
+
+def test_multilevel_matches_oracle(dd, ddo):
+    # 64x64, levels 32 -> 64, eps 1 -> (1/64)^2: refinement and the eps schedule
+    mu, nu = datagen.small_pair(64, 4, seed=17)
+    stages = datagen.eps_schedule(64, 2)
+    g = dd.Problem(mu, nu, stages, s=4, n_levels=2)
+    g.run_schedule()
+    o = ddo.Oracle(mu, nu, s=4, n_levels=2, eps=stages[0][1])
+    o.run_schedule(stages)
+    cg, co = g.cost(), o.cost()
+    assert cg["level"] == co["level"] == 1
+    assert abs(cg["cost"] - co["cost"]) <= 1e-5 * co["cost"]
+    assert cg["err_x"] <= 1e-5 and cg["err_y"] <= 1e-5 and co["err_x"] <= 1e-5
+
+
+def test_refine_matches_oracle_from_same_state(dd, ddo):
+    mu, nu = datagen.small_pair(64, 4, seed=23)
+    eps = 2.0 ** -9
+    g = dd.Problem(mu, nu, [(0, eps, 4)], s=4, n_levels=2)
+    for ell in range(4):
+        g.half_iterate(ell % 2)
+    e = g.export()
+    o = ddo.Oracle(mu, nu, s=4, n_levels=2, eps=eps)
+    o.import_state(0, eps, e["row_ptr"], e["col"], e["val"], e["alpha_a"], e["alpha_b"])
+    g.refine()
+    o.refine()
+    eg, eo = _valid_state(g), o.export()
+    assert np.array_equal(eg["row_ptr"], eo["row_ptr"])
+    assert np.array_equal(eg["col"], eo["col"])
+    assert np.abs(eg["val"] - eo["val"]).max() <= 1e-15 * eo["val"].max() * 4
+    assert np.abs(eg["alpha_a"] - eo["alpha_a"]).max() < 1e-9 * np.abs(eo["alpha_a"]).max() + 1e-12
+    assert np.array_equal(eg["alpha_a"], eg["alpha_b"])
+
+
+def test_iteration_cap_and_safeguard(dd, ddo):
+    mu, nu, cfg = datagen.config1_pair()
+    eps = cfg["stages"][0][1]
+    g = dd.Problem(mu, nu, cfg["stages"], s=4, n_levels=1, max_iter=1)
+    st = g.half_iterate(0)
+    o = ddo.Oracle(mu, nu, s=4, n_levels=1, eps=eps, max_iter=1)
+    so = o.half_iterate(0)
+    assert st["status"] == dd.DD_ENOTCONV and st["n_failed"] == so["n_failed"] > 0
+    assert st["n_safeguard"] == so["n_safeguard"]
+    res = g.cell_results()
+    assert np.all((res["status"] & 4) != 0)
+    _valid_state(g)
+
+
+def test_invalid_inputs_rejected(dd):
+    mu, nu = datagen.small_pair(32, 3, seed=5)
+    with pytest.raises(dd.DDError):
+        dd.Problem(mu, nu * 2, [(0, 0.01, 2)])
+    with pytest.raises(dd.DDError):
+        dd.Problem(mu[:, :28] / mu[:, :28].sum(), nu[:, :28] / nu[:, :28].sum(), [(0, 0.01, 2)])
+    with pytest.raises(dd.DDError):
+        dd.Problem(mu, nu, [(0, -1.0, 2)])
+    bad = mu.copy()
+    bad[:4, :4] = 0
+    with pytest.raises(dd.DDError):
+        dd.Problem(bad / bad.sum(), nu, [(0, 0.01, 2)])
+
+
+def test_deterministic(dd):
+    mu, nu, cfg = datagen.config1_pair()
+    outs = []
+    for _ in range(2):
+        g = dd.Problem(mu, nu, cfg["stages"], s=4, n_levels=1)
+        for ell in range(6):
+            g.half_iterate(ell % 2)
+        outs.append(g.export())
+    for k in ("row_ptr", "col", "val", "alpha_a", "alpha_b"):
+        assert np.array_equal(outs[0][k], outs[1][k])
+
+
+def test_device_inputs_match_host_inputs(dd):
+    torch = pytest.importorskip("torch")
+    mu, nu, cfg = datagen.config1_pair()
+    g1 = dd.Problem(mu, nu, cfg["stages"], s=4, n_levels=1)
+    g2 = dd.Problem(torch.from_numpy(mu).cuda(), torch.from_numpy(nu).cuda(), cfg["stages"], s=4,
+                    n_levels=1)
+    for ell in range(3):
+        g1.half_iterate(ell % 2)
+        g2.half_iterate(ell % 2)
+    e1, e2 = g1.export(), g2.export()
+    assert np.array_equal(e1["val"], e2["val"]) and np.array_equal(e1["alpha_a"], e2["alpha_a"])
