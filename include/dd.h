@@ -74,6 +74,8 @@ typedef struct {
   double trunc_threshold;  /* truncation threshold of the basic marginals (Sec. 6.1 (ii)); default 1e-15 */
   int max_sinkhorn_iter;   /* Sinkhorn loop cap per cell solve; default 50000 */
   int safeguard;           /* 1: re-solve failed cells at 2*eps, then eps (Sec. 7.4); default 1 */
+  int accel;               /* 1: Chebyshev-accelerated X-iteration of the cell Sinkhorn (same
+                              stopping test, same fixed point), 0: plain Sinkhorn; default 1 */
   int inputs_on_device;    /* 1: mu, nu passed to dd_init are device pointers; default 0 */
   int timing;              /* 1: record HIP events around every kernel of a sweep; default 0 */
   void* stream;            /* hipStream_t for all work of the context; default NULL */

@@ -113,6 +113,70 @@ static void cell_pixel(const lvl_t* l, int s, const cell_t* C, int k, int* r, in
 
 /* --------------------------------------------------------------- Sinkhorn */
 
+/* Chebyshev acceleration of the X-iteration (optional).  One Sinkhorn loop
+ * F -> X(Y(F)) is a fixed-point map whose Jacobian at the solution has real
+ * eigenvalues in [0, rho) (it is similar to a symmetric positive
+ * semi-definite matrix), so the Chebyshev semi-iterative method for the
+ * interval [0, rho] (Golub & Varga 1961) converges at the rate
+ * (1 - sqrt(1 - rho)) / (1 + sqrt(1 - rho)) instead of rho.  The Y-iteration
+ * stays exact, so the stopping test (X-marginal error after a Y-iteration)
+ * and the exact Y-marginal at termination are those of Sec. 6.2.  The same
+ * rule (constants and decisions) runs in the GPU solvers. */
+typedef struct {
+  double rho, omega, hist[17];
+  int k, kstart, pstart, att;
+} cheb_t;
+
+static void cheb_reset(cheb_t* c) {
+  memset(c, 0, sizeof(*c));
+  c->rho = -1;
+}
+
+/* decide the update after loop `it` (1-based) with error err; returns 0 for
+ * a plain step F <- Fh, 1 for a Chebyshev step with weights (*a, *b, *d):
+ * F <- a F + b Fh + d Fprev.  Plain loops estimate rho from the error decay
+ * over the last 8 loops (at least 16 plain loops after a (re)start); a
+ * Chebyshev run that decays slower than the square root of its promised
+ * rate over a 16-loop window is abandoned for plain loops; at most four
+ * runs per solve, rho <= 0.9999, so the solver always ends as plain
+ * Sinkhorn if acceleration does not pay. */
+static int cheb_next(cheb_t* c, int it, double err, double* a, double* b, double* d) {
+  c->hist[it % 17] = err;
+  if (c->rho < 0) {
+    if (it - c->pstart >= 16 && c->att < 4) {
+      double r = pow(err / c->hist[(it - 8) % 17], 1.0 / 8);
+      if (r > 0.8) {
+        c->rho = r < 0.9999 ? r : 0.9999;
+        c->k = 0;
+        c->kstart = it;
+        c->att++;
+      }
+    }
+    return 0;
+  }
+  if (it - c->kstart >= 16 && (it - c->kstart) % 16 == 0) {
+    double robs = pow(err / c->hist[(it - 16) % 17], 1.0 / 16);
+    double sq = sqrt(1 - c->rho), cexp = (1 - sq) / (1 + sq);
+    if (robs > sqrt(cexp)) {
+      c->rho = -1;
+      c->pstart = it;
+      return 0;
+    }
+  }
+  double sigma = c->rho / (2 - c->rho), gamma = 2 / (2 - c->rho);
+  if (c->k == 0)
+    c->omega = 1;
+  else if (c->k == 1)
+    c->omega = 1 / (1 - sigma * sigma / 2);
+  else
+    c->omega = 1 / (1 - sigma * sigma * c->omega / 4);
+  c->k++;
+  *a = c->omega * (1 - gamma);
+  *b = c->omega * gamma;
+  *d = 1 - c->omega;
+  return 1;
+}
+
 /* Log-domain Sinkhorn of Remark "Sinkhorn algorithm", in the dual variables
  * F = f/eps, G = g/eps, with plan pi(x,y) = exp(F(x)+G(y)-C(x,y)) mu(x) nu(y)
  * and C = lam*|x-y|^2 (integer pixel offsets).  Warm start F, first a
@@ -122,17 +186,22 @@ static void cell_pixel(const lvl_t* l, int s, const cell_t* C, int k, int* r, in
  * value went non-finite. */
 static int sinkhorn_log(int nx, const int* xr, const int* xc, const double* mu,
                         int ny, const int* yr, const int* yc, const double* nu,
-                        double lam, double tol, int maxit, double* F, double* G,
+                        double lam, double tol, int maxit, int accel, double* F, double* G,
                         double* Fh, int* loops, double* err_out) {
   double* lmu = (double*)malloc(sizeof(double) * (size_t)nx);
   double* lnu = (double*)malloc(sizeof(double) * (size_t)ny);
-  if (!lmu || !lnu) {
+  double* Fp = (double*)malloc(sizeof(double) * (size_t)nx);
+  if (!lmu || !lnu || !Fp) {
     free(lmu);
     free(lnu);
+    free(Fp);
     return 2;
   }
   for (int i = 0; i < nx; i++) lmu[i] = mu[i] > 0 ? log(mu[i]) : -INFINITY;
   for (int j = 0; j < ny; j++) lnu[j] = nu[j] > 0 ? log(nu[j]) : -INFINITY;
+  for (int i = 0; i < nx; i++) Fp[i] = F[i];
+  cheb_t ch;
+  cheb_reset(&ch);
   int rc = 1;
   double err = INFINITY;
   int it;
@@ -179,15 +248,22 @@ static int sinkhorn_log(int nx, const int* xr, const int* xc, const double* mu,
       break;
     }
     if (it == maxit) break;
-    /* X-iteration */
+    /* X-iteration (plain, or the Chebyshev-accelerated one) */
+    double a = 0, b = 1, d = 0;
+    int acc = accel ? cheb_next(&ch, it, err, &a, &b, &d) : 0;
     for (int i = 0; i < nx; i++)
-      if (mu[i] > 0) F[i] = Fh[i];
+      if (mu[i] > 0) {
+        double fn = acc ? a * F[i] + b * Fh[i] + d * Fp[i] : Fh[i];
+        Fp[i] = F[i];
+        F[i] = fn;
+      }
   }
   if (it > maxit) it = maxit;
   *loops = it;
   *err_out = err;
   free(lmu);
   free(lnu);
+  free(Fp);
   return rc;
 }
 
@@ -198,7 +274,7 @@ int ddo_cell_solve(int nx, const int* xr, const int* xc, const double* mu, int n
   if (nx <= 0 || ny <= 0 || !(lam > 0) || max_iter < 1) return -1;
   double* Fh = (double*)malloc(sizeof(double) * (size_t)nx);
   if (!Fh) return -2;
-  int rc = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nu, lam, tol, max_iter, F, G, Fh,
+  int rc = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nu, lam, tol, max_iter, 0, F, G, Fh,
                         loops, err);
   free(Fh);
   if (plan) {
@@ -339,8 +415,8 @@ static void solve_cell(const ddo_ctx* c, int part, const cell_t* C, cell_out_t* 
   }
   double tol = c->opt.err_tol * muJ, err = 0;
   int loops = 0;
-  int rc = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nuJ, lam, tol, c->opt.max_iter, F, G,
-                        Fh, &loops, &err);
+  int rc = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nuJ, lam, tol, c->opt.max_iter,
+                        c->opt.accel, F, G, Fh, &loops, &err);
   o->loops = loops;
   if (rc != 0 && c->opt.safeguard) {
     /* Safeguard of Sec. 7.4: solve the failing cell at a temporarily larger
@@ -349,11 +425,11 @@ static void solve_cell(const ddo_ctx* c, int part, const cell_t* C, cell_out_t* 
     int l2 = 0, l3 = 0;
     for (int k = 0; k < nx; k++) F[k] = F0[k] * 0.5;
     int r2 = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nuJ, lam * 0.5, tol, c->opt.max_iter,
-                          F, G, Fh, &l2, &err);
+                          c->opt.accel, F, G, Fh, &l2, &err);
     if (r2 != 2) {
       for (int k = 0; k < nx; k++) F[k] *= 2.0;
-      rc = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nuJ, lam, tol, c->opt.max_iter, F, G, Fh,
-                        &l3, &err);
+      rc = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nuJ, lam, tol, c->opt.max_iter,
+                        c->opt.accel, F, G, Fh, &l3, &err);
     } else {
       rc = 2;
     }

@@ -40,6 +40,7 @@ typedef struct {
   int max_iter;      /* Sinkhorn loop cap per cell solve */
   int n_threads;     /* OpenMP threads over cells (0 = runtime default) */
   int safeguard;     /* 1: re-solve failed cells at 2*eps, then eps (Sec. 7.4) */
+  int accel;         /* 1: Chebyshev-accelerated X-iteration, 0: plain Sinkhorn */
 } ddo_opts;
 
 typedef struct {

@@ -15,7 +15,7 @@ _lib = None
 
 class Opts(C.Structure):
     _fields_ = [("err_tol", C.c_double), ("trunc", C.c_double), ("max_iter", C.c_int),
-                ("n_threads", C.c_int), ("safeguard", C.c_int)]
+                ("n_threads", C.c_int), ("safeguard", C.c_int), ("accel", C.c_int)]
 
 
 class Stage(C.Structure):
@@ -79,13 +79,13 @@ class Oracle:
     """One problem instance of the oracle; mirrors the C-ABI of the GPU library."""
 
     def __init__(self, mu, nu, s=4, n_levels=1, eps=1.0, err_tol=1e-5, trunc=1e-15,
-                 max_iter=50000, n_threads=0, safeguard=1):
+                 max_iter=50000, n_threads=0, safeguard=1, accel=1):
         mu = np.ascontiguousarray(mu, dtype=np.float64)
         nu = np.ascontiguousarray(nu, dtype=np.float64)
         assert mu.shape == nu.shape and mu.ndim == 2
         self.H, self.W = mu.shape
         self.s, self.n_levels = s, n_levels
-        o = Opts(err_tol, trunc, max_iter, n_threads, safeguard)
+        o = Opts(err_tol, trunc, max_iter, n_threads, safeguard, accel)
         h = C.c_void_p()
         rc = lib().ddo_init(_dp(mu), _dp(nu), self.H, self.W, s, n_levels, eps, C.byref(o),
                             C.byref(h))

@@ -19,7 +19,7 @@ struct HalfParams {
   int part;
   double h, eps, lam;          // lam = h^2 / eps (cost in units of eps per pixel^2)
   double err_tol, trunc;
-  int max_iter, safeguard;
+  int max_iter, safeguard, accel;
   const double* mu;            // level mu, H*W
   const double* nu;            // level nu, H*W
   double* alpha;               // potentials f of partition `part`, H*W (in/out)

@@ -414,6 +414,69 @@ DEVI void balance_truncate_write(const HalfParams& p, const CellGeo& g, int64_t 
   __syncthreads();
 }
 
+// Chebyshev acceleration of the X-iteration (same rule as the oracle): one
+// Sinkhorn loop F -> X(Y(F)) has a Jacobian with real eigenvalues in [0, rho)
+// at the solution, so the Chebyshev semi-iteration for [0, rho] (Golub & Varga)
+// converges at (1 - sqrt(1-rho))/(1 + sqrt(1-rho)).  The Y-iteration and the
+// stopping test are untouched.  Every lane of the
+// calling wave runs the rule on the same values, so the decision is uniform.
+struct ChebState {
+  double rho, omega;
+  double hist[17];
+  int k, kstart, pstart, att;
+};
+
+DEVI void cheb_reset(ChebState& c) {
+  c.rho = -1.0;
+  c.omega = 1.0;
+  c.k = 0;
+  c.kstart = 0;
+  c.pstart = 0;
+  c.att = 0;
+}
+
+// returns true for an accelerated step F <- a F + b Fh + d Fprev.  Plain
+// loops estimate rho from the error decay over the last 8 loops (at least 16
+// plain loops after a (re)start); a Chebyshev run that decays slower than
+// the square root of its promised rate over 16 loops is abandoned for plain
+// loops; at most four runs per solve and rho <= 0.9999.
+DEVI bool cheb_next(ChebState& c, int it, double err, double* a, double* b, double* d) {
+  c.hist[it % 17] = err;
+  if (c.rho < 0) {
+    if (it - c.pstart >= 16 && c.att < 4) {
+      const double r = fast_exp2(fast_log2((float)(err / c.hist[(it - 8) % 17])) * 0.125f);
+      if (r > 0.8) {
+        c.rho = r < 0.9999 ? r : 0.9999;
+        c.k = 0;
+        c.kstart = it;
+        c.att++;
+      }
+    }
+    return false;
+  }
+  if (it - c.kstart >= 16 && (it - c.kstart) % 16 == 0) {
+    const double robs = fast_exp2(fast_log2((float)(err / c.hist[(it - 16) % 17])) * 0.0625f);
+    const double sq = sqrt(1 - c.rho), cexp = (1 - sq) / (1 + sq);
+    if (robs > sqrt(cexp)) {
+      c.rho = -1;
+      c.pstart = it;
+      return false;
+    }
+  }
+  const double sigma = c.rho / (2 - c.rho), gamma = 2 / (2 - c.rho);
+  if (c.k == 0)
+    c.omega = 1;
+  else if (c.k == 1)
+    c.omega = 1 / (1 - sigma * sigma / 2);
+  else
+    c.omega = 1 / (1 - sigma * sigma * c.omega / 4);
+  c.k++;
+  *a = c.omega * (1 - gamma);
+  *b = c.omega * gamma;
+  *d = 1 - c.omega;
+  return true;
+}
+
 // ------------------------------------------------------------ register solver
 
 // Stabilised Sinkhorn for cells whose union fits NW*64 support points.
@@ -442,6 +505,10 @@ struct RegShared {
   float S[NW * 64];
   float nuf[NW * 64];
   int yrc[NW * 64];           // support point (row << 16 | col)
+  float lup[64];              // log2 of the previous iterate's scaling (relative to F0)
+  ChebState cheb;
+  double ca, cb, cd;          // weights of the pending accelerated step
+  int cacc;
   double err;
   int flag;
   CellOutSh out;
@@ -533,13 +600,11 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
         lam = p.lam;
         if (tid < 64 && sh.mu[tid] > 0) sh.F0[tid] = (sh.F0[tid] + log((double)sh.u[tid])) * 2.0;
       }
+      if (tid < 64) sh.lup[tid] = 0.f;
+      if (tid == 0) cheb_reset(sh.cheb);
       __syncthreads();
-      bool rebuild = true;
-      int it = 0;
-      converged = false;
-      for (;;) {
-        if (rebuild) {
-          // ---- absorb: P = exp(Fmu - lam d2 - m(y)) with Fmu = F0 + log mu
+      // ---- absorb: P = exp(Fmu - lam d2 - m(y)) with Fmu = F0 + log mu
+      auto absorb = [&]() {
           if (tid < 64) {
             sh.Fmu[tid] = sh.mu[tid] > 0 ? sh.F0[tid] + log(sh.mu[tid]) : -INFINITY;
             sh.u[tid] = sh.mu[tid] > 0 ? 1.0f : 0.0f;
@@ -574,9 +639,12 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
             }
             if (xg == 0 && valid) mbuf[yi] = mloc;
           }
-          rebuild = false;
-          __syncthreads();
-        }
+        __syncthreads();
+      };
+      absorb();
+      int it = 0;
+      converged = false;
+      for (;;) {
         it++;
         // ---- Y-iteration: S(y) = sum_x P u, w = nu_J / S
         {
@@ -629,11 +697,34 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
           double e = mu > 0 ? fabs((double)u * (double)r - mu) : 0.0;
           e = wave_sum(e);
           sh.r[lane] = r;
-          const float un = mu > 0 ? (float)(mu / (double)r) : 0.f;
-          const bool bad = mu > 0 && !(un > 9.357623e-14f && un < 1.0686475e13f);
-          const unsigned long long anyb = __ballot(bad);
           const bool go_on = !(e <= tol) && it < p.max_iter && (e == e);
-          if (go_on && anyb == 0ull) sh.u[lane] = un;
+          // X-iteration: plain u = mu/r, or the accelerated combination of the
+          // log-scalings (relative to F0) of the current, plain-next and previous iterate
+          if (lane == 0) {
+            double a0 = 0, b0 = 1, d0 = 0;
+            const bool acc0 = go_on && p.accel && cheb_next(sh.cheb, it, e, &a0, &b0, &d0);
+            sh.cacc = acc0;
+            sh.ca = a0;
+            sh.cb = b0;
+            sh.cd = d0;
+          }
+          wave_sync();
+          const bool acc = sh.cacc;
+          const double a = sh.ca, b = sh.cb, d = sh.cd;
+          const float un = mu > 0 ? (float)(mu / (double)r) : 0.f;
+          const float lu = mu > 0 ? fast_log2(u) : 0.f;
+          float unew = un;
+          if (acc && mu > 0) {
+            const float ln = fast_log2(un);
+            unew = fast_exp2((float)(a * lu + b * ln + d * sh.lup[lane]));
+          }
+          const bool bad = mu > 0 && !(unew > 9.357623e-14f && unew < 1.0686475e13f &&
+                                       un > 0.f && un < 3.0e38f);
+          const unsigned long long anyb = __ballot(bad);
+          if (go_on && anyb == 0ull) {
+            sh.u[lane] = unew;
+            sh.lup[lane] = lu;
+          }
           if (lane == 0) {
             sh.err = e;
             sh.flag = go_on && anyb != 0ull;
@@ -706,10 +797,15 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
           if (tid < 64 && sh.mu[tid] > 0) {
             double s = 0;
             for (int w = 0; w < NW; w++) s += reinterpret_cast<double*>(sh.red[w])[64 + tid];
-            sh.F0[tid] = -(sh.mx[tid] + log(s));
+            const double Fh = -(sh.mx[tid] + log(s));
+            const double F = sh.F0[tid] + (double)fast_log2(sh.u[tid]) * kLn2;
+            const double Fp = sh.F0[tid] + (double)sh.lup[tid] * kLn2;
+            const double Fn = sh.cacc ? sh.ca * F + sh.cb * Fh + sh.cd * Fp : Fh;
+            sh.F0[tid] = Fn;
+            sh.lup[tid] = (float)((F - Fn) * kLog2e);
           }
-          rebuild = true;
           __syncthreads();
+          absorb();
         }
       }
       loops_all += it;
@@ -819,7 +915,10 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
 // exponentials, FP64 sums), potentials G(y) kept in the union scratch.
 constexpr int kBigThreads = 1024;
 struct BigShared {
-  double F[64], Fmu[64], mu[64], Fh[64], F0orig[64];
+  double F[64], Fmu[64], mu[64], Fh[64], F0orig[64], Fp[64];
+  ChebState cheb;
+  double ca, cb, cd;
+  int cacc;
   int xr[64], xc[64];
   double pm[16][64], ps[16][64];
   double err;
@@ -872,7 +971,11 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int bin
         if (tid < 64) sh.F[tid] *= 2.0;
       }
       __syncthreads();
-      if (tid < 64) sh.Fmu[tid] = sh.mu[tid] > 0 ? sh.F[tid] + log(sh.mu[tid]) : -INFINITY;
+      if (tid < 64) {
+        sh.Fmu[tid] = sh.mu[tid] > 0 ? sh.F[tid] + log(sh.mu[tid]) : -INFINITY;
+        sh.Fp[tid] = sh.F[tid];
+      }
+      if (tid == 0) cheb_reset(sh.cheb);
       __syncthreads();
       int it = 0;
       for (;;) {
@@ -929,7 +1032,15 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int bin
           const double mu = sh.mu[lane];
           double e = mu > 0 ? mu * fabs(exp(sh.F[lane] - Fh) - 1.0) : 0.0;
           e = wave_sum(e);
-          if (lane == 0) sh.err = e;
+          if (lane == 0) {
+            double a0 = 0, b0 = 1, d0 = 0;
+            const bool go_on = !(e <= tol) && it < p.max_iter && (e == e);
+            sh.cacc = go_on && p.accel && cheb_next(sh.cheb, it, e, &a0, &b0, &d0);
+            sh.ca = a0;
+            sh.cb = b0;
+            sh.cd = d0;
+            sh.err = e;
+          }
         }
         __syncthreads();
         const double err = sh.err;
@@ -939,8 +1050,11 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int bin
         }
         if (!(err == err) || it >= p.max_iter) break;
         if (tid < 64 && sh.mu[tid] > 0) {
-          sh.F[tid] = sh.Fh[tid];
-          sh.Fmu[tid] = sh.F[tid] + log(sh.mu[tid]);
+          const double F = sh.F[tid];
+          const double Fn = sh.cacc ? sh.ca * F + sh.cb * sh.Fh[tid] + sh.cd * sh.Fp[tid] : sh.Fh[tid];
+          sh.Fp[tid] = F;
+          sh.F[tid] = Fn;
+          sh.Fmu[tid] = Fn + log(sh.mu[tid]);
         }
         __syncthreads();
       }

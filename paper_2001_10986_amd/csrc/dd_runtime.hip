@@ -246,6 +246,7 @@ extern "C" void dd_options_default(dd_options* o) {
   o->trunc_threshold = 1e-15;
   o->max_sinkhorn_iter = 50000;
   o->safeguard = 1;
+  o->accel = 1;
   o->inputs_on_device = 0;
   o->timing = 0;
   o->stream = nullptr;
@@ -465,6 +466,7 @@ static HalfParams make_params(dd_ctx* c, int part) {
   p.trunc = c->opt.trunc_threshold;
   p.max_iter = c->opt.max_sinkhorn_iter;
   p.safeguard = c->opt.safeguard;
+  p.accel = c->opt.accel;
   p.mu = l.mu;
   p.nu = l.nu;
   p.alpha = c->alpha[part];

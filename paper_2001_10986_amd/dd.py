@@ -27,7 +27,7 @@ class Stage(C.Structure):
 
 class Options(C.Structure):
     _fields_ = [("err_tol", C.c_double), ("trunc_threshold", C.c_double),
-                ("max_sinkhorn_iter", C.c_int), ("safeguard", C.c_int),
+                ("max_sinkhorn_iter", C.c_int), ("safeguard", C.c_int), ("accel", C.c_int),
                 ("inputs_on_device", C.c_int), ("timing", C.c_int), ("stream", C.c_void_p)]
 
 
@@ -134,12 +134,13 @@ class Problem:
     """
 
     def __init__(self, mu, nu, schedule, s=4, n_levels=1, err_tol=1e-5, trunc=1e-15,
-                 max_iter=50000, safeguard=1, stream=None, timing=False):
+                 max_iter=50000, safeguard=1, stream=None, timing=False, accel=1):
         opt = Options()
         lib.dd_options_default(C.byref(opt))
         opt.err_tol, opt.trunc_threshold = err_tol, trunc
         opt.max_sinkhorn_iter, opt.safeguard = max_iter, safeguard
         opt.timing = 1 if timing else 0
+        opt.accel = int(accel)
         on_dev = hasattr(mu, "data_ptr") and getattr(mu, "is_cuda", False)
         if on_dev:
             import torch
