@@ -164,6 +164,7 @@ def main():
         "nnz_max": rs["nnz_max"],
         "cells_failed": rs["n_failed"],
         "cells_safeguard": rs["n_safeguard"],
+        "cells_newton": rs["n_newton"],
         "sinkhorn_loops": rs["loops_total"],
         "kernel_ms_per_step": kernel_ms,
         "learned_warm_start": None,

@@ -76,6 +76,9 @@ typedef struct {
   int safeguard;           /* 1: re-solve failed cells at 2*eps, then eps (Sec. 7.4); default 1 */
   int accel;               /* 1: Chebyshev-accelerated X-iteration of the cell Sinkhorn (same
                               stopping test, same fixed point), 0: plain Sinkhorn; default 1 */
+  int newton_after;        /* >0: a cell not converged after this many loops continues with
+                              damped Newton steps on its X potential (same stopping test, same
+                              fixed point); 0: never; default 128 */
   int inputs_on_device;    /* 1: mu, nu passed to dd_init are device pointers; default 0 */
   int timing;              /* 1: record HIP events around every kernel of a sweep; default 0 */
   void* stream;            /* hipStream_t for all work of the context; default NULL */
@@ -84,8 +87,9 @@ typedef struct {
 /* Kernels of one sweep, in launch order (indices of the ms_kernel arrays):
  * 0 cell sizes scan, 1 union, 2 output scan + size bins, 3..7 register
  * solvers for unions of <= 64, 128, 256, 512, 1024 points, 8 log-domain
- * solver for larger unions, 9 statistics. */
-#define DD_N_KERNELS 10
+ * solver for larger unions, 9 Newton solver for the cells the register
+ * solvers handed over, 10 statistics. */
+#define DD_N_KERNELS 11
 #define DD_N_BINS 6
 
 typedef struct {
@@ -94,6 +98,7 @@ typedef struct {
   int64_t loops_total;     /* sum of Sinkhorn loop counts */
   int n_failed;            /* cells still over the iteration cap after the safeguard */
   int n_safeguard;         /* cells that needed the safeguard */
+  int n_newton;            /* cells that switched to Newton steps */
   int64_t nnz;             /* entries of the basic Y-marginals after truncation */
   int64_t entry_evals;     /* sum over cells of loops * |X_J| * |Y_J| (kernel entries touched per loop) */
   double cost;             /* sum over cells of <c, pi_J> (plans before balancing) */
@@ -112,6 +117,7 @@ typedef struct {
   int64_t entry_evals;
   int n_failed;
   int n_safeguard;
+  int n_newton;
   int64_t nnz_max;
   double ms_total;         /* wall time of the whole schedule (ms) */
   double ms_kernel[DD_N_KERNELS];   /* summed per-kernel device time when timing is on */

@@ -177,6 +177,200 @@ static int cheb_next(cheb_t* c, int it, double err, double* a, double* b, double
   return 1;
 }
 
+/* Newton fallback for slowly converging cells (optional, after a fixed
+ * number of Sinkhorn loops).  The cell problem of Remark "Sinkhorn algorithm"
+ * is maximised over the X potential alone, the Y potential being eliminated
+ * by the exact Y-iteration (the semi-dual):
+ *
+ *   Phi(F) = sum_x mu(x) F(x) - sum_y nu(y) L_y(F),
+ *   L_y(F) = log sum_x exp(F(x) - C(x,y)) mu(x),
+ *
+ * with p_x(y) = exp(F(x) - C(x,y)) mu(x) / exp(L_y) the conditional plan, so
+ * that pi(x,y) = nu(y) p_x(y) is the plan after a Y-iteration.  Its gradient
+ * is mu - r (r the X-marginal of pi) and minus its Hessian is the graph
+ * Laplacian of the weights W(x,x') = sum_y nu(y) p_x(y) p_x'(y).  A slowly
+ * converging Sinkhorn iteration means that this graph is nearly disconnected
+ * (a tiny Laplacian eigenvalue); the Newton step resolves exactly that mode.
+ * The stopping test is the one of Sec. 6.2 (X-marginal error after a
+ * Y-iteration), so the fixed point and the exact Y-marginal at termination are
+ * those of the Sinkhorn solver.  The same rule (constants and decisions) runs
+ * in the GPU solvers. */
+#define NEWTON_MAX_STEPS 100
+#define NEWTON_STEP_CAP 8.0
+#define NEWTON_TRIALS 10
+#define NEWTON_ARMIJO 1e-4
+
+/* Solve Lap(W) d = b with d[n-1] = 0 (b must sum to zero) by Gaussian
+ * elimination in the subtraction-free form of Grassmann, Taksar and Heyman:
+ * the Schur complement of a graph Laplacian is the Laplacian of the weights
+ * W(i,j) + W(i,k) W(k,j) / d_k, and every pivot d_k is taken as the sum of the
+ * remaining off-diagonal weights of its row, so tiny eigenvalues keep their
+ * relative accuracy.  W (n*n, row-major, diagonal ignored) is overwritten. */
+static void gth_solve(int n, double* W, double* b, double* d, double* piv) {
+  for (int k = 0; k < n - 1; k++) {
+    double dk = 0;
+    for (int j = k + 1; j < n; j++) dk += W[(size_t)k * n + j];
+    piv[k] = dk;
+    if (!(dk > 0)) continue;
+    for (int i = k + 1; i < n; i++) {
+      double c = W[(size_t)i * n + k] / dk;
+      if (c == 0) continue;
+      b[i] += c * b[k];
+      for (int j = k + 1; j < n; j++)
+        if (j != i) W[(size_t)i * n + j] += c * W[(size_t)k * n + j];
+    }
+  }
+  d[n - 1] = 0;
+  for (int k = n - 2; k >= 0; k--) {
+    double s = b[k];
+    for (int j = k + 1; j < n; j++) s += W[(size_t)k * n + j] * d[j];
+    d[k] = piv[k] > 0 ? s / piv[k] : 0.0;
+  }
+}
+
+/* e^b - 1 - b >= 0 without cancellation for small |b| */
+static double phi1(double b) {
+  if (fabs(b) < 1e-3) return b * b * (0.5 + b * (1.0 / 6 + b * (1.0 / 24 + b / 120)));
+  return expm1(b) - b;
+}
+
+/* Newton iterations from F (loops it0+1 ...); same outputs as sinkhorn_log.
+ * Each iteration is one Y-iteration (a loop), the stopping test, then either
+ * a damped Newton step or, when the line search fails or after
+ * NEWTON_MAX_STEPS steps, a plain X-iteration.
+ *   direction: Lap(W) d = g - r sum(g)/sum(r), g = mu - r (the projection
+ *     makes the right side sum to zero; d is grounded at the last active x),
+ *     scaled down to max|d| <= NEWTON_STEP_CAP;
+ *   line search: t = 1, 1/2, ... (NEWTON_TRIALS values), accept when
+ *     Phi(F + t d) - Phi(F) >= NEWTON_ARMIJO t <g, d>, where the increase is
+ *     evaluated from the conditional plans at F as
+ *     <g, a> - sum_y nu(y) log(sum_x p_x(y) exp(a(x) - c_y)), a = t d,
+ *     c_y = sum_x p_x(y) a(x) -- both terms are non-negative sums, so the
+ *     test stays meaningful when the increase is far below the size of Phi. */
+static int newton_log(int nx, const int* xr, const int* xc, const double* mu, int ny,
+                      const int* yr, const int* yc, const double* nu, double lam, double tol,
+                      int it0, int maxit, double* F, double* G, int* loops, double* err_out) {
+  int n = 0;
+  for (int i = 0; i < nx; i++) n += mu[i] > 0;
+  int* act = malloc(sizeof(int) * (size_t)(n > 0 ? n : 1));
+  double* P = malloc(sizeof(double) * (size_t)n * ny);
+  double* W = malloc(sizeof(double) * (size_t)n * n);
+  double* buf = malloc(sizeof(double) * (size_t)n * 6);
+  if (!act || !P || !W || !buf || n == 0) {
+    free(act);
+    free(P);
+    free(W);
+    free(buf);
+    *loops = it0;
+    return 2;
+  }
+  double *r = buf, *g = buf + n, *b = buf + 2 * n, *dd = buf + 3 * n, *piv = buf + 4 * n,
+         *lm = buf + 5 * n;
+  n = 0;
+  for (int i = 0; i < nx; i++)
+    if (mu[i] > 0) {
+      act[n] = i;
+      lm[n] = log(mu[i]);
+      n++;
+    }
+  int it = it0, rc = 1, nst = 0;
+  double err = INFINITY;
+  while (it < maxit) {
+    it++;
+    /* Y-iteration and conditional plans */
+    for (int j = 0; j < ny; j++) {
+      double m = -INFINITY;
+      for (int a = 0; a < n; a++) {
+        int i = act[a];
+        double dr = xr[i] - yr[j], dc = xc[i] - yc[j];
+        double e = F[i] + lm[a] - lam * (dr * dr + dc * dc);
+        if (e > m) m = e;
+      }
+      double s = 0;
+      for (int a = 0; a < n; a++) {
+        int i = act[a];
+        double dr = xr[i] - yr[j], dc = xc[i] - yc[j];
+        double v = exp(F[i] + lm[a] - lam * (dr * dr + dc * dc) - m);
+        P[(size_t)a * ny + j] = v;
+        s += v;
+      }
+      for (int a = 0; a < n; a++) P[(size_t)a * ny + j] /= s;
+      G[j] = -(m + log(s));
+    }
+    err = 0;
+    for (int a = 0; a < n; a++) {
+      double s = 0;
+      for (int j = 0; j < ny; j++) s += nu[j] * P[(size_t)a * ny + j];
+      r[a] = s;
+      err += fabs(s - mu[act[a]]);
+    }
+    if (!isfinite(err)) {
+      rc = 2;
+      break;
+    }
+    if (err <= tol) {
+      rc = 0;
+      break;
+    }
+    if (it >= maxit) break;
+    int step = 0;
+    double t = 1, slope = 0;
+    if (nst < NEWTON_MAX_STEPS && n > 1) {
+      nst++;
+      for (int a = 0; a < n; a++)
+        for (int c = 0; c < n; c++) {
+          double s = 0;
+          if (a != c)
+            for (int j = 0; j < ny; j++) s += nu[j] * P[(size_t)a * ny + j] * P[(size_t)c * ny + j];
+          W[(size_t)a * n + c] = s;
+        }
+      double sg = 0, sr = 0;
+      for (int a = 0; a < n; a++) {
+        g[a] = mu[act[a]] - r[a];
+        sg += g[a];
+        sr += r[a];
+      }
+      for (int a = 0; a < n; a++) b[a] = g[a] - r[a] * (sg / sr);
+      gth_solve(n, W, b, dd, piv);
+      double dm = 0;
+      for (int a = 0; a < n; a++) dm = fmax(dm, fabs(dd[a]));
+      if (dm > NEWTON_STEP_CAP)
+        for (int a = 0; a < n; a++) dd[a] *= NEWTON_STEP_CAP / dm;
+      for (int a = 0; a < n; a++) slope += g[a] * dd[a];
+      if (slope > 0) {
+        for (int trial = 0; trial < NEWTON_TRIALS; trial++) {
+          double inc = 0;
+          for (int a = 0; a < n; a++) inc += g[a] * t * dd[a];
+          for (int j = 0; j < ny; j++) {
+            double cy = 0, s = 0;
+            for (int a = 0; a < n; a++) cy += P[(size_t)a * ny + j] * t * dd[a];
+            for (int a = 0; a < n; a++) s += P[(size_t)a * ny + j] * phi1(t * dd[a] - cy);
+            inc -= nu[j] * log1p(s);
+          }
+          if (inc >= NEWTON_ARMIJO * t * slope) {
+            step = 1;
+            break;
+          }
+          t *= 0.5;
+        }
+      }
+    }
+    if (step) {
+      for (int a = 0; a < n; a++) F[act[a]] += t * dd[a];
+    } else {
+      /* plain X-iteration: F <- F + log mu - log r */
+      for (int a = 0; a < n; a++) F[act[a]] += lm[a] - log(r[a]);
+    }
+  }
+  *loops = it;
+  *err_out = err;
+  free(act);
+  free(P);
+  free(W);
+  free(buf);
+  return rc;
+}
+
 /* Log-domain Sinkhorn of Remark "Sinkhorn algorithm", in the dual variables
  * F = f/eps, G = g/eps, with plan pi(x,y) = exp(F(x)+G(y)-C(x,y)) mu(x) nu(y)
  * and C = lam*|x-y|^2 (integer pixel offsets).  Warm start F, first a
@@ -186,8 +380,9 @@ static int cheb_next(cheb_t* c, int it, double err, double* a, double* b, double
  * value went non-finite. */
 static int sinkhorn_log(int nx, const int* xr, const int* xc, const double* mu,
                         int ny, const int* yr, const int* yc, const double* nu,
-                        double lam, double tol, int maxit, int accel, double* F, double* G,
-                        double* Fh, int* loops, double* err_out) {
+                        double lam, double tol, int maxit, int accel, int newton_after,
+                        double* F, double* G, double* Fh, int* loops, double* err_out,
+                        int* used_newton) {
   double* lmu = (double*)malloc(sizeof(double) * (size_t)nx);
   double* lnu = (double*)malloc(sizeof(double) * (size_t)ny);
   double* Fp = (double*)malloc(sizeof(double) * (size_t)nx);
@@ -257,6 +452,14 @@ static int sinkhorn_log(int nx, const int* xr, const int* xc, const double* mu,
         Fp[i] = F[i];
         F[i] = fn;
       }
+    if (it == newton_after) {
+      free(lmu);
+      free(lnu);
+      free(Fp);
+      *used_newton = 1;
+      return newton_log(nx, xr, xc, mu, ny, yr, yc, nu, lam, tol, it, maxit, F, G, loops,
+                        err_out);
+    }
   }
   if (it > maxit) it = maxit;
   *loops = it;
@@ -269,14 +472,16 @@ static int sinkhorn_log(int nx, const int* xr, const int* xc, const double* mu,
 
 int ddo_cell_solve(int nx, const int* xr, const int* xc, const double* mu, int ny,
                    const int* yr, const int* yc, const double* nu, double lam,
-                   double tol, int max_iter, double* F, double* G, double* plan,
-                   int* loops, double* err) {
+                   double tol, int max_iter, int accel, int newton_after, double* F,
+                   double* G, double* plan, int* loops, double* err) {
   if (nx <= 0 || ny <= 0 || !(lam > 0) || max_iter < 1) return -1;
   double* Fh = (double*)malloc(sizeof(double) * (size_t)nx);
   if (!Fh) return -2;
-  int rc = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nu, lam, tol, max_iter, 0, F, G, Fh,
-                        loops, err);
+  int used = 0;
+  int rc = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nu, lam, tol, max_iter, accel,
+                        newton_after, F, G, Fh, loops, err, &used);
   free(Fh);
+  if (used && rc >= 0) rc += 16;
   if (plan) {
     for (int i = 0; i < nx; i++)
       for (int j = 0; j < ny; j++) {
@@ -415,8 +620,9 @@ static void solve_cell(const ddo_ctx* c, int part, const cell_t* C, cell_out_t* 
   }
   double tol = c->opt.err_tol * muJ, err = 0;
   int loops = 0;
+  int used = 0;
   int rc = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nuJ, lam, tol, c->opt.max_iter,
-                        c->opt.accel, F, G, Fh, &loops, &err);
+                        c->opt.accel, c->opt.newton_after, F, G, Fh, &loops, &err, &used);
   o->loops = loops;
   if (rc != 0 && c->opt.safeguard) {
     /* Safeguard of Sec. 7.4: solve the failing cell at a temporarily larger
@@ -425,11 +631,11 @@ static void solve_cell(const ddo_ctx* c, int part, const cell_t* C, cell_out_t* 
     int l2 = 0, l3 = 0;
     for (int k = 0; k < nx; k++) F[k] = F0[k] * 0.5;
     int r2 = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nuJ, lam * 0.5, tol, c->opt.max_iter,
-                          c->opt.accel, F, G, Fh, &l2, &err);
+                          c->opt.accel, c->opt.newton_after, F, G, Fh, &l2, &err, &used);
     if (r2 != 2) {
       for (int k = 0; k < nx; k++) F[k] *= 2.0;
       rc = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nuJ, lam, tol, c->opt.max_iter,
-                        c->opt.accel, F, G, Fh, &l3, &err);
+                        c->opt.accel, c->opt.newton_after, F, G, Fh, &l3, &err, &used);
     } else {
       rc = 2;
     }
@@ -438,6 +644,7 @@ static void solve_cell(const ddo_ctx* c, int part, const cell_t* C, cell_out_t* 
   }
   if (rc == 1) o->status |= 1;
   if (rc == 2) o->status |= 2;
+  if (used) o->status |= 16;
   o->err = err;
 
   /* plan of the last Y-iteration, split into basic-cell Y-marginals
@@ -720,6 +927,7 @@ int ddo_half_iterate(ddo_ctx* c, int part, const uint8_t* mask, ddo_iter_stats* 
     if (o->loops > S.loops_max) S.loops_max = o->loops;
     if (o->status & 3) S.n_failed++;
     if (o->status & 4) S.n_safeguard++;
+    if (o->status & 16) S.n_newton++;
     S.cost += o->cost;
     S.obj += o->obj;
     S.err_x += o->err;
@@ -975,6 +1183,7 @@ int ddo_run_schedule(ddo_ctx* c, const ddo_stage* st, int n, ddo_iter_stats* tot
       if (S.loops_max > T.loops_max) T.loops_max = S.loops_max;
       T.n_failed += S.n_failed;
       T.n_safeguard += S.n_safeguard;
+      T.n_newton += S.n_newton;
       T.nnz = S.nnz;
       T.cost = S.cost;
       T.obj = S.obj;

@@ -11,6 +11,8 @@
  * All pointers are host pointers.  Every function returns 0 on success and a
  * negative code on error (-1 invalid argument, -2 out of memory, -5 state);
  * ddo_half_iterate returns 1 when some cell hit the iteration cap.
+ * Per-cell status bits: 1 cap, 2 non-finite, 4 safeguard used, 8 skipped (mask),
+ * 16 Newton steps used.
  *
  * Conventions (the readings of the paper this oracle implements):
  *  - level 0 is the coarsest grid, level nlev-1 the finest; each coarser
@@ -41,6 +43,7 @@ typedef struct {
   int n_threads;     /* OpenMP threads over cells (0 = runtime default) */
   int safeguard;     /* 1: re-solve failed cells at 2*eps, then eps (Sec. 7.4) */
   int accel;         /* 1: Chebyshev-accelerated X-iteration, 0: plain Sinkhorn */
+  int newton_after;  /* >0: switch a cell to Newton steps after this many loops; 0: never */
 } ddo_opts;
 
 typedef struct {
@@ -55,6 +58,7 @@ typedef struct {
   int loops_max;
   int n_failed;      /* cells that hit max_iter or went non-finite (after safeguard) */
   int n_safeguard;   /* cells that needed the safeguard */
+  int n_newton;      /* cells that switched to Newton steps */
   int64_t nnz;       /* entries of the basic Y-marginals after truncation */
   double cost;       /* sum over cells of <c, pi_J> (plans before balance/truncation) */
   double obj;        /* sum over cells of eps*KL(pi_J|K_J) - eps*|K_J| */
@@ -97,13 +101,15 @@ int ddo_cell_results(const ddo_ctx* c, double* cost, double* obj, double* err_x,
 
 /* One composite-cell problem, for unit tests: log-domain Sinkhorn between
  * mu (nx points at integer coords xr,xc) and nu (ny points at yr,yc) with
- * cost lam*|dx|^2 in units of eps (lam = h^2/eps).  F (in/out, units of eps)
- * is the warm start; on return G holds the Y potential of the last Y-update
- * and plan (nx*ny, row-major by x) the plan of that Y-update. */
+ * cost lam*|dx|^2 in units of eps (lam = h^2/eps), optionally accelerated
+ * and with the Newton fallback after newton_after loops.  F (in/out, units of
+ * eps) is the warm start; on return G holds the Y potential of the last
+ * Y-update and plan (nx*ny, row-major by x) the plan of that Y-update.
+ * Returns 0 converged, 1 at the cap, 2 non-finite, +16 when Newton ran. */
 int ddo_cell_solve(int nx, const int* xr, const int* xc, const double* mu,
                    int ny, const int* yr, const int* yc, const double* nu,
-                   double lam, double tol, int max_iter, double* F, double* G,
-                   double* plan, int* loops, double* err);
+                   double lam, double tol, int max_iter, int accel, int newton_after,
+                   double* F, double* G, double* plan, int* loops, double* err);
 
 #ifdef __cplusplus
 }

@@ -20,6 +20,7 @@ struct HalfParams {
   double h, eps, lam;          // lam = h^2 / eps (cost in units of eps per pixel^2)
   double err_tol, trunc;
   int max_iter, safeguard, accel;
+  int newton_after;            // >0: hand a cell to Newton steps after this many loops
   const double* mu;            // level mu, H*W
   const double* nu;            // level nu, H*W
   double* alpha;               // potentials f of partition `part`, H*W (in/out)
@@ -43,14 +44,16 @@ struct HalfParams {
   int* r_loops;
   int* r_status;
   long long* r_evals;
-  long long* misc;             // [0] nnz_in, [1] out entries, [2] bad-row flag
+  long long* misc;             // [0] nnz_in, [1] out entries, [2] bad-row flag, [3] deferred cells
+  int* defer_list;             // cells handed from the register solver to the Newton solver
+  double* defer_F;             // their potentials (units of eps), 64 per cell, indexed by cell
   long long capE;              // entry buffer capacity (rows are checked against it)
 };
 
 struct IterStatsDev {
   double cost, obj, err;
   long long loops_total, evals, nnz;
-  int loops_max, n_failed, n_safeguard, n_cells;
+  int loops_max, n_failed, n_safeguard, n_newton, n_cells;
   long long evals_bin[kNBins];
   int cells_bin[kNBins];
 };

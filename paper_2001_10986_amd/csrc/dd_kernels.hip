@@ -589,7 +589,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
     int status = 0, loops_all = 0;
     double lam = p.lam;
     const int phases = p.safeguard ? 3 : 1;
-    bool converged = false;
+    bool converged = false, deferred = false;
     const int xr = g.R0 + xg;  // pixel row of the lane's 8 pixels
 
     for (int phase = 0; phase < phases; phase++) {
@@ -807,7 +807,23 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
           __syncthreads();
           absorb();
         }
+        if (it == p.newton_after && phase == 0) {
+          // hand the cell to the Newton solver with its current potential
+          // F0 + log u; the stored potential (alpha) stays for the safeguard
+          if (tid < 64)
+            p.defer_F[(int64_t)cell * 64 + tid] =
+                sh.mu[tid] > 0 ? sh.F0[tid] + log((double)sh.u[tid]) : 0.0;
+          if (tid == 0) {
+            const unsigned long long slot =
+                atomicAdd(reinterpret_cast<unsigned long long*>(&p.misc[3]), 1ull);
+            if (slot < (unsigned long long)p.n_cells) p.defer_list[slot] = cell;
+            p.r_loops[cell] = it;
+          }
+          deferred = true;
+          break;
+        }
       }
+      if (deferred) break;
       loops_all += it;
       if (phase == 0) {
         if (converged) break;
@@ -816,6 +832,10 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
       }
       if (phase == 1 && sh.err == sh.err) continue;  // always return to eps
       break;
+    }
+    if (deferred) {
+      __syncthreads();
+      continue;
     }
     if (!converged) status |= (sh.err == sh.err) ? 1 : 2;
 
@@ -910,28 +930,95 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
 
 // ------------------------------------------------------------ big-cell solver
 
-// Cells whose union exceeds the register capacity: the same Sinkhorn
-// iteration evaluated in the log domain on every pass (FP64 exponents, FP32
-// exponentials, FP64 sums), potentials G(y) kept in the union scratch.
+// Cells whose union exceeds the register capacity, and cells handed over by
+// the register solver for Newton steps.  The Sinkhorn iteration is evaluated
+// in the log domain on every pass (FP64 exponents, FP32 exponentials, FP64
+// sums), potentials G(y) kept in the union scratch.
+//
+// Newton fallback (same rule as the oracle): after `newton_after` loops the
+// cell problem is maximised over the X potential alone (the semi-dual
+//   Phi(F) = sum_x mu F - sum_y nu_J(y) log sum_x exp(F - C) mu,
+// Y potential eliminated by the exact Y-iteration).  Gradient mu - r, minus
+// the Hessian is the Laplacian of W(x,x') = sum_y nu_J p_x(y) p_x'(y) with
+// p_x(y) the conditional plan.  Each iteration: one Y-iteration (the loop and
+// its stopping test), W in FP32, the grounded Laplacian system solved by
+// subtraction-free (GTH) elimination, the step capped to max|d| <= 8, then a
+// backtracking Armijo search on the increase of Phi evaluated as
+//   <g, a> - sum_y nu_J log(sum_x p_x (e^(a - c_y))),  c_y = sum_x p_x a,
+// (two non-negative sums) and, if no trial passes, a plain X-iteration.
 constexpr int kBigThreads = 1024;
+constexpr int kNewtonMaxSteps = 100;
+constexpr double kNewtonStepCap = 8.0;
+constexpr int kNewtonTrials = 10;
+constexpr double kNewtonArmijo = 1e-4;
+
 struct BigShared {
   double F[64], Fmu[64], mu[64], Fh[64], F0orig[64], Fp[64];
+  double r[64], b[64], dl[64], piv[64];
   ChebState cheb;
   double ca, cb, cd;
   int cacc;
   int xr[64], xc[64];
-  double pm[16][64], ps[16][64];
-  double err;
+  union {
+    struct {
+      double pm[16][64], ps[16][64];
+    } lse;                 // Sinkhorn X-marginal partials
+    float q[64][65];       // Newton: p_x(y) sqrt(nu_J(y)) of one chunk of 64 support points
+    double racc[16][64];   // Newton: X-marginal partials per wave
+  } u;
+  float Wm[64][65];        // Newton: weights, then the GTH elimination in place
+  double err, slope;
+  int last;                // last active pixel (ground of the Laplacian system)
+  int nact;                // active pixels (mu > 0)
   CellOutSh out;
 };
 
-__global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int bin) {
+// e^b - 1 - b without cancellation for small |b|
+DEVI double phi1(double b) {
+  if (fabs(b) < 1e-3) return b * b * (0.5 + b * (1.0 / 6 + b * (1.0 / 24 + b / 120)));
+  return expm1(b) - b;
+}
+
+// Conditional plan of support point yi for the 4 pixels xs + 16k of this
+// thread (16 threads per support point, lanes xs = tid & 15 of a 16-lane
+// group): pk[k] = p_x(y), returns m + log s (= -G(y)).
+DEVI double cond_plan(const BigShared& sh, int r, int c, int xs, double lam, double pk[4]) {
+  double e[4];
+  double m = -INFINITY;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const int x = xs + 16 * k;
+    const int dr = r - sh.xr[x], dc = c - sh.xc[x];
+    e[k] = sh.Fmu[x] - lam * (double)(dr * dr + dc * dc);
+    m = e[k] > m ? e[k] : m;
+  }
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) {
+    const double v = __shfl_xor(m, o, 64);
+    m = v > m ? v : m;
+  }
+  double v[4], s = 0;
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    v[k] = e[k] == -INFINITY ? 0.0 : (double)fast_exp2((float)((e[k] - m) * kLog2e));
+    s += v[k];
+  }
+#pragma unroll
+  for (int o = 1; o < 16; o <<= 1) s += __shfl_xor(s, o, 64);
+#pragma unroll
+  for (int k = 0; k < 4; k++) pk[k] = v[k] / s;
+  return m + log(s);
+}
+
+__global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mode) {
   __shared__ BigShared sh;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int count = p.bin_count[bin];
+  const int yl = tid >> 4, xs = tid & 15;  // Newton layout: 64 support points x 16 threads
+  const bool deferred = mode == 1;
+  const int count = deferred ? (int)p.misc[3] : p.bin_count[kNBins - 1];
   const double invW = 1.0 / p.W;
   for (int ci = blockIdx.x; ci < count; ci += gridDim.x) {
-    const int cell = p.bin_list[bin * p.n_cells + ci];
+    const int cell = deferred ? p.defer_list[ci] : p.bin_list[(kNBins - 1) * p.n_cells + ci];
     const CellGeo g = load_geo(p, cell);
     const int U = p.cell_U[cell];
     const int64_t ub = p.cell_toff[cell];
@@ -940,23 +1027,30 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int bin
       const int i = tid >> 3, j = tid & 7;
       const int qa = (i >> 2) * 2 + (j >> 2);
       const int r = g.R0 + i, c = g.C0 + j;
-      double mu = 0, F = 0;
+      double mu = 0, F = 0, F0 = 0;
       const int bq = qa == 0 ? g.bq[0] : qa == 1 ? g.bq[1] : qa == 2 ? g.bq[2] : g.bq[3];
       if (bq >= 0) {
         mu = p.mu[(int64_t)r * p.W + c];
-        F = p.alpha[(int64_t)r * p.W + c] / p.eps;
+        F0 = p.alpha[(int64_t)r * p.W + c] / p.eps;
+        F = deferred ? p.defer_F[(int64_t)cell * 64 + tid] : F0;
       }
       sh.mu[tid] = mu;
       sh.F[tid] = F;
-      sh.F0orig[tid] = F;
+      sh.F0orig[tid] = F0;
       sh.xr[tid] = r;
       sh.xc[tid] = c;
+      const unsigned long long act = __ballot(mu > 0);
+      if (tid == 0) {
+        sh.last = act ? 63 - __builtin_clzll(act) : -1;
+        sh.nact = __builtin_popcountll(act);
+      }
     }
     __syncthreads();
     double massmu[4] = {0, 0, 0, 0};
 #pragma unroll
     for (int k = 0; k < 64; k++) massmu[((k >> 3) >> 2) * 2 + ((k & 7) >> 2)] += sh.mu[k];
     const double tol = p.err_tol * (massmu[0] + massmu[1] + massmu[2] + massmu[3]);
+    const int n_act = sh.nact;
     double* G = p.uni_G + ub;
     int status = 0, loops_all = 0;
     bool converged = false;
@@ -977,8 +1071,9 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int bin
       }
       if (tid == 0) cheb_reset(sh.cheb);
       __syncthreads();
-      int it = 0;
-      for (;;) {
+      bool newton = deferred && phase == 0;
+      int it = newton ? p.r_loops[cell] : 0;
+      while (!newton) {
         it++;
         // Y-iteration
         for (int yi = tid; yi < U; yi += kBigThreads) {
@@ -1017,16 +1112,16 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int bin
               s += (double)fast_exp2((float)((e - m) * kLog2e));
             }
           }
-          sh.pm[wave][x] = m;
-          sh.ps[wave][x] = s;
+          sh.u.lse.pm[wave][x] = m;
+          sh.u.lse.ps[wave][x] = s;
         }
         __syncthreads();
         if (wave == 0) {
           double m = -INFINITY;
-          for (int w = 0; w < 16; w++) m = sh.pm[w][lane] > m ? sh.pm[w][lane] : m;
+          for (int w = 0; w < 16; w++) m = sh.u.lse.pm[w][lane] > m ? sh.u.lse.pm[w][lane] : m;
           double s = 0;
           for (int w = 0; w < 16; w++)
-            if (sh.ps[w][lane] > 0) s += sh.ps[w][lane] * exp(sh.pm[w][lane] - m);
+            if (sh.u.lse.ps[w][lane] > 0) s += sh.u.lse.ps[w][lane] * exp(sh.u.lse.pm[w][lane] - m);
           const double Fh = -(m + log(s));
           sh.Fh[lane] = Fh;
           const double mu = sh.mu[lane];
@@ -1056,6 +1151,170 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int bin
           sh.F[tid] = Fn;
           sh.Fmu[tid] = Fn + log(sh.mu[tid]);
         }
+        __syncthreads();
+        if (it == p.newton_after) newton = true;
+      }
+      if (newton) {
+        status |= 16;
+        int nst = 0;
+        for (;;) {
+          it++;
+          const bool build_w = nst < kNewtonMaxSteps && n_act > 1;
+          // ---- Y-iteration with conditional plans, X-marginal r, weights W
+          double racc[4] = {0, 0, 0, 0};
+          float wacc[4] = {0.f, 0.f, 0.f, 0.f};
+          for (int y0 = 0; y0 < U; y0 += 64) {
+            const int yi = y0 + yl;
+            double pk[4] = {0, 0, 0, 0};
+            double sq = 0;
+            if (yi < U) {  // uniform within each 16-lane group
+              int r, c;
+              split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
+              const double lse = cond_plan(sh, r, c, xs, lam, pk);
+              const double nu = p.uni_nu[ub + yi];
+#pragma unroll
+              for (int k = 0; k < 4; k++) racc[k] += nu * pk[k];
+              if (xs == 0) G[yi] = -lse + (nu > 0 ? log(nu) : -INFINITY);
+              sq = sqrt(nu);
+            }
+            if (build_w) {
+#pragma unroll
+              for (int k = 0; k < 4; k++) sh.u.q[xs + 16 * k][yl] = (float)(pk[k] * sq);
+              __syncthreads();
+              const float* qa = sh.u.q[yl];  // row x = yl of W
+#pragma unroll 4
+              for (int l = 0; l < 64; l++) {
+                const float a = qa[l];
+#pragma unroll
+                for (int k = 0; k < 4; k++) wacc[k] = fmaf(a, sh.u.q[xs + 16 * k][l], wacc[k]);
+              }
+              __syncthreads();
+            }
+          }
+#pragma unroll
+          for (int k = 0; k < 4; k++) {
+            racc[k] += __shfl_xor(racc[k], 16, 64);
+            racc[k] += __shfl_xor(racc[k], 32, 64);
+          }
+          if (lane < 16)
+#pragma unroll
+            for (int k = 0; k < 4; k++) sh.u.racc[wave][lane + 16 * k] = racc[k];
+          if (build_w)
+#pragma unroll
+            for (int k = 0; k < 4; k++) {
+              const int x2 = xs + 16 * k;
+              sh.Wm[yl][x2] = x2 == yl ? 0.f : wacc[k];
+            }
+          __syncthreads();
+          if (wave == 0) {
+            double r = 0;
+            for (int w = 0; w < 16; w++) r += sh.u.racc[w][lane];
+            const double mu = sh.mu[lane];
+            if (!(mu > 0)) r = 0;
+            sh.r[lane] = r;
+            const double e = wave_sum(mu > 0 ? fabs(r - mu) : 0.0);
+            if (lane == 0) sh.err = e;
+          }
+          __syncthreads();
+          const double err = sh.err;
+          if (err <= tol) {
+            converged = true;
+            break;
+          }
+          if (!(err == err) || it >= p.max_iter) break;
+          bool step = false;
+          double t = 1.0;
+          if (build_w) {
+            nst++;
+            if (wave == 0) {
+              // right side g - r sum(g)/sum(r), g = mu - r, then GTH elimination
+              const double mu = sh.mu[lane], r = sh.r[lane];
+              const double gx = mu > 0 ? mu - r : 0.0;
+              const double sg = wave_sum(gx), sr = wave_sum(r);
+              sh.b[lane] = gx - r * (sg / sr);
+              const int last = sh.last;
+              wave_sync();
+              for (int k = 0; k < last; k++) {
+                const double dk = wave_sum(lane > k ? (double)sh.Wm[k][lane] : 0.0);
+                if (lane == 0) sh.piv[k] = dk;
+                if (dk > 0 && lane > k) {
+                  const float cf = (float)((double)sh.Wm[lane][k] / dk);
+                  if (cf != 0.f) {
+                    sh.b[lane] += (double)cf * sh.b[k];
+                    float* row = sh.Wm[lane];
+                    const float* prow = sh.Wm[k];
+                    for (int j = k + 1; j < 64; j++)
+                      if (j != lane) row[j] = fmaf(cf, prow[j], row[j]);
+                  }
+                }
+                wave_sync();
+              }
+              sh.dl[lane] = 0.0;
+              wave_sync();
+              for (int k = last - 1; k >= 0; k--) {
+                const double s = wave_sum(lane > k ? (double)sh.Wm[k][lane] * sh.dl[lane] : 0.0);
+                if (lane == 0) sh.dl[k] = sh.piv[k] > 0 ? (sh.b[k] + s) / sh.piv[k] : 0.0;
+                wave_sync();
+              }
+              double dx = sh.dl[lane];
+              const double dm = wave_max(fabs(dx));
+              if (dm > kNewtonStepCap) dx *= kNewtonStepCap / dm;
+              sh.dl[lane] = dx;
+              const double sl = wave_sum(gx * dx);
+              if (lane == 0) sh.slope = sl;
+            }
+            __syncthreads();
+            const double slope = sh.slope;
+            if (slope > 0) {
+              for (int trial = 0; trial < kNewtonTrials; trial++) {
+                double loc = 0;
+                for (int y0 = 0; y0 < U; y0 += 64) {
+                  const int yi = y0 + yl;
+                  if (yi < U) {
+                    int r, c;
+                    split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
+                    double pk[4];
+                    cond_plan(sh, r, c, xs, lam, pk);
+                    double a[4], cy = 0;
+#pragma unroll
+                    for (int k = 0; k < 4; k++) {
+                      a[k] = t * sh.dl[xs + 16 * k];
+                      cy += pk[k] * a[k];
+                    }
+#pragma unroll
+                    for (int o = 1; o < 16; o <<= 1) cy += __shfl_xor(cy, o, 64);
+                    double s = 0;
+#pragma unroll
+                    for (int k = 0; k < 4; k++) s += pk[k] > 0 ? pk[k] * phi1(a[k] - cy) : 0.0;
+#pragma unroll
+                    for (int o = 1; o < 16; o <<= 1) s += __shfl_xor(s, o, 64);
+                    if (xs == 0) loc -= p.uni_nu[ub + yi] * log1p(s);
+                  }
+                }
+                if (tid < 64) {
+                  const double mu = sh.mu[tid];
+                  loc += mu > 0 ? (mu - sh.r[tid]) * t * sh.dl[tid] : 0.0;
+                }
+                const double inc = block_sum_d(loc, sh.out.red);
+                if (inc >= kNewtonArmijo * t * slope) {
+                  step = true;
+                  break;
+                }
+                t *= 0.5;
+              }
+            }
+          }
+          if (tid < 64 && sh.mu[tid] > 0) {
+            const double F = step ? sh.F[tid] + t * sh.dl[tid]
+                                  : sh.F[tid] + log(sh.mu[tid]) - log(sh.r[tid]);
+            sh.F[tid] = F;
+            sh.Fmu[tid] = F + log(sh.mu[tid]);
+          }
+          __syncthreads();
+        }
+        // X-marginal of the last Y-iteration as mu exp(F - Fh) (final pass)
+        if (tid < 64)
+          sh.Fh[tid] = sh.mu[tid] > 0 ? sh.F[tid] - log(sh.r[tid] / sh.mu[tid]) : 0.0;
         __syncthreads();
       }
       loops_all += it;
@@ -1227,7 +1486,7 @@ __global__ __launch_bounds__(1024) void k_stats(HalfParams p, IterStatsDev* out)
   __shared__ long long shl[16];
   double c = 0, o = 0, e = 0;
   long long lt = 0, ev = 0, nnz = 0;
-  int lmax = 0, nf = 0, ns = 0;
+  int lmax = 0, nf = 0, ns = 0, nn = 0;
   for (int i = threadIdx.x; i < p.n_cells; i += 1024) {
     c += p.r_cost[i];
     o += p.r_obj[i];
@@ -1237,6 +1496,7 @@ __global__ __launch_bounds__(1024) void k_stats(HalfParams p, IterStatsDev* out)
     lmax = max(lmax, p.r_loops[i]);
     nf += (p.r_status[i] & 3) != 0;
     ns += (p.r_status[i] & 4) != 0;
+    nn += (p.r_status[i] & 16) != 0;
   }
   for (int b = threadIdx.x; b < p.n_basic; b += 1024) nnz += p.row_len[b];
   long long eb[kNBins];
@@ -1268,6 +1528,8 @@ __global__ __launch_bounds__(1024) void k_stats(HalfParams p, IterStatsDev* out)
   nf = (int)tot;
   block_excl_scan((long long)ns, shl, &tot);
   ns = (int)tot;
+  block_excl_scan((long long)nn, shl, &tot);
+  nn = (int)tot;
 #pragma unroll
   for (int k = 0; k < kNBins; k++) {
     long long t2;
@@ -1292,6 +1554,7 @@ __global__ __launch_bounds__(1024) void k_stats(HalfParams p, IterStatsDev* out)
     out->loops_max = (int)m;
     out->n_failed = nf;
     out->n_safeguard = ns;
+    out->n_newton = nn;
     out->n_cells = p.n_cells;
     for (int k = 0; k < kNBins; k++) {
       out->evals_bin[k] = eb[k];
@@ -1325,7 +1588,10 @@ void launch_sweep(const HalfParams& p, hipStream_t st, int grid_cap, hipEvent_t*
   mark();
   hipLaunchKernelGGL(k_solve_reg<16>, dim3(g), dim3(1024), 0, st, p, 4);
   mark();
-  hipLaunchKernelGGL(k_solve_big, dim3(g), dim3(kBigThreads), 0, st, p, 5);
+  hipLaunchKernelGGL(k_solve_big, dim3(g), dim3(kBigThreads), 0, st, p, 0);
+  mark();
+  // cells handed over by the register solvers (count known on the device only)
+  hipLaunchKernelGGL(k_solve_big, dim3(g), dim3(kBigThreads), 0, st, p, 1);
   mark();
 }
 

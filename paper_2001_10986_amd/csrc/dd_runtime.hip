@@ -75,6 +75,8 @@ struct dd_ctx {
   double *r_cost = nullptr, *r_obj = nullptr, *r_err = nullptr;
   int *r_loops = nullptr, *r_status = nullptr;
   long long* r_evals = nullptr;
+  int* defer_list = nullptr;
+  double* defer_F = nullptr;
   long long* misc = nullptr;
   int* uni_key = nullptr;
   double* uni_nu = nullptr;
@@ -168,6 +170,8 @@ static dd_status upload_cells(dd_ctx* c) {
     hipFree(c->r_loops);
     hipFree(c->r_status);
     hipFree(c->r_evals);
+    hipFree(c->defer_list);
+    hipFree(c->defer_F);
     HIPCHK(c, dmalloc(&c->cell_toff, need));
     HIPCHK(c, dmalloc(&c->cell_U, need));
     HIPCHK(c, dmalloc(&c->cell_ooff, need));
@@ -178,6 +182,8 @@ static dd_status upload_cells(dd_ctx* c) {
     HIPCHK(c, dmalloc(&c->r_loops, need));
     HIPCHK(c, dmalloc(&c->r_status, need));
     HIPCHK(c, dmalloc(&c->r_evals, need));
+    HIPCHK(c, dmalloc(&c->defer_list, need));
+    HIPCHK(c, dmalloc(&c->defer_F, (size_t)need * 64));
     c->cell_cap = need;
   }
   return DD_OK;
@@ -247,6 +253,7 @@ extern "C" void dd_options_default(dd_options* o) {
   o->max_sinkhorn_iter = 50000;
   o->safeguard = 1;
   o->accel = 1;
+  o->newton_after = 128;
   o->inputs_on_device = 0;
   o->timing = 0;
   o->stream = nullptr;
@@ -275,6 +282,8 @@ extern "C" void dd_free(dd_ctx* c) {
   hipFree(c->r_loops);
   hipFree(c->r_status);
   hipFree(c->r_evals);
+  hipFree(c->defer_list);
+  hipFree(c->defer_F);
   hipFree(c->misc);
   hipFree(c->uni_key);
   hipFree(c->uni_nu);
@@ -364,7 +373,8 @@ extern "C" dd_status dd_init(const double* mu, const double* nu, int H, int W, i
     c->opt = *opt;
   else
     dd_options_default(&c->opt);
-  if (!(c->opt.err_tol > 0) || !(c->opt.trunc_threshold >= 0) || c->opt.max_sinkhorn_iter < 1) {
+  if (!(c->opt.err_tol > 0) || !(c->opt.trunc_threshold >= 0) || c->opt.max_sinkhorn_iter < 1 ||
+      c->opt.newton_after < 0) {
     delete c;
     return fail(nullptr, DD_EINVAL, "invalid options");
   }
@@ -467,6 +477,7 @@ static HalfParams make_params(dd_ctx* c, int part) {
   p.max_iter = c->opt.max_sinkhorn_iter;
   p.safeguard = c->opt.safeguard;
   p.accel = c->opt.accel;
+  p.newton_after = c->opt.newton_after;
   p.mu = l.mu;
   p.nu = l.nu;
   p.alpha = c->alpha[part];
@@ -491,6 +502,8 @@ static HalfParams make_params(dd_ctx* c, int part) {
   p.r_status = c->r_status;
   p.r_evals = c->r_evals;
   p.misc = c->misc;
+  p.defer_list = c->defer_list;
+  p.defer_F = c->defer_F;
   p.capE = c->capE;
   return p;
 }
@@ -526,6 +539,7 @@ extern "C" dd_status dd_half_iterate(dd_ctx* c, int part, dd_iter_stats* out) {
   r.loops_total = d.loops_total;
   r.n_failed = d.n_failed;
   r.n_safeguard = d.n_safeguard;
+  r.n_newton = d.n_newton;
   r.nnz = d.nnz;
   r.entry_evals = d.evals;
   r.cost = d.cost;
@@ -736,6 +750,7 @@ extern "C" dd_status dd_run_schedule(dd_ctx* c, dd_run_stats* out) {
       rs.entry_evals += it.entry_evals;
       rs.n_failed += it.n_failed;
       rs.n_safeguard += it.n_safeguard;
+      rs.n_newton += it.n_newton;
       rs.nnz_max = std::max(rs.nnz_max, it.nnz);
       for (int b = 0; b < DD_N_KERNELS; b++) rs.ms_kernel[b] += it.ms_kernel[b];
       for (int b = 0; b < DD_N_BINS; b++) {

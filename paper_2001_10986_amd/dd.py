@@ -28,20 +28,21 @@ class Stage(C.Structure):
 class Options(C.Structure):
     _fields_ = [("err_tol", C.c_double), ("trunc_threshold", C.c_double),
                 ("max_sinkhorn_iter", C.c_int), ("safeguard", C.c_int), ("accel", C.c_int),
-                ("inputs_on_device", C.c_int), ("timing", C.c_int), ("stream", C.c_void_p)]
+                ("newton_after", C.c_int), ("inputs_on_device", C.c_int), ("timing", C.c_int), ("stream", C.c_void_p)]
 
 
-N_KERNELS, N_BINS = 10, 6
+N_KERNELS, N_BINS = 11, 6
 KERNEL_NAMES = ["scan_cells", "union", "scan_out_bins", "solve_reg_1w", "solve_reg_2w",
-                "solve_reg_4w", "solve_reg_8w", "solve_reg_16w", "solve_big", "stats"]
+                "solve_reg_4w", "solve_reg_8w", "solve_reg_16w", "solve_big", "solve_newton",
+                "stats"]
 
 
 class IterStats(C.Structure):
     _fields_ = [("n_cells", C.c_int), ("loops_max", C.c_int), ("loops_total", C.c_int64),
-                ("n_failed", C.c_int), ("n_safeguard", C.c_int), ("nnz", C.c_int64),
-                ("entry_evals", C.c_int64), ("cost", C.c_double), ("obj", C.c_double),
-                ("err_x", C.c_double), ("ms", C.c_double),
-                ("ms_kernel", C.c_double * 10), ("cells_bin", C.c_int * 6),
+                ("n_failed", C.c_int), ("n_safeguard", C.c_int), ("n_newton", C.c_int),
+                ("nnz", C.c_int64), ("entry_evals", C.c_int64), ("cost", C.c_double),
+                ("obj", C.c_double), ("err_x", C.c_double), ("ms", C.c_double),
+                ("ms_kernel", C.c_double * N_KERNELS), ("cells_bin", C.c_int * 6),
                 ("evals_bin", C.c_int64 * 6)]
 
     def as_dict(self):
@@ -52,8 +53,9 @@ class IterStats(C.Structure):
 class RunStats(C.Structure):
     _fields_ = [("n_half_iters", C.c_int), ("n_cell_solves", C.c_int),
                 ("loops_total", C.c_int64), ("entry_evals", C.c_int64), ("n_failed", C.c_int),
-                ("n_safeguard", C.c_int), ("nnz_max", C.c_int64), ("ms_total", C.c_double),
-                ("ms_kernel", C.c_double * 10), ("launches_bin", C.c_int * 6),
+                ("n_safeguard", C.c_int), ("n_newton", C.c_int), ("nnz_max", C.c_int64),
+                ("ms_total", C.c_double), ("ms_kernel", C.c_double * N_KERNELS),
+                ("launches_bin", C.c_int * 6),
                 ("evals_bin", C.c_int64 * 6)]
 
     def as_dict(self):
@@ -134,13 +136,15 @@ class Problem:
     """
 
     def __init__(self, mu, nu, schedule, s=4, n_levels=1, err_tol=1e-5, trunc=1e-15,
-                 max_iter=50000, safeguard=1, stream=None, timing=False, accel=1):
+                 max_iter=50000, safeguard=1, stream=None, timing=False, accel=1,
+                 newton_after=128):
         opt = Options()
         lib.dd_options_default(C.byref(opt))
         opt.err_tol, opt.trunc_threshold = err_tol, trunc
         opt.max_sinkhorn_iter, opt.safeguard = max_iter, safeguard
         opt.timing = 1 if timing else 0
         opt.accel = int(accel)
+        opt.newton_after = int(newton_after)
         on_dev = hasattr(mu, "data_ptr") and getattr(mu, "is_cuda", False)
         if on_dev:
             import torch

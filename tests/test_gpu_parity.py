@@ -177,3 +177,40 @@ def test_device_inputs_match_host_inputs(dd):
         g2.half_iterate(ell % 2)
     e1, e2 = g1.export(), g2.export()
     assert np.array_equal(e1["val"], e2["val"]) and np.array_equal(e1["alpha_a"], e2["alpha_a"])
+
+
+@pytest.mark.parametrize("N,K", [(32, 4), (64, 2)])
+def test_newton_fallback_matches_oracle(dd, ddo, N, K):
+    # Newton steps after K loops: N=32 hands register-solver cells to the Newton
+    # kernel, N=64 (U = 4096) runs them inside the log-domain big-cell solver.
+    # Both sides stop on the same test at the same fixed point, but their
+    # Newton iterates differ (FP32 weights on the GPU), so the bar is the
+    # stopping tolerance rather than loop-for-loop agreement.
+    mu, nu = datagen.small_pair(N, 3, seed=6)
+    eps = 4.0 / N ** 2
+    g = dd.Problem(mu, nu, [(0, eps, 4)], s=4, n_levels=1, newton_after=K)
+    o = ddo.Oracle(mu, nu, s=4, n_levels=1, eps=eps, newton_after=K)
+    info = g.level_info()
+    for ell in range(4 if N < 64 else 2):
+        sg = g.half_iterate(ell % 2)
+        so = o.half_iterate(ell % 2)
+        print(N, K, ell, "gpu", {k: sg[k] for k in ("loops_total", "loops_max", "n_newton", "cost", "err_x")},
+              "oracle", {k: so[k] for k in ("loops_total", "loops_max", "n_newton", "cost", "err_x")},
+              flush=True)
+        eg = _valid_state(g)
+        assert sg["n_failed"] == 0 and so["n_failed"] == 0
+        assert sg["n_newton"] > 0 and so["n_newton"] > 0
+        assert abs(sg["n_newton"] - so["n_newton"]) <= 0.05 * so["n_newton"] + 1
+        rg, ro = g.cell_results(), o.cell_results(ell % 2)
+        nw = (rg["status"] & 16) != 0
+        assert nw.sum() == sg["n_newton"]
+        # per cell: the same optimum within the stopping tolerance
+        assert np.all(np.abs(rg["cost"] - ro["cost"]) <= 2e-5 * np.abs(ro["cost"]) + 1e-18)
+        assert abs(sg["cost"] - so["cost"]) <= 2e-6 * so["cost"]
+        assert sg["err_x"] <= 1e-5
+        bg, bo = g.basic_marginals(), o.basic_marginals()
+        print("  marg diff", np.abs(bg - bo).max() / bg.sum(axis=1).max(), flush=True)
+        assert np.abs(bg - bo).max() < 2e-5 * bg.sum(axis=1).max()
+        rm_g = _row_masses(eg, info["n_basic"])
+        rm_o = _row_masses(o.export(), info["n_basic"])
+        assert np.abs(rm_g - rm_o).max() < 1e-15 * N * N + 1e-14

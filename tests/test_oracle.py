@@ -202,9 +202,64 @@ def test_accelerated_sinkhorn_same_fixed_point_fewer_loops():
     eps = 2.0 / 32 ** 2
     res = {}
     for accel in (0, 1):
-        o = ddo.Oracle(mu, nu, s=4, n_levels=1, eps=eps, err_tol=1e-11, trunc=0.0, accel=accel)
+        o = ddo.Oracle(mu, nu, s=4, n_levels=1, eps=eps, err_tol=1e-11, trunc=0.0, accel=accel,
+                       newton_after=0)
         st = o.half_iterate(0)
         res[accel] = (st, o.basic_marginals())
     assert res[1][0]["loops_total"] < 0.6 * res[0][0]["loops_total"]
     assert np.abs(res[1][1] - res[0][1]).max() < 1e-9 * res[0][1].max()
     assert abs(res[1][0]["cost"] - res[0][0]["cost"]) < 1e-10
+
+
+def _two_strip_cell():
+    # 8x8 X block with mass only in columns 0-1 (0.55) and 6-7 (0.45); Y in two
+    # 8x3 strips around them with the masses swapped (0.45 / 0.55), so exactly
+    # 0.1 must cross the 4-column gap: the coupling graph of the cell is nearly
+    # disconnected and plain Sinkhorn converges slowly.
+    xr, xc = np.divmod(np.arange(64), 8)
+    mu = np.where((xc < 2) | (xc >= 6), 1.0, 0.0) * (1 + 0.1 * np.sin(np.arange(64)))
+    mu[xc < 2] *= 0.55 / mu[xc < 2].sum()
+    mu[xc >= 6] *= 0.45 / mu[xc >= 6].sum()
+    yr, yc = np.meshgrid(np.arange(1, 9), np.r_[-1, 0, 1, 6, 7, 8], indexing="ij")
+    yr, yc = yr.ravel(), yc.ravel()
+    nu = 1 + 0.2 * np.cos(np.arange(len(yr)))
+    nu[yc < 3] *= 0.45 / nu[yc < 3].sum()
+    nu[yc >= 3] *= 0.55 / nu[yc >= 3].sum()
+    return xr, xc, mu, yr, yc, nu
+
+
+def test_newton_fallback_on_nearly_disconnected_cell():
+    xr, xc, mu, yr, yc, nu = _two_strip_cell()
+    lam = 3.0
+    plain = ddo.cell_solve(xr, xc, mu, yr, yc, nu, lam, 1e-12, 200000)
+    newt = ddo.cell_solve(xr, xc, mu, yr, yc, nu, lam, 1e-12, 200000, newton_after=16)
+    assert plain["rc"] == 0 and newt["rc"] == 0 and newt["newton"] and not plain["newton"]
+    assert newt["loops"] < plain["loops"] / 10
+    P = newt["plan"]
+    # the plan has the Gibbs form by construction; with both marginals met it is
+    # the unique entropic optimum, hence equal to the plain Sinkhorn plan
+    assert np.abs(P.sum(1) - mu).sum() <= 1e-12
+    assert np.abs(P.sum(0) - nu).max() < 1e-15
+    assert np.abs(P - plain["plan"]).max() < 1e-12
+    # mass conservation fixes what crosses the gap: 0.55 - 0.45 from left to right
+    assert abs(P[xc < 2][:, yc >= 3].sum() - 0.1) < 1e-11
+    assert P[xc >= 6][:, yc < 3].sum() < 1e-30
+
+
+def test_newton_fallback_same_cell_optima_in_a_sweep():
+    # one sweep of every cell with and without the Newton fallback (after 4
+    # loops): same stopping test, so the same cell optima within tolerance
+    mu, nu = datagen.small_pair(32, 4, seed=72)
+    eps = 2.0 / 32 ** 2
+    res = {}
+    for k in (0, 4):
+        o = ddo.Oracle(mu, nu, s=4, n_levels=1, eps=eps, err_tol=1e-11, trunc=0.0, accel=0,
+                       newton_after=k)
+        st = o.half_iterate(0)
+        res[k] = (st, o.basic_marginals(), o.cell_results(0))
+    assert res[0][0]["n_newton"] == 0 and res[4][0]["n_newton"] > 0
+    assert res[4][0]["n_failed"] == 0
+    assert (res[4][2]["status"] & 16).sum() > 0
+    assert res[4][0]["loops_total"] < 0.5 * res[0][0]["loops_total"]
+    assert np.abs(res[4][1] - res[0][1]).max() < 1e-9 * res[0][1].max()
+    assert abs(res[4][0]["cost"] - res[0][0]["cost"]) < 1e-10
