@@ -81,7 +81,7 @@ def main():
 
     # roofline of the dominant solver kernel, from the events recorded around it
     tot_ms = [sum(r["ms_kernel"][k] for r, _ in runs) for k in range(dd.N_KERNELS)]
-    solver = max(range(3, 9), key=lambda k: tot_ms[k])
+    solver = max(range(3, 3 + dd.N_BINS), key=lambda k: tot_ms[k])
     b = solver - 3
     launches = sum(r["launches_bin"][b] for r, _ in runs)
     evals = sum(r["evals_bin"][b] for r, _ in runs)

@@ -84,13 +84,14 @@ typedef struct {
   void* stream;            /* hipStream_t for all work of the context; default NULL */
 } dd_options;
 
-/* Kernels of one sweep, in launch order (indices of the ms_kernel arrays):
- * 0 cell sizes scan, 1 union, 2 output scan + size bins, 3..7 register
- * solvers for unions of <= 64, 128, 256, 512, 1024 points, 8 log-domain
- * solver for larger unions, 9 Newton solver for the cells the register
- * solvers handed over, 10 statistics. */
-#define DD_N_KERNELS 11
-#define DD_N_BINS 6
+/* Kernels of one sweep (indices of the ms_kernel arrays): 0 cell sizes scan,
+ * 1 union, 2 output scan + size bins, 3..7 register solvers for unions of
+ * <= 64, 128, 256, 512, 1024 points, 8 streamed solver for unions of <= 8192
+ * points, 9 log-domain solver for larger unions, 10 Newton solver for the
+ * cells the register and streamed solvers handed over, 11 statistics.
+ * Solver bins 0..6 are kernels 3..9; kernels 3..9 run concurrently. */
+#define DD_N_KERNELS 12
+#define DD_N_BINS 7
 
 typedef struct {
   int n_cells;             /* composite cells solved */

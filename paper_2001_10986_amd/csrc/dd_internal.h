@@ -10,7 +10,10 @@ constexpr int kS = 4;          // basic cell edge in pixels (the only supported 
 constexpr int kCellPx = 64;    // a composite cell is a virtual 8x8 pixel block
 constexpr int kNRegBins = 5;   // register-resident solver bins: 1,2,4,8,16 waves
 constexpr int kRegMaxU = 1024; // largest Y-support kept in registers (16 waves x 64)
-constexpr int kNBins = kNRegBins + 1;
+constexpr int kStreamSlabs = 8;                // streamed solver: slabs of 1024 support points
+constexpr int kStreamMaxU = kStreamSlabs * 1024;
+constexpr size_t kStreamTileFloats = (size_t)kStreamMaxU * 64;  // tile buffer per workgroup
+constexpr int kNBins = kNRegBins + 2;          // + streamed solver + log-domain solver
 
 // Everything one sweep over one partition needs.  Device pointers.
 struct HalfParams {
@@ -45,6 +48,11 @@ struct HalfParams {
   int* r_status;
   long long* r_evals;
   long long* misc;             // [0] nnz_in, [1] out entries, [2] bad-row flag, [3] deferred cells
+  int* queue;                  // per solver launch: next cell of its list (kNBins + 1 counters)
+  float* stream_tile;          // streamed solver: kStreamTileFloats per workgroup
+  float* stream_S;             // streamed solver: S(y), kStreamMaxU per workgroup
+  float* stream_nu;            // streamed solver: nu_J(y) in FP32, kStreamMaxU per workgroup
+  int stream_wgs;              // workgroups the streamed-solver buffers are sized for
   int* defer_list;             // cells handed from the register solver to the Newton solver
   double* defer_F;             // their potentials (units of eps), 64 per cell, indexed by cell
   long long capE;              // entry buffer capacity (rows are checked against it)
@@ -58,10 +66,20 @@ struct IterStatsDev {
   int cells_bin[kNBins];
 };
 
-// Kernel launchers (all asynchronous on `st`).
-// ev: nullptr, or 11 events recorded before the first and after every launch
-void launch_sweep(const HalfParams& p, hipStream_t st, int grid_cap, hipEvent_t* ev);
-void launch_stats(const HalfParams& p, IterStatsDev* out, hipStream_t st, hipEvent_t ev_after);
+// Streams of one sweep: the solver launches of the size bins run concurrently
+// on `main` and three auxiliary streams (fork/join through events).
+struct SweepStreams {
+  hipStream_t main;
+  hipStream_t aux[3];
+  hipEvent_t fork;
+  hipEvent_t join[3];
+};
+constexpr int kNKernels = 12;  // scan, union, scan_out, 5 register, streamed, big, newton, stats
+
+// Kernel launchers (all asynchronous).  ev: nullptr, or 2*kNKernels events;
+// ev[2k] and ev[2k+1] are recorded around kernel k on the stream it runs on.
+void launch_sweep(const HalfParams& p, const SweepStreams& s, int grid_cap, hipEvent_t* ev);
+void launch_stats(const HalfParams& p, IterStatsDev* out, hipStream_t st, hipEvent_t* ev2);
 size_t sweep_max_static_lds();
 
 void launch_validate(const double* mu, const double* nu, int H, int W, double* out4,

@@ -134,7 +134,8 @@ DEVI int bin_of(int U) {
   if (U <= 256) return 2;
   if (U <= 512) return 3;
   if (U <= kRegMaxU) return 4;
-  return 5;
+  if (U <= kStreamMaxU) return 5;
+  return 6;
 }
 
 // cell_ooff = exclusive scan of |J| * U_J; stable lists of cells per size bin
@@ -414,6 +415,84 @@ DEVI void balance_truncate_write(const HalfParams& p, const CellGeo& g, int64_t 
   __syncthreads();
 }
 
+// Balancing, truncation and compaction for cells whose support exceeds the
+// block size: the unbalanced split nu_J(y) S_i(y)/S(y) has been
+// stashed at obase + qidx*U + yi; norms over the whole support, then the same
+// BalanceMeasures rule, truncation and an order-preserving compaction chunk by
+// chunk (out.cnt must be zero on entry).
+DEVI void balance_compact_chunked(const HalfParams& p, const CellGeo& g, int64_t obase, int U,
+                                  const double massmu[4], CellOutSh& out) {
+  // balance: norms over the whole support, then per-y update and compaction
+  double nrm[4];
+  _Pragma("unroll") for (int a = 0; a < 4; a++) {
+    double s = 0;
+    if (g.bq[a] >= 0)
+      for (int yi = (int)threadIdx.x; yi < U; yi += (int)blockDim.x) s += p.ent_val[obase + (int64_t)g.qidx[a] * U + yi];
+    nrm[a] = block_sum_d(s, out.red);
+  }
+  if (threadIdx.x == 0) {
+    double E = 0, D = 0;
+    _Pragma("unroll") for (int a = 0; a < 4; a++) {
+      double d = g.bq[a] >= 0 ? massmu[a] - nrm[a] : 0.0;
+      out.dq[a] = d;
+      if (d < 0) E += -d;
+      if (d > 0) D += d;
+    }
+    double T = E < D ? E : D;
+    _Pragma("unroll") for (int a = 0; a < 4; a++)
+      out.tq[a] = (T > 0 && out.dq[a] < 0) ? T * (-out.dq[a]) / (E * nrm[a]) : 0.0;
+    out.E = T > 0 ? E : 0.0;
+    out.D = T > 0 ? D : 0.0;
+  }
+  __syncthreads();
+  for (int y0 = 0; y0 < U; y0 += (int)blockDim.x) {
+    const int yi = y0 + (int)threadIdx.x;
+    const bool own = yi < U;
+    double v[4] = {0, 0, 0, 0};
+    int key = 0;
+    if (own) {
+      _Pragma("unroll") for (int a = 0; a < 4; a++)
+        if (g.bq[a] >= 0) {
+          const int64_t at = obase + (int64_t)g.qidx[a] * U + yi;
+          v[a] = p.ent_val[at];
+          key = p.ent_col[at];
+        }
+      if (out.D > 0) {
+        double R = 0;
+        _Pragma("unroll") for (int a = 0; a < 4; a++)
+          if (g.bq[a] >= 0 && out.dq[a] < 0) {
+            const double rr = v[a] * out.tq[a];
+            v[a] -= rr;
+            R += rr;
+          }
+        _Pragma("unroll") for (int a = 0; a < 4; a++)
+          if (g.bq[a] >= 0 && out.dq[a] > 0) v[a] += R * out.dq[a] / out.D;
+      }
+    }
+    unsigned long long flags = 0;
+    if (own)
+      _Pragma("unroll") for (int a = 0; a < 4; a++)
+        if (g.bq[a] >= 0 && v[a] >= p.trunc && v[a] > 0.0) flags |= 1ull << (16 * a);
+    long long tot;
+    long long ex = block_excl_scan((long long)flags, out.scan, &tot);
+    __syncthreads();  // every thread has read its chunk before any compacted write
+    if (own)
+      _Pragma("unroll") for (int a = 0; a < 4; a++)
+        if ((flags >> (16 * a)) & 1ull) {
+          const long long pos = out.cnt[a] + ((ex >> (16 * a)) & 0xffffll);
+          if (pos < U) {
+            const int64_t at = obase + (int64_t)g.qidx[a] * U + pos;
+            p.ent_col[at] = key;
+            p.ent_val[at] = v[a];
+          }
+        }
+    __syncthreads();
+    if (threadIdx.x == 0)
+      _Pragma("unroll") for (int a = 0; a < 4; a++) out.cnt[a] += (tot >> (16 * a)) & 0xffffll;
+    __syncthreads();
+  }
+}
+
 // Chebyshev acceleration of the X-iteration (same rule as the oracle): one
 // Sinkhorn loop F -> X(Y(F)) has a Jacobian with real eigenvalues in [0, rho)
 // at the solution, so the Chebyshev semi-iteration for [0, rho] (Golub & Varga)
@@ -511,6 +590,7 @@ struct RegShared {
   int cacc;
   double err;
   int flag;
+  int next;
   CellOutSh out;
 };
 
@@ -545,7 +625,13 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
   const int count = p.bin_count[bin];
   const double invW = 1.0 / p.W;
   float* rd = sh.red[wave];
-  for (int ci = blockIdx.x; ci < count; ci += gridDim.x) {
+  for (;;) {
+    // next cell of this bin (a work queue, so that slow cells do not hold up
+    // the cells behind them)
+    if (tid == 0) sh.next = atomicAdd(&p.queue[bin], 1);
+    __syncthreads();
+    const int ci = sh.next;
+    if (ci >= count) break;
     const int cell = p.bin_list[bin * p.n_cells + ci];
     const CellGeo g = load_geo(p, cell);
     const int U = p.cell_U[cell];
@@ -928,6 +1014,484 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
   }
 }
 
+// ------------------------------------------------------------ streamed solver
+
+// Cells whose union exceeds the register capacity (1024 < U <= kStreamMaxU):
+// the iteration of the register solver with the absorbed tile kept in a
+// per-workgroup global buffer (FP32, written at every absorption, read once
+// per loop) and the support processed in slabs of kSlab = 512 points.  Within
+// a slab the lane layout is the one of the 8-wave register solver, and the
+// Y-iteration and the X-marginal of a slab share one read of its tile:
+//   S(y) = sum_x P u  ->  w(y) = nu_J / S  ->  r(x) += sum_y P w.
+// The tile of slab s, wave w is stored as 16 float4 per lane, float4 k of
+// lane l at ((s*kSW + w)*16 + k)*64 + l, so that every load instruction of a
+// wave reads 1 KiB of consecutive memory.  Eight waves leave 256 VGPRs per
+// lane for the tile, its scaling vectors and the FP64 bookkeeping.
+constexpr int kSW = 8;
+constexpr int kSlab = kSW * 64;
+static_assert(kStreamMaxU % kSlab == 0, "slabs tile the streamed support");
+struct StreamShared {
+  double F0[64], Fmu[64], mu[64], F0orig[64], mx[64];
+  float u[64], r[64];
+  float red[kSW][512];  // per-wave transposition scratch (also FP64 scratch)
+  float wred[kSW][64];  // per-wave X partials
+  float wl[kSW][64];    // per-wave w of the current slab
+  float lup[64];
+  ChebState cheb;
+  double ca, cb, cd;
+  int cacc;
+  double err;
+  int flag;
+  int next;
+  CellOutSh out;
+};
+
+DEVI float4* tile_at(float* base, int slab, int wave, int k, int lane) {
+  return reinterpret_cast<float4*>(base) + ((size_t)((slab * kSW + wave) * 16 + k) * 64 + lane);
+}
+
+__global__ __launch_bounds__(kSlab) void k_solve_stream(HalfParams p) {
+  __shared__ StreamShared sh;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int xg = lane & 7, yg = lane >> 3;
+  const int yoff = wave * 64 + yg * 8;  // first of the lane's 8 points within a slab
+  const int bin = kNBins - 2;
+  const int count = p.bin_count[bin];
+  const double invW = 1.0 / p.W;
+  float* rd = sh.red[wave];
+  float* tileb = p.stream_tile + (size_t)blockIdx.x * kStreamTileFloats;
+  float* Sg = p.stream_S + (size_t)blockIdx.x * kStreamMaxU;
+  float* nug = p.stream_nu + (size_t)blockIdx.x * kStreamMaxU;
+  for (;;) {
+    if (tid == 0) sh.next = atomicAdd(&p.queue[bin], 1);
+    __syncthreads();
+    const int ci = sh.next;
+    if (ci >= count) break;
+    const int cell = p.bin_list[bin * p.n_cells + ci];
+    const CellGeo g = load_geo(p, cell);
+    const int U = min(p.cell_U[cell], kStreamMaxU);  // the bin holds U <= kStreamMaxU only
+    const int nslab = (U + kSlab - 1) / kSlab;
+    const int64_t ub = p.cell_toff[cell];
+    const int64_t obase = p.cell_ooff[cell];
+    double* mbuf = p.uni_G + ub;  // m(y) of the absorbed tile
+    if (tid < 64) {
+      const int i = tid >> 3, j = tid & 7;
+      const int qa = (i >> 2) * 2 + (j >> 2);
+      const int bq = qa == 0 ? g.bq[0] : qa == 1 ? g.bq[1] : qa == 2 ? g.bq[2] : g.bq[3];
+      const int r = g.R0 + i, c = g.C0 + j;
+      double mu = 0, F0 = 0;
+      if (bq >= 0) {
+        mu = p.mu[(int64_t)r * p.W + c];
+        F0 = p.alpha[(int64_t)r * p.W + c] / p.eps;
+      }
+      sh.mu[tid] = mu;
+      sh.F0orig[tid] = F0;
+      sh.F0[tid] = F0;
+    }
+    for (int yi = tid; yi < nslab * kSlab; yi += kSlab) nug[yi] = yi < U ? (float)p.uni_nu[ub + yi] : 0.f;
+    __syncthreads();
+    double massmu[4] = {0, 0, 0, 0};
+#pragma unroll
+    for (int k = 0; k < 64; k++) massmu[((k >> 3) >> 2) * 2 + ((k & 7) >> 2)] += sh.mu[k];
+    const double muJ = (massmu[0] + massmu[1]) + (massmu[2] + massmu[3]);
+    const double tol = p.err_tol * muJ;
+
+    int status = 0, loops_all = 0;
+    double lam = p.lam;
+    const int phases = p.safeguard ? 3 : 1;
+    bool converged = false, deferred = false;
+    const int xr = g.R0 + xg;
+
+    for (int phase = 0; phase < phases; phase++) {
+      if (phase == 1) {
+        lam = p.lam * 0.5;
+        if (tid < 64) sh.F0[tid] = sh.F0orig[tid] * 0.5;
+      } else if (phase == 2) {
+        lam = p.lam;
+        if (tid < 64 && sh.mu[tid] > 0) sh.F0[tid] = (sh.F0[tid] + log((double)sh.u[tid])) * 2.0;
+      }
+      if (tid < 64) sh.lup[tid] = 0.f;
+      if (tid == 0) cheb_reset(sh.cheb);
+      __syncthreads();
+      // ---- absorb: tile P = exp(Fmu - lam d2 - m(y)) of every slab to the buffer
+      auto absorb = [&]() {
+        if (tid < 64) {
+          sh.Fmu[tid] = sh.mu[tid] > 0 ? sh.F0[tid] + log(sh.mu[tid]) : -INFINITY;
+          sh.u[tid] = sh.mu[tid] > 0 ? 1.0f : 0.0f;
+        }
+        __syncthreads();
+        for (int sl = 0; sl < nslab; sl++)
+#pragma unroll
+        for (int th = 0; th < 2; th++) {  // four support points at a time
+          float P[8][4];
+#pragma unroll
+          for (int tt = 0; tt < 4; tt++) {
+            const int t = th * 4 + tt;
+            const int yi = sl * kSlab + yoff + t;
+            const bool valid = yi < U;
+            int r = 0, c = 0;
+            if (valid) split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
+            const int dr = r - xr;
+            const int dc0 = c - g.C0;
+            const double ldr = lam * (double)(dr * dr);
+            double mloc = -INFINITY;
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+              const int dc = dc0 - j;
+              const double e = sh.Fmu[xg * 8 + j] - (ldr + lam * (double)(dc * dc));
+              mloc = e > mloc ? e : mloc;
+            }
+#pragma unroll
+            for (int o = 1; o < 8; o <<= 1) {
+              const double v = __shfl_xor(mloc, o, 64);
+              mloc = v > mloc ? v : mloc;
+            }
+            if (!valid) mloc = 0.0;
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+              const int dc = dc0 - j;
+              const double e = sh.Fmu[xg * 8 + j] - (ldr + lam * (double)(dc * dc)) - mloc;
+              P[j][tt] = valid ? fast_exp2((float)(e * kLog2e)) : 0.0f;
+            }
+            if (xg == 0 && valid) mbuf[yi] = mloc;
+          }
+#pragma unroll
+          for (int j = 0; j < 8; j++)
+            *tile_at(tileb, sl, wave, 2 * j + th, lane) = make_float4(P[j][0], P[j][1], P[j][2], P[j][3]);
+        }
+        __syncthreads();
+      };
+      absorb();
+      int it = 0;
+      converged = false;
+      for (;;) {
+        it++;
+        // ---- per slab: Y-iteration, w, X-marginal partials
+        float uu[8], rx[8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+          uu[j] = sh.u[xg * 8 + j];
+          rx[j] = 0.f;
+        }
+        for (int sl = 0; sl < nslab; sl++) {
+          float P[8][8];
+#pragma unroll
+          for (int j = 0; j < 8; j++) {
+            const float4 a = *tile_at(tileb, sl, wave, 2 * j, lane);
+            const float4 b = *tile_at(tileb, sl, wave, 2 * j + 1, lane);
+            P[j][0] = a.x; P[j][1] = a.y; P[j][2] = a.z; P[j][3] = a.w;
+            P[j][4] = b.x; P[j][5] = b.y; P[j][6] = b.z; P[j][7] = b.w;
+          }
+          float Sp[8];
+#pragma unroll
+          for (int t = 0; t < 8; t++) {
+            float s = 0.f;
+#pragma unroll
+            for (int j = 0; j < 8; j++) s = fmaf(P[j][t], uu[j], s);
+            Sp[t] = s;
+          }
+          float a, b;
+          transpose_y(rd, xg, yg, Sp, &a, &b);
+          const int yi = sl * kSlab + yoff + xg;
+          const float S = a + b;
+          const float w = (yi < U && S > 0.f) ? nug[yi] / S : 0.f;
+          Sg[yi] = S;
+          sh.wl[wave][yg * 8 + xg] = w;
+          wave_sync();
+          float wv[8];
+#pragma unroll
+          for (int t = 0; t < 8; t++) wv[t] = sh.wl[wave][yg * 8 + t];
+#pragma unroll
+          for (int j = 0; j < 8; j++)
+#pragma unroll
+            for (int t = 0; t < 8; t++) rx[j] = fmaf(P[j][t], wv[t], rx[j]);
+          wave_sync();
+        }
+#pragma unroll
+        for (int j = 0; j < 8; j++) rd[tsw(xg, yg, j)] = rx[j];
+        wave_sync();
+        {
+          float s = 0.f;
+#pragma unroll
+          for (int k = 0; k < 8; k++) s += rd[tsw(xg, k, yg)];
+          sh.wred[wave][xg * 8 + yg] = s;
+        }
+        __syncthreads();
+        if (wave == 0) {
+          float r = 0.f;
+#pragma unroll
+          for (int w = 0; w < kSW; w++) r += sh.wred[w][lane];
+          const double mu = sh.mu[lane];
+          const float u = sh.u[lane];
+          double e = mu > 0 ? fabs((double)u * (double)r - mu) : 0.0;
+          e = wave_sum(e);
+          sh.r[lane] = r;
+          const bool go_on = !(e <= tol) && it < p.max_iter && (e == e);
+          if (lane == 0) {
+            double a0 = 0, b0 = 1, d0 = 0;
+            const bool acc0 = go_on && p.accel && cheb_next(sh.cheb, it, e, &a0, &b0, &d0);
+            sh.cacc = acc0;
+            sh.ca = a0;
+            sh.cb = b0;
+            sh.cd = d0;
+          }
+          wave_sync();
+          const bool acc = sh.cacc;
+          const double a = sh.ca, b = sh.cb, d = sh.cd;
+          const float un = mu > 0 ? (float)(mu / (double)r) : 0.f;
+          const float lu = mu > 0 ? fast_log2(u) : 0.f;
+          float unew = un;
+          if (acc && mu > 0) {
+            const float ln = fast_log2(un);
+            unew = fast_exp2((float)(a * lu + b * ln + d * sh.lup[lane]));
+          }
+          const bool bad = mu > 0 && !(unew > 9.357623e-14f && unew < 1.0686475e13f &&
+                                       un > 0.f && un < 3.0e38f);
+          const unsigned long long anyb = __ballot(bad);
+          if (go_on && anyb == 0ull) {
+            sh.u[lane] = unew;
+            sh.lup[lane] = lu;
+          }
+          if (lane == 0) {
+            sh.err = e;
+            sh.flag = go_on && anyb != 0ull;
+          }
+        }
+        __syncthreads();
+        const double err = sh.err;
+        if (err <= tol) {
+          converged = true;
+          break;
+        }
+        if (!(err == err) || it >= p.max_iter) break;
+        if (sh.flag) {
+          // exact X-iteration in the log domain over all slabs:
+          //   F0(x) = -LSE_y[G(y) + log nu_J(y) - C(x,y)],  G(y) = -(m(y) + log S(y))
+          double* dr8 = reinterpret_cast<double*>(rd);
+          double mm[8];
+#pragma unroll
+          for (int j = 0; j < 8; j++) mm[j] = -INFINITY;
+          for (int sl = 0; sl < nslab; sl++)
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+              const int yi = sl * kSlab + yoff + t;
+              if (yi < U) {
+                const float S = Sg[yi], nf = nug[yi];
+                if (S > 0.f && nf > 0.f) {
+                  int r, c;
+                  split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
+                  const int dr = r - xr;
+                  const double gl = -(mbuf[yi] + log((double)S)) + log((double)nf) -
+                                    lam * (double)(dr * dr);
+#pragma unroll
+                  for (int j = 0; j < 8; j++) {
+                    const int dc = c - (g.C0 + j);
+                    const double e = gl - lam * (double)(dc * dc);
+                    mm[j] = e > mm[j] ? e : mm[j];
+                  }
+                }
+              }
+            }
+#pragma unroll
+          for (int j = 0; j < 8; j++) {
+#pragma unroll
+            for (int o = 8; o < 64; o <<= 1) {
+              const double v = __shfl_xor(mm[j], o, 64);
+              mm[j] = v > mm[j] ? v : mm[j];
+            }
+          }
+          wave_sync();
+          if (yg == 0)
+#pragma unroll
+            for (int j = 0; j < 8; j++) dr8[xg * 8 + j] = mm[j];
+          __syncthreads();
+          if (tid < 64) {
+            double m = -INFINITY;
+            for (int w = 0; w < kSW; w++) {
+              const double v = reinterpret_cast<double*>(sh.red[w])[tid];
+              m = v > m ? v : m;
+            }
+            sh.mx[tid] = m;
+          }
+          __syncthreads();
+          double sj[8];
+#pragma unroll
+          for (int j = 0; j < 8; j++) sj[j] = 0.0;
+          for (int sl = 0; sl < nslab; sl++)
+#pragma unroll
+            for (int t = 0; t < 8; t++) {
+              const int yi = sl * kSlab + yoff + t;
+              if (yi < U) {
+                const float S = Sg[yi], nf = nug[yi];
+                if (S > 0.f && nf > 0.f) {
+                  int r, c;
+                  split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
+                  const int dr = r - xr;
+                  const double gl = -(mbuf[yi] + log((double)S)) + log((double)nf) -
+                                    lam * (double)(dr * dr);
+#pragma unroll
+                  for (int j = 0; j < 8; j++) {
+                    const int dc = c - (g.C0 + j);
+                    const double e = gl - lam * (double)(dc * dc) - sh.mx[xg * 8 + j];
+                    sj[j] += (double)fast_exp2((float)(e * kLog2e));
+                  }
+                }
+              }
+            }
+#pragma unroll
+          for (int j = 0; j < 8; j++) {
+#pragma unroll
+            for (int o = 8; o < 64; o <<= 1) sj[j] += __shfl_xor(sj[j], o, 64);
+          }
+          if (yg == 0)
+#pragma unroll
+            for (int j = 0; j < 8; j++) dr8[64 + xg * 8 + j] = sj[j];
+          __syncthreads();
+          if (tid < 64 && sh.mu[tid] > 0) {
+            double s = 0;
+            for (int w = 0; w < kSW; w++) s += reinterpret_cast<double*>(sh.red[w])[64 + tid];
+            const double Fh = -(sh.mx[tid] + log(s));
+            const double F = sh.F0[tid] + (double)fast_log2(sh.u[tid]) * kLn2;
+            const double Fp = sh.F0[tid] + (double)sh.lup[tid] * kLn2;
+            const double Fn = sh.cacc ? sh.ca * F + sh.cb * Fh + sh.cd * Fp : Fh;
+            sh.F0[tid] = Fn;
+            sh.lup[tid] = (float)((F - Fn) * kLog2e);
+          }
+          __syncthreads();
+          absorb();
+        }
+        if (it == p.newton_after && phase == 0) {
+          if (tid < 64)
+            p.defer_F[(int64_t)cell * 64 + tid] =
+                sh.mu[tid] > 0 ? sh.F0[tid] + log((double)sh.u[tid]) : 0.0;
+          if (tid == 0) {
+            const unsigned long long slot =
+                atomicAdd(reinterpret_cast<unsigned long long*>(&p.misc[3]), 1ull);
+            if (slot < (unsigned long long)p.n_cells) p.defer_list[slot] = cell;
+            p.r_loops[cell] = it;
+          }
+          deferred = true;
+          break;
+        }
+      }
+      if (deferred) break;
+      loops_all += it;
+      if (phase == 0) {
+        if (converged) break;
+        if (phases > 1) status |= 4;
+        continue;
+      }
+      if (phase == 1 && sh.err == sh.err) continue;  // always return to eps
+      break;
+    }
+    if (deferred) {
+      __syncthreads();
+      continue;
+    }
+    if (!converged) status |= (sh.err == sh.err) ? 1 : 2;
+
+    // ---- final: split of the last Y-iteration by basic cell, cost, objective,
+    // stashed per support point in the output region, then balanced and compacted
+    if (tid < 4) sh.out.cnt[tid] = 0;
+    double cost_acc = 0, obj_acc = 0;
+    {
+      float uu[8];
+#pragma unroll
+      for (int j = 0; j < 8; j++) uu[j] = sh.u[xg * 8 + j];
+      for (int sl = 0; sl < nslab; sl++) {
+        float P[8][8];
+#pragma unroll
+        for (int j = 0; j < 8; j++) {
+          const float4 a = *tile_at(tileb, sl, wave, 2 * j, lane);
+          const float4 b = *tile_at(tileb, sl, wave, 2 * j + 1, lane);
+          P[j][0] = a.x; P[j][1] = a.y; P[j][2] = a.z; P[j][3] = a.w;
+          P[j][4] = b.x; P[j][5] = b.y; P[j][6] = b.z; P[j][7] = b.w;
+        }
+        float sl_t, sl_b, sr_t, sr_b, c1, c2, v[8];
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+          float s = 0.f;
+#pragma unroll
+          for (int j = 0; j < 4; j++) s = fmaf(P[j][t], uu[j], s);
+          v[t] = s;
+        }
+        transpose_y(rd, xg, yg, v, &sl_t, &sl_b);
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+          float s = 0.f;
+#pragma unroll
+          for (int j = 4; j < 8; j++) s = fmaf(P[j][t], uu[j], s);
+          v[t] = s;
+        }
+        transpose_y(rd, xg, yg, v, &sr_t, &sr_b);
+#pragma unroll
+        for (int t = 0; t < 8; t++) {
+          const int yi = sl * kSlab + yoff + t;
+          int r = 0, c = 0;
+          if (yi < U) split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
+          const int dr = r - xr, dc0 = c - g.C0;
+          float s = 0.f;
+#pragma unroll
+          for (int j = 0; j < 8; j++) {
+            const int dc = dc0 - j;
+            s = fmaf((float)(dr * dr + dc * dc), P[j][t] * uu[j], s);
+          }
+          v[t] = s;
+        }
+        transpose_y(rd, xg, yg, v, &c1, &c2);
+        const int yi = sl * kSlab + yoff + xg;
+        if (yi < U) {
+          const int key = p.uni_key[ub + yi];
+          const double nuJ = p.uni_nu[ub + yi];
+          const double s0 = sl_t, s1 = sr_t, s2 = sl_b, s3 = sr_b;
+          const double S = (s0 + s1) + (s2 + s3);
+          const double vq[4] = {nuJ * (s0 / S), nuJ * (s1 / S), nuJ * (s2 / S), nuJ * (s3 / S)};
+          cost_acc += nuJ * ((double)(c1 + c2) / S) * (p.h * p.h);
+          const bool key_ok = (unsigned)key < (unsigned)(p.H * p.W);
+          if (nuJ > 0 && key_ok)
+            obj_acc += nuJ * (-(mbuf[yi] + log(S)) + log(nuJ) - log(p.nu[key])) - nuJ;
+#pragma unroll
+          for (int a = 0; a < 4; a++)
+            if (g.bq[a] >= 0) {
+              const int64_t at = obase + (int64_t)g.qidx[a] * U + yi;
+              p.ent_val[at] = vq[a];
+              p.ent_col[at] = key;
+            }
+        }
+        wave_sync();
+      }
+    }
+    __syncthreads();
+    balance_compact_chunked(p, g, obase, U, massmu, sh.out);
+    const double cost = block_sum_d(cost_acc, sh.out.red);
+    double objx = 0;
+    if (tid < 64 && sh.mu[tid] > 0) {
+      const double F = sh.F0[tid] + log((double)sh.u[tid]);
+      objx = (double)sh.u[tid] * (double)sh.r[tid] * F;
+    }
+    const double obj = block_sum_d(obj_acc + objx, sh.out.red);
+    if (tid == 0) {
+#pragma unroll
+      for (int a = 0; a < 4; a++)
+        if (g.bq[a] >= 0) {
+          p.row_off[g.bq[a]] = obase + (int64_t)g.qidx[a] * U;
+          p.row_len[g.bq[a]] = (int)min((long long)U, sh.out.cnt[a]);
+        }
+      p.r_cost[cell] = cost;
+      p.r_obj[cell] = p.eps * obj;
+      p.r_err[cell] = sh.err;
+      p.r_loops[cell] = loops_all;
+      p.r_status[cell] = status;
+      p.r_evals[cell] = (long long)loops_all * 16 * g.nq * U;
+    }
+    if (tid < 64 && sh.mu[tid] > 0) {
+      const int i = tid >> 3, j = tid & 7;
+      p.alpha[(int64_t)(g.R0 + i) * p.W + g.C0 + j] = p.eps * (sh.F0[tid] + log((double)sh.u[tid]));
+    }
+    __syncthreads();
+  }
+}
+
 // ------------------------------------------------------------ big-cell solver
 
 // Cells whose union exceeds the register capacity, and cells handed over by
@@ -970,6 +1534,7 @@ struct BigShared {
   double err, slope;
   int last;                // last active pixel (ground of the Laplacian system)
   int nact;                // active pixels (mu > 0)
+  int next;
   CellOutSh out;
 };
 
@@ -1017,7 +1582,11 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mod
   const bool deferred = mode == 1;
   const int count = deferred ? (int)p.misc[3] : p.bin_count[kNBins - 1];
   const double invW = 1.0 / p.W;
-  for (int ci = blockIdx.x; ci < count; ci += gridDim.x) {
+  for (;;) {
+    if (tid == 0) sh.next = atomicAdd(&p.queue[deferred ? kNBins : kNBins - 1], 1);
+    __syncthreads();
+    const int ci = sh.next;
+    if (ci >= count) break;
     const int cell = deferred ? p.defer_list[ci] : p.bin_list[(kNBins - 1) * p.n_cells + ci];
     const CellGeo g = load_geo(p, cell);
     const int U = p.cell_U[cell];
@@ -1382,75 +1951,7 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mod
       }
     }
     __syncthreads();
-    // balance: norms over the whole support, then per-y update and compaction
-    double nrm[4];
-    _Pragma("unroll") for (int a = 0; a < 4; a++) {
-      double s = 0;
-      if (g.bq[a] >= 0)
-        for (int yi = tid; yi < U; yi += kBigThreads) s += p.ent_val[obase + (int64_t)g.qidx[a] * U + yi];
-      nrm[a] = block_sum_d(s, sh.out.red);
-    }
-    if (tid == 0) {
-      double E = 0, D = 0;
-      _Pragma("unroll") for (int a = 0; a < 4; a++) {
-        double d = g.bq[a] >= 0 ? massmu[a] - nrm[a] : 0.0;
-        sh.out.dq[a] = d;
-        if (d < 0) E += -d;
-        if (d > 0) D += d;
-      }
-      double T = E < D ? E : D;
-      _Pragma("unroll") for (int a = 0; a < 4; a++)
-        sh.out.tq[a] = (T > 0 && sh.out.dq[a] < 0) ? T * (-sh.out.dq[a]) / (E * nrm[a]) : 0.0;
-      sh.out.E = T > 0 ? E : 0.0;
-      sh.out.D = T > 0 ? D : 0.0;
-    }
-    __syncthreads();
-    for (int y0 = 0; y0 < U; y0 += kBigThreads) {
-      const int yi = y0 + tid;
-      const bool own = yi < U;
-      double v[4] = {0, 0, 0, 0};
-      int key = 0;
-      if (own) {
-        _Pragma("unroll") for (int a = 0; a < 4; a++)
-          if (g.bq[a] >= 0) {
-            const int64_t at = obase + (int64_t)g.qidx[a] * U + yi;
-            v[a] = p.ent_val[at];
-            key = p.ent_col[at];
-          }
-        if (sh.out.D > 0) {
-          double R = 0;
-          _Pragma("unroll") for (int a = 0; a < 4; a++)
-            if (g.bq[a] >= 0 && sh.out.dq[a] < 0) {
-              const double rr = v[a] * sh.out.tq[a];
-              v[a] -= rr;
-              R += rr;
-            }
-          _Pragma("unroll") for (int a = 0; a < 4; a++)
-            if (g.bq[a] >= 0 && sh.out.dq[a] > 0) v[a] += R * sh.out.dq[a] / sh.out.D;
-        }
-      }
-      unsigned long long flags = 0;
-      if (own)
-        _Pragma("unroll") for (int a = 0; a < 4; a++)
-          if (g.bq[a] >= 0 && v[a] >= p.trunc && v[a] > 0.0) flags |= 1ull << (16 * a);
-      long long tot;
-      long long ex = block_excl_scan((long long)flags, sh.out.scan, &tot);
-      __syncthreads();  // every thread has read its chunk before any compacted write
-      if (own)
-        _Pragma("unroll") for (int a = 0; a < 4; a++)
-          if ((flags >> (16 * a)) & 1ull) {
-            const long long pos = sh.out.cnt[a] + ((ex >> (16 * a)) & 0xffffll);
-            if (pos < U) {
-              const int64_t at = obase + (int64_t)g.qidx[a] * U + pos;
-              p.ent_col[at] = key;
-              p.ent_val[at] = v[a];
-            }
-          }
-      __syncthreads();
-      if (tid == 0)
-        _Pragma("unroll") for (int a = 0; a < 4; a++) sh.out.cnt[a] += (tot >> (16 * a)) & 0xffffll;
-      __syncthreads();
-    }
+    balance_compact_chunked(p, g, obase, U, massmu, sh.out);
     const double cost = block_sum_d(cost_acc, sh.out.red);
     double objx = 0;
     if (tid < 64 && sh.mu[tid] > 0) {
@@ -1565,34 +2066,57 @@ __global__ __launch_bounds__(1024) void k_stats(HalfParams p, IterStatsDev* out)
 
 // ------------------------------------------------------------ launchers
 
-void launch_sweep(const HalfParams& p, hipStream_t st, int grid_cap, hipEvent_t* ev) {
-  int e = 0;
-  auto mark = [&]() {
-    if (ev) hipEventRecord(ev[e++], st);
+void launch_sweep(const HalfParams& p, const SweepStreams& s, int grid_cap, hipEvent_t* ev) {
+  auto pre = [&](int k, hipStream_t st) {
+    if (ev) hipEventRecord(ev[2 * k], st);
   };
-  mark();
+  auto post = [&](int k, hipStream_t st) {
+    if (ev) hipEventRecord(ev[2 * k + 1], st);
+  };
+  hipStream_t st = s.main;
+  pre(0, st);
   hipLaunchKernelGGL(k_scan_T, dim3(1), dim3(1024), 0, st, p);
-  mark();
+  post(0, st);
   const int g = p.n_cells < grid_cap ? p.n_cells : grid_cap;
+  pre(1, st);
   hipLaunchKernelGGL(k_union, dim3(g), dim3(kUnionThreads), 0, st, p);
-  mark();
+  post(1, st);
+  pre(2, st);
   hipLaunchKernelGGL(k_scan_out, dim3(1), dim3(1024), 0, st, p);
-  mark();
-  hipLaunchKernelGGL(k_solve_reg<1>, dim3(g), dim3(64), 0, st, p, 0);
-  mark();
-  hipLaunchKernelGGL(k_solve_reg<2>, dim3(g), dim3(128), 0, st, p, 1);
-  mark();
+  post(2, st);
+  // fork: the heaviest bins on their own streams, the light ones on main
+  hipEventRecord(s.fork, st);
+  for (int i = 0; i < 3; i++) hipStreamWaitEvent(s.aux[i], s.fork, 0);
+  const int gs = g < p.stream_wgs ? g : p.stream_wgs;  // one tile buffer per workgroup
+  pre(8, s.aux[0]);
+  if (gs > 0) hipLaunchKernelGGL(k_solve_stream, dim3(gs), dim3(kSlab), 0, s.aux[0], p);
+  post(8, s.aux[0]);
+  pre(9, s.aux[0]);
+  hipLaunchKernelGGL(k_solve_big, dim3(g), dim3(kBigThreads), 0, s.aux[0], p, 0);
+  post(9, s.aux[0]);
+  pre(7, s.aux[1]);
+  hipLaunchKernelGGL(k_solve_reg<16>, dim3(g), dim3(1024), 0, s.aux[1], p, 4);
+  post(7, s.aux[1]);
+  pre(6, s.aux[2]);
+  hipLaunchKernelGGL(k_solve_reg<8>, dim3(g), dim3(512), 0, s.aux[2], p, 3);
+  post(6, s.aux[2]);
+  pre(5, st);
   hipLaunchKernelGGL(k_solve_reg<4>, dim3(g), dim3(256), 0, st, p, 2);
-  mark();
-  hipLaunchKernelGGL(k_solve_reg<8>, dim3(g), dim3(512), 0, st, p, 3);
-  mark();
-  hipLaunchKernelGGL(k_solve_reg<16>, dim3(g), dim3(1024), 0, st, p, 4);
-  mark();
-  hipLaunchKernelGGL(k_solve_big, dim3(g), dim3(kBigThreads), 0, st, p, 0);
-  mark();
-  // cells handed over by the register solvers (count known on the device only)
+  post(5, st);
+  pre(4, st);
+  hipLaunchKernelGGL(k_solve_reg<2>, dim3(g), dim3(128), 0, st, p, 1);
+  post(4, st);
+  pre(3, st);
+  hipLaunchKernelGGL(k_solve_reg<1>, dim3(g), dim3(64), 0, st, p, 0);
+  post(3, st);
+  // join, then the cells handed over by the register solvers
+  for (int i = 0; i < 3; i++) {
+    hipEventRecord(s.join[i], s.aux[i]);
+    hipStreamWaitEvent(st, s.join[i], 0);
+  }
+  pre(10, st);
   hipLaunchKernelGGL(k_solve_big, dim3(g), dim3(kBigThreads), 0, st, p, 1);
-  mark();
+  post(10, st);
 }
 
 size_t sweep_max_static_lds() {
@@ -1607,9 +2131,10 @@ size_t sweep_max_static_lds() {
   return mx;
 }
 
-void launch_stats(const HalfParams& p, IterStatsDev* out, hipStream_t st, hipEvent_t ev_after) {
+void launch_stats(const HalfParams& p, IterStatsDev* out, hipStream_t st, hipEvent_t* ev2) {
+  if (ev2) hipEventRecord(ev2[0], st);
   hipLaunchKernelGGL(k_stats, dim3(1), dim3(1024), 0, st, p, out);
-  if (ev_after) hipEventRecord(ev_after, st);
+  if (ev2) hipEventRecord(ev2[1], st);
 }
 
 // ------------------------------------------------------------ setup kernels

@@ -90,7 +90,15 @@ struct dd_ctx {
   int64_t px_cap = 0;
   dd_iter_stats last{};
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  hipEvent_t kev[DD_N_KERNELS + 1] = {};
+  hipEvent_t kev[2 * DD_N_KERNELS] = {};
+  static_assert(DD_N_KERNELS == ddk::kNKernels, "kernel count of the ABI and the launcher");
+  ddk::SweepStreams ss{};
+  int* queue = nullptr;
+  int n_cu = 0;
+  int stream_wgs = 0;
+  float* stream_tile = nullptr;
+  float* stream_S = nullptr;
+  float* stream_nu = nullptr;
   int grid_cap = 2048;
 };
 
@@ -285,6 +293,10 @@ extern "C" void dd_free(dd_ctx* c) {
   hipFree(c->defer_list);
   hipFree(c->defer_F);
   hipFree(c->misc);
+  hipFree(c->queue);
+  hipFree(c->stream_tile);
+  hipFree(c->stream_S);
+  hipFree(c->stream_nu);
   hipFree(c->uni_key);
   hipFree(c->uni_nu);
   hipFree(c->uni_G);
@@ -295,6 +307,11 @@ extern "C" void dd_free(dd_ctx* c) {
   if (c->hscal) hipHostFree(c->hscal);
   if (c->ev0) hipEventDestroy(c->ev0);
   if (c->ev1) hipEventDestroy(c->ev1);
+  for (int i = 0; i < 3; i++) {
+    if (c->ss.aux[i]) hipStreamDestroy(c->ss.aux[i]);
+    if (c->ss.join[i]) hipEventDestroy(c->ss.join[i]);
+  }
+  if (c->ss.fork) hipEventDestroy(c->ss.fork);
   for (auto& e : c->kev)
     if (e) hipEventDestroy(e);
   delete c;
@@ -413,10 +430,20 @@ extern "C" dd_status dd_init(const double* mu, const double* nu, int H, int W, i
   if (dmalloc(&c->dscal, 8) != hipSuccess || hipHostMalloc((void**)&c->hscal, sizeof(double) * 8) != hipSuccess ||
       dmalloc(&c->dstats, 1) != hipSuccess ||
       hipHostMalloc((void**)&c->hstats, sizeof(IterStatsDev)) != hipSuccess ||
-      dmalloc(&c->misc, 8) != hipSuccess || dmalloc(&c->bin_count, ddk::kNBins) != hipSuccess)
+      dmalloc(&c->misc, 8) != hipSuccess || dmalloc(&c->bin_count, ddk::kNBins) != hipSuccess ||
+      dmalloc(&c->queue, 8) != hipSuccess)
     return bail(fail(c, DD_ENOMEM, "hipMalloc failed"));
   hipEventCreate(&c->ev0);
   hipEventCreate(&c->ev1);
+  // auxiliary streams of a sweep (default priority; ordered with the
+  // context's stream through events only)
+  c->ss.main = c->st;
+  if (hipEventCreateWithFlags(&c->ss.fork, hipEventDisableTiming) != hipSuccess)
+    return bail(fail(c, DD_EHIP, "event creation failed"));
+  for (int i = 0; i < 3; i++)
+    if (hipStreamCreateWithFlags(&c->ss.aux[i], hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->ss.join[i], hipEventDisableTiming) != hipSuccess)
+      return bail(fail(c, DD_EHIP, "stream creation failed"));
   if (c->opt.timing)
     for (auto& e : c->kev) hipEventCreate(&e);
   // validation of the finest images
@@ -439,6 +466,7 @@ extern "C" dd_status dd_init(const double* mu, const double* nu, int H, int W, i
       hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
     return bail(fail(c, DD_EHIP, "no HIP device"));
   if (n_cu > 0) c->grid_cap = n_cu * 8;
+  c->n_cu = n_cu > 0 ? n_cu : 64;
   {
     const size_t need = ddk::sweep_max_static_lds();
     if (need == 0 || need > (size_t)lds_max)
@@ -502,10 +530,34 @@ static HalfParams make_params(dd_ctx* c, int part) {
   p.r_status = c->r_status;
   p.r_evals = c->r_evals;
   p.misc = c->misc;
+  p.queue = c->queue;
+  p.stream_tile = c->stream_tile;
+  p.stream_S = c->stream_S;
+  p.stream_nu = c->stream_nu;
+  p.stream_wgs = c->stream_wgs;
   p.defer_list = c->defer_list;
   p.defer_F = c->defer_F;
   p.capE = c->capE;
   return p;
+}
+
+// Tile buffers of the streamed solver: one per workgroup, two workgroups per
+// compute unit at most (2 MiB each).
+static dd_status ensure_stream(dd_ctx* c, int n_cells) {
+  const int want = std::min(n_cells, 2 * c->n_cu);
+  if (want <= c->stream_wgs) return DD_OK;
+  hipFree(c->stream_tile);
+  hipFree(c->stream_S);
+  hipFree(c->stream_nu);
+  c->stream_tile = nullptr;
+  c->stream_S = nullptr;
+  c->stream_nu = nullptr;
+  c->stream_wgs = 0;
+  HIPCHK(c, dmalloc(&c->stream_tile, (size_t)want * ddk::kStreamTileFloats));
+  HIPCHK(c, dmalloc(&c->stream_S, (size_t)want * ddk::kStreamMaxU));
+  HIPCHK(c, dmalloc(&c->stream_nu, (size_t)want * ddk::kStreamMaxU));
+  c->stream_wgs = want;
+  return DD_OK;
 }
 
 extern "C" dd_status dd_half_iterate(dd_ctx* c, int part, dd_iter_stats* out) {
@@ -515,13 +567,16 @@ extern "C" dd_status dd_half_iterate(dd_ctx* c, int part, dd_iter_stats* out) {
   if (s) return s;
   s = ensure_union(c, c->nnz + 64);
   if (s) return s;
+  s = ensure_stream(c, c->cells[part].n);
+  if (s) return s;
   HalfParams p = make_params(c, part);
   HIPCHK(c, hipMemsetAsync(c->misc, 0, sizeof(long long) * 8, c->st));
+  HIPCHK(c, hipMemsetAsync(c->queue, 0, sizeof(int) * 8, c->st));
   HIPCHK(c, hipEventRecord(c->ev0, c->st));
   hipEvent_t* kev = c->opt.timing ? c->kev : nullptr;
-  ddk::launch_sweep(p, c->st, c->grid_cap, kev);
+  ddk::launch_sweep(p, c->ss, c->grid_cap, kev);
   HIPCHK(c, hipGetLastError());
-  ddk::launch_stats(p, c->dstats, c->st, kev ? kev[DD_N_KERNELS] : nullptr);
+  ddk::launch_stats(p, c->dstats, c->st, kev ? kev + 2 * (DD_N_KERNELS - 1) : nullptr);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipEventRecord(c->ev1, c->st));
   HIPCHK(c, hipMemcpyAsync(c->hstats, c->dstats, sizeof(IterStatsDev), hipMemcpyDeviceToHost, c->st));
@@ -553,7 +608,7 @@ extern "C" dd_status dd_half_iterate(dd_ctx* c, int part, dd_iter_stats* out) {
   if (kev)
     for (int k = 0; k < DD_N_KERNELS; k++) {
       float t = 0;
-      hipEventElapsedTime(&t, kev[k], kev[k + 1]);
+      hipEventElapsedTime(&t, kev[2 * k], kev[2 * k + 1]);
       r.ms_kernel[k] = t;
     }
   c->nnz = d.nnz;

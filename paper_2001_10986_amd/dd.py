@@ -31,10 +31,10 @@ class Options(C.Structure):
                 ("newton_after", C.c_int), ("inputs_on_device", C.c_int), ("timing", C.c_int), ("stream", C.c_void_p)]
 
 
-N_KERNELS, N_BINS = 11, 6
+N_KERNELS, N_BINS = 12, 7
 KERNEL_NAMES = ["scan_cells", "union", "scan_out_bins", "solve_reg_1w", "solve_reg_2w",
-                "solve_reg_4w", "solve_reg_8w", "solve_reg_16w", "solve_big", "solve_newton",
-                "stats"]
+                "solve_reg_4w", "solve_reg_8w", "solve_reg_16w", "solve_stream", "solve_big",
+                "solve_newton", "stats"]
 
 
 class IterStats(C.Structure):
@@ -42,8 +42,8 @@ class IterStats(C.Structure):
                 ("n_failed", C.c_int), ("n_safeguard", C.c_int), ("n_newton", C.c_int),
                 ("nnz", C.c_int64), ("entry_evals", C.c_int64), ("cost", C.c_double),
                 ("obj", C.c_double), ("err_x", C.c_double), ("ms", C.c_double),
-                ("ms_kernel", C.c_double * N_KERNELS), ("cells_bin", C.c_int * 6),
-                ("evals_bin", C.c_int64 * 6)]
+                ("ms_kernel", C.c_double * N_KERNELS), ("cells_bin", C.c_int * N_BINS),
+                ("evals_bin", C.c_int64 * N_BINS)]
 
     def as_dict(self):
         return {k: (list(getattr(self, k)) if k in ("ms_kernel", "cells_bin", "evals_bin")
@@ -55,8 +55,8 @@ class RunStats(C.Structure):
                 ("loops_total", C.c_int64), ("entry_evals", C.c_int64), ("n_failed", C.c_int),
                 ("n_safeguard", C.c_int), ("n_newton", C.c_int), ("nnz_max", C.c_int64),
                 ("ms_total", C.c_double), ("ms_kernel", C.c_double * N_KERNELS),
-                ("launches_bin", C.c_int * 6),
-                ("evals_bin", C.c_int64 * 6)]
+                ("launches_bin", C.c_int * N_BINS),
+                ("evals_bin", C.c_int64 * N_BINS)]
 
     def as_dict(self):
         return {k: (list(getattr(self, k)) if k in ("ms_kernel", "launches_bin", "evals_bin")

@@ -48,7 +48,7 @@ def _row_masses(e, nb):
 
 @pytest.mark.parametrize("N", [16, 32, 64])
 def test_half_iterations_match_oracle(dd, ddo, N):
-    # 16: 4-wave bin; 32: 16- and 8-wave bins; 64: the log-domain big-cell solver (U = 4096)
+    # 16: 4-wave bin; 32: 16- and 8-wave bins; 64: the streamed solver (U = 4096)
     mu, nu = datagen.small_pair(N, 3, seed=5)
     eps = 4.0 / N ** 2
     g = dd.Problem(mu, nu, [(0, eps, 4)], s=4, n_levels=1)
@@ -214,3 +214,20 @@ def test_newton_fallback_matches_oracle(dd, ddo, N, K):
         rm_g = _row_masses(eg, info["n_basic"])
         rm_o = _row_masses(o.export(), info["n_basic"])
         assert np.abs(rm_g - rm_o).max() < 1e-15 * N * N + 1e-14
+
+
+def test_log_domain_solver_matches_oracle(dd, ddo):
+    # 128x128 from the product coupling: every union is the whole image
+    # (U = 16384 > 8192), which only the log-domain solver takes
+    N = 128
+    mu, nu = datagen.small_pair(N, 3, seed=8)
+    eps = 0.05
+    g = dd.Problem(mu, nu, [(0, eps, 1)], s=4, n_levels=1)
+    o = ddo.Oracle(mu, nu, s=4, n_levels=1, eps=eps)
+    sg = g.half_iterate(0)
+    so = o.half_iterate(0)
+    assert sg["cells_bin"][6] == sg["n_cells"] and sg["n_failed"] == 0
+    assert abs(sg["cost"] - so["cost"]) <= 1e-7 * so["cost"]
+    assert abs(sg["loops_total"] - so["loops_total"]) <= 0.02 * so["loops_total"] + 2
+    bg, bo = g.basic_marginals(), o.basic_marginals()
+    assert np.abs(bg - bo).max() < 1e-6 * bg.sum(axis=1).max()
