@@ -26,6 +26,9 @@ def main():
     ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3])
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the oracle leg (0 disables it)")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB 5 times (calibrates the HBM "
+                         "byte counters of a profiler) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -34,6 +37,17 @@ def main():
 
     import numpy as np
     import torch
+
+    if args.copy_probe > 0:
+        torch.cuda.set_device(0)
+        n = args.copy_probe * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": 4 * n, "launches": 5}))
+        return
 
     from paper_2001_10986_amd import datagen, dd
 

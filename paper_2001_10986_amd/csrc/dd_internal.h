@@ -78,7 +78,13 @@ constexpr int kNKernels = 12;  // scan, union, scan_out, 5 register, streamed, b
 
 // Kernel launchers (all asynchronous).  ev: nullptr, or 2*kNKernels events;
 // ev[2k] and ev[2k+1] are recorded around kernel k on the stream it runs on.
-void launch_sweep(const HalfParams& p, const SweepStreams& s, int grid_cap, hipEvent_t* ev);
+// Workgroups per solver launch (each loops over its bin's work queue).
+struct SweepGrid {
+  int bin[kNBins];   // solver launches of bins 0..kNBins-1
+  int newton;        // the launch for the cells handed over to Newton steps
+  int other;         // union kernel
+};
+void launch_sweep(const HalfParams& p, const SweepStreams& s, const SweepGrid& gr, hipEvent_t* ev);
 void launch_stats(const HalfParams& p, IterStatsDev* out, hipStream_t st, hipEvent_t* ev2);
 size_t sweep_max_static_lds();
 
@@ -89,7 +95,9 @@ void launch_product_init(const int* ypos, int nzy, const double* nu, const doubl
                          int n_basic, int* col, double* val, int64_t* row_off, int* row_len,
                          hipStream_t st);
 
-// Diagnostics: out[0] = sum |sum_i nu_i - nu|, out[1] = sum_i | |nu_i| - |mu_i| |, out[2] = nnz
+// Diagnostics: out[0] = sum |sum_i nu_i - nu|, out[1] = sum_i | |nu_i| - |mu_i| |, out[2] = nnz.
+// scratch_px holds H*W + 3*kDiagBlocks doubles.
+constexpr int kDiagBlocks = 256;
 void launch_diag(const int64_t* row_off, const int* row_len, const int* col, const double* val,
                  const double* mu, const double* nu, int H, int W, int bw, int n_basic,
                  double* scratch_px, double* out3, hipStream_t st);

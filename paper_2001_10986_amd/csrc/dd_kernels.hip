@@ -57,6 +57,33 @@ DEVI T wave_min(T v) {
   }
   return v;
 }
+// Wave-wide sums through DPP lane moves (a fixed tree: quad swaps, row
+// rotations, row broadcasts; the total lands in lane 63 and is read back as a
+// uniform value).  Cheaper than the LDS crossbar behind __shfl_xor.
+template <int CTRL>
+DEVI int dpp_mov0(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xf, 0xf, false);
+}
+template <int CTRL>
+DEVI double dpp_d(double v) {
+  const long long q = __builtin_bit_cast(long long, v);
+  const int lo = dpp_mov0<CTRL>((int)(q & 0xffffffffll));
+  const int hi = dpp_mov0<CTRL>((int)(q >> 32));
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+DEVI double wave_sum_dpp(double v) {
+  v += dpp_d<0xb1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_d<0x4e>(v);   // quad_perm [2,3,0,1]
+  v += dpp_d<0x124>(v);  // row_ror:4
+  v += dpp_d<0x128>(v);  // row_ror:8
+  v += dpp_d<0x142>(v);  // row_bcast:15
+  v += dpp_d<0x143>(v);  // row_bcast:31
+  const long long q = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(q & 0xffffffffll), 63);
+  const int hi = __builtin_amdgcn_readlane((int)(q >> 32), 63);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
 template <typename T>
 DEVI T wave_incl_scan(T v, int lane) {
 #pragma unroll
@@ -501,6 +528,7 @@ DEVI void balance_compact_chunked(const HalfParams& p, const CellGeo& g, int64_t
 // calling wave runs the rule on the same values, so the decision is uniform.
 struct ChebState {
   double rho, omega;
+  double sig2, gam, rmax;  // sigma^2, gamma and the abandon threshold of the current run
   double hist[17];
   int k, kstart, pstart, att;
 };
@@ -518,14 +546,22 @@ DEVI void cheb_reset(ChebState& c) {
 // loops estimate rho from the error decay over the last 8 loops (at least 16
 // plain loops after a (re)start); a Chebyshev run that decays slower than
 // the square root of its promised rate over 16 loops is abandoned for plain
-// loops; at most four runs per solve and rho <= 0.9999.
+// loops; at most four runs per solve and rho <= 0.9999.  The constants of a
+// run (sigma^2 = (rho/(2-rho))^2, gamma = 2/(2-rho), the threshold) are
+// computed once when it starts, so an accelerated loop costs one division.
+// Safe to run in every lane of a wave on the same state (same values written).
 DEVI bool cheb_next(ChebState& c, int it, double err, double* a, double* b, double* d) {
   c.hist[it % 17] = err;
   if (c.rho < 0) {
     if (it - c.pstart >= 16 && c.att < 4) {
-      const double r = fast_exp2(fast_log2((float)(err / c.hist[(it - 8) % 17])) * 0.125f);
-      if (r > 0.8) {
-        c.rho = r < 0.9999 ? r : 0.9999;
+      const float r = fast_exp2(fast_log2((float)err / (float)c.hist[(it - 8) % 17]) * 0.125f);
+      if (r > 0.8f) {
+        const double rho = r < 0.9999f ? (double)r : 0.9999;
+        const double sig = rho / (2 - rho), sq = sqrt(1 - rho);
+        c.rho = rho;
+        c.sig2 = sig * sig;
+        c.gam = 2 / (2 - rho);
+        c.rmax = sqrt((1 - sq) / (1 + sq));
         c.k = 0;
         c.kstart = it;
         c.att++;
@@ -534,24 +570,22 @@ DEVI bool cheb_next(ChebState& c, int it, double err, double* a, double* b, doub
     return false;
   }
   if (it - c.kstart >= 16 && (it - c.kstart) % 16 == 0) {
-    const double robs = fast_exp2(fast_log2((float)(err / c.hist[(it - 16) % 17])) * 0.0625f);
-    const double sq = sqrt(1 - c.rho), cexp = (1 - sq) / (1 + sq);
-    if (robs > sqrt(cexp)) {
+    const float robs = fast_exp2(fast_log2((float)err / (float)c.hist[(it - 16) % 17]) * 0.0625f);
+    if (robs > c.rmax) {
       c.rho = -1;
       c.pstart = it;
       return false;
     }
   }
-  const double sigma = c.rho / (2 - c.rho), gamma = 2 / (2 - c.rho);
   if (c.k == 0)
     c.omega = 1;
   else if (c.k == 1)
-    c.omega = 1 / (1 - sigma * sigma / 2);
+    c.omega = 1 / (1 - c.sig2 / 2);
   else
-    c.omega = 1 / (1 - sigma * sigma * c.omega / 4);
+    c.omega = 1 / (1 - c.sig2 * c.omega / 4);
   c.k++;
-  *a = c.omega * (1 - gamma);
-  *b = c.omega * gamma;
+  *a = c.omega * (1 - c.gam);
+  *b = c.omega * c.gam;
   *d = 1 - c.omega;
   return true;
 }
@@ -577,19 +611,14 @@ DEVI bool cheb_next(ChebState& c, int it, double err, double* a, double* b, doub
 template <int NW>
 struct RegShared {
   double F0[64], Fmu[64], mu[64], F0orig[64], mx[64];
-  float u[64], r[64];
+  float uw[NW][64];           // per-wave copy of the scaling u (every wave runs the X-update)
+  float lupx[64];             // broadcast of the previous log2-scaling after an exact step
   float red[NW][512];         // per-wave transposition scratch (also FP64 scratch)
-  float wred[NW][64];         // per-wave X partials
-  float w[NW * 64];
-  float S[NW * 64];
+  float wred[2][NW][64];      // per-wave X partials, double-buffered by loop parity
+  float w[NW * 64];           // w(y) = nu_J(y) / S(y)
   float nuf[NW * 64];
   int yrc[NW * 64];           // support point (row << 16 | col)
-  float lup[64];              // log2 of the previous iterate's scaling (relative to F0)
-  ChebState cheb;
-  double ca, cb, cd;          // weights of the pending accelerated step
-  int cacc;
-  double err;
-  int flag;
+  ChebState cheb[NW];         // per-wave copy of the acceleration state
   int next;
   CellOutSh out;
 };
@@ -616,6 +645,56 @@ DEVI void transpose_y(float* rd, int xg, int yg, const float v[8], float* top, f
   *bot = b;
 }
 
+DEVI double readlane0_d(double v) {
+  const long long q = __builtin_bit_cast(long long, v);
+  const int lo = __builtin_amdgcn_readlane((int)(q & 0xffffffffll), 0);
+  const int hi = __builtin_amdgcn_readlane((int)(q >> 32), 0);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+// The X-update of one loop, run by every wave on the same data so that all
+// waves take the same decisions without a second block barrier (lane = x):
+// the X-marginal r = sum of the per-wave partials, the stopping error, the
+// acceleration weights and the new scaling (written to this wave's copy).
+struct XUpdate {
+  float r;
+  double err;
+  bool go_on, flag, acc;
+  double a, b, d;
+};
+
+DEVI XUpdate x_update(float r, double mu, float u, float* lup, float* unew_out, double tol,
+                      int it, int max_iter, int accel, ChebState& cheb, int lane) {
+  XUpdate o;
+  o.r = r;
+  const double e = wave_sum_dpp(mu > 0 ? fabs((double)u * (double)r - mu) : 0.0);
+  o.err = e;
+  o.go_on = !(e <= tol) && it < max_iter && (e == e);
+  double a0 = 0, b0 = 1, d0 = 0;
+  int acc0 = 0;
+  if (lane == 0 && o.go_on && accel) acc0 = cheb_next(cheb, it, e, &a0, &b0, &d0);
+  o.acc = __builtin_amdgcn_readlane(acc0, 0) != 0;
+  o.a = readlane0_d(a0);
+  o.b = readlane0_d(b0);
+  o.d = readlane0_d(d0);
+  const float muf = (float)mu;
+  const float un = mu > 0 ? muf / r : 0.f;
+  const float lu = mu > 0 ? fast_log2(u) : 0.f;
+  float unew = un;
+  if (o.acc && mu > 0) unew = fast_exp2((float)(o.a * lu + o.b * fast_log2(un) + o.d * *lup));
+  const bool bad = mu > 0 && !(unew > 9.357623e-14f && unew < 1.0686475e13f && un > 0.f &&
+                               un < 3.0e38f);
+  const unsigned long long anyb = __ballot(bad);
+  o.flag = o.go_on && anyb != 0ull;
+  if (o.go_on && anyb == 0ull) {
+    *unew_out = unew;
+    *lup = lu;
+  } else {
+    *unew_out = u;
+  }
+  return o;
+}
+
 template <int NW>
 __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
   __shared__ RegShared<NW> sh;
@@ -625,6 +704,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
   const int count = p.bin_count[bin];
   const double invW = 1.0 / p.W;
   float* rd = sh.red[wave];
+  float* uw = sh.uw[wave];
   for (;;) {
     // next cell of this bin (a work queue, so that slow cells do not hold up
     // the cells behind them)
@@ -670,12 +750,15 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
     for (int k = 0; k < 64; k++) massmu[((k >> 3) >> 2) * 2 + ((k & 7) >> 2)] += sh.mu[k];
     const double muJ = (massmu[0] + massmu[1]) + (massmu[2] + massmu[3]);
     const double tol = p.err_tol * muJ;
+    const double mux = sh.mu[lane];  // this lane's pixel in the X-update
 
     float P[8][8];
     int status = 0, loops_all = 0;
     double lam = p.lam;
     const int phases = p.safeguard ? 3 : 1;
     bool converged = false, deferred = false;
+    double err_last = 0;
+    float r_last = 0.f;
     const int xr = g.R0 + xg;  // pixel row of the lane's 8 pixels
 
     for (int phase = 0; phase < phases; phase++) {
@@ -684,17 +767,15 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
         if (tid < 64) sh.F0[tid] = sh.F0orig[tid] * 0.5;
       } else if (phase == 2) {  // back to eps from the 2*eps solution
         lam = p.lam;
-        if (tid < 64 && sh.mu[tid] > 0) sh.F0[tid] = (sh.F0[tid] + log((double)sh.u[tid])) * 2.0;
+        if (tid < 64 && sh.mu[tid] > 0) sh.F0[tid] = (sh.F0[tid] + log((double)uw[tid])) * 2.0;
       }
-      if (tid < 64) sh.lup[tid] = 0.f;
-      if (tid == 0) cheb_reset(sh.cheb);
+      float lup = 0.f;  // log2 of the previous iterate's scaling (relative to F0), lane = x
+      if (lane == 0) cheb_reset(sh.cheb[wave]);
       __syncthreads();
       // ---- absorb: P = exp(Fmu - lam d2 - m(y)) with Fmu = F0 + log mu
       auto absorb = [&]() {
-          if (tid < 64) {
-            sh.Fmu[tid] = sh.mu[tid] > 0 ? sh.F0[tid] + log(sh.mu[tid]) : -INFINITY;
-            sh.u[tid] = sh.mu[tid] > 0 ? 1.0f : 0.0f;
-          }
+          if (tid < 64) sh.Fmu[tid] = sh.mu[tid] > 0 ? sh.F0[tid] + log(sh.mu[tid]) : -INFINITY;
+          uw[lane] = mux > 0 ? 1.0f : 0.0f;
           __syncthreads();
 #pragma unroll
           for (int t = 0; t < 8; t++) {
@@ -732,11 +813,12 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
       converged = false;
       for (;;) {
         it++;
+        float (*wred)[64] = sh.wred[it & 1];
         // ---- Y-iteration: S(y) = sum_x P u, w = nu_J / S
         {
           float uu[8], Sp[8];
 #pragma unroll
-          for (int j = 0; j < 8; j++) uu[j] = sh.u[xg * 8 + j];
+          for (int j = 0; j < 8; j++) uu[j] = uw[xg * 8 + j];
 #pragma unroll
           for (int t = 0; t < 8; t++) {
             float s = 0.f;
@@ -748,7 +830,6 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
           transpose_y(rd, xg, yg, Sp, &a, &b);
           const float s = a + b;
           const int yi = ybase + xg;
-          sh.S[yi] = s;
           sh.w[yi] = s > 0.f ? sh.nuf[yi] / s : 0.f;
         }
         wave_sync();
@@ -771,73 +852,43 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
           float s = 0.f;
 #pragma unroll
           for (int k = 0; k < 8; k++) s += rd[tsw(xg, k, yg)];
-          sh.wred[wave][xg * 8 + yg] = s;
+          wred[wave][xg * 8 + yg] = s;
         }
         __syncthreads();
-        if (wave == 0) {
-          float r = 0.f;
+        // ---- X-update in every wave: plain u = mu/r, or the accelerated
+        // combination of the log-scalings of the current, plain-next and
+        // previous iterate; identical in all waves
+        float r = 0.f;
 #pragma unroll
-          for (int w = 0; w < NW; w++) r += sh.wred[w][lane];
-          const double mu = sh.mu[lane];
-          const float u = sh.u[lane];
-          double e = mu > 0 ? fabs((double)u * (double)r - mu) : 0.0;
-          e = wave_sum(e);
-          sh.r[lane] = r;
-          const bool go_on = !(e <= tol) && it < p.max_iter && (e == e);
-          // X-iteration: plain u = mu/r, or the accelerated combination of the
-          // log-scalings (relative to F0) of the current, plain-next and previous iterate
-          if (lane == 0) {
-            double a0 = 0, b0 = 1, d0 = 0;
-            const bool acc0 = go_on && p.accel && cheb_next(sh.cheb, it, e, &a0, &b0, &d0);
-            sh.cacc = acc0;
-            sh.ca = a0;
-            sh.cb = b0;
-            sh.cd = d0;
-          }
-          wave_sync();
-          const bool acc = sh.cacc;
-          const double a = sh.ca, b = sh.cb, d = sh.cd;
-          const float un = mu > 0 ? (float)(mu / (double)r) : 0.f;
-          const float lu = mu > 0 ? fast_log2(u) : 0.f;
-          float unew = un;
-          if (acc && mu > 0) {
-            const float ln = fast_log2(un);
-            unew = fast_exp2((float)(a * lu + b * ln + d * sh.lup[lane]));
-          }
-          const bool bad = mu > 0 && !(unew > 9.357623e-14f && unew < 1.0686475e13f &&
-                                       un > 0.f && un < 3.0e38f);
-          const unsigned long long anyb = __ballot(bad);
-          if (go_on && anyb == 0ull) {
-            sh.u[lane] = unew;
-            sh.lup[lane] = lu;
-          }
-          if (lane == 0) {
-            sh.err = e;
-            sh.flag = go_on && anyb != 0ull;
-          }
-        }
-        __syncthreads();
-        const double err = sh.err;
-        if (err <= tol) {
+        for (int w = 0; w < NW; w++) r += wred[w][lane];
+        float unew;
+        const XUpdate xu = x_update(r, mux, uw[lane], &lup, &unew, tol, it, p.max_iter, p.accel,
+                                    sh.cheb[wave], lane);
+        err_last = xu.err;
+        r_last = r;
+        if (xu.err <= tol) {
           converged = true;
           break;
         }
-        if (!(err == err) || it >= p.max_iter) break;
-        if (sh.flag) {
+        if (!xu.go_on) break;  // cap or non-finite
+        uw[lane] = unew;       // own copy: read by this wave only
+        if (xu.flag) {
           // exact X-iteration in the log domain:
-          //   F0(x) = -LSE_y[G(y) + log nu_J(y) - C(x,y)],  G(y) = -(m(y) + log S(y))
-          double* dr8 = reinterpret_cast<double*>(rd);  // 288 doubles per wave
+          //   F0(x) = -LSE_y[G(y) + log nu_J(y) - C(x,y)],  G(y) = -(m(y) + log S(y)),
+          // with S(y) = nu_J(y) / w(y) of this loop's Y-iteration
+          __syncthreads();  // every wave is done with its partials
+          double* dr8 = reinterpret_cast<double*>(rd);  // 256 doubles per wave
 #pragma unroll
           for (int j = 0; j < 8; j++) {
             double mm = -INFINITY;
 #pragma unroll
             for (int t = 0; t < 8; t++) {
               const int yi = ybase + t;
-              const float S = sh.S[yi], nf = sh.nuf[yi];
-              if (yi < U && S > 0.f && nf > 0.f) {
+              const float wy = sh.w[yi], nf = sh.nuf[yi];
+              if (yi < U && wy > 0.f && nf > 0.f) {
                 const int rc = sh.yrc[yi];
                 const int dr = (rc >> 16) - xr, dc = (rc & 0xffff) - (g.C0 + j);
-                const double e = -(mbuf[yi] + log((double)S)) + log((double)nf) -
+                const double e = -(mbuf[yi] + log((double)(nf / wy))) + log((double)nf) -
                                  lam * (double)(dr * dr + dc * dc);
                 mm = e > mm ? e : mm;
               }
@@ -866,11 +917,11 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
 #pragma unroll
             for (int t = 0; t < 8; t++) {
               const int yi = ybase + t;
-              const float S = sh.S[yi], nf = sh.nuf[yi];
-              if (yi < U && S > 0.f && nf > 0.f) {
+              const float wy = sh.w[yi], nf = sh.nuf[yi];
+              if (yi < U && wy > 0.f && nf > 0.f) {
                 const int rc = sh.yrc[yi];
                 const int dr = (rc >> 16) - xr, dc = (rc & 0xffff) - (g.C0 + j);
-                const double e = -(mbuf[yi] + log((double)S)) + log((double)nf) -
+                const double e = -(mbuf[yi] + log((double)(nf / wy))) + log((double)nf) -
                                  lam * (double)(dr * dr + dc * dc) - mm;
                 s += (double)fast_exp2((float)(e * kLog2e));
               }
@@ -880,17 +931,23 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
             if (yg == 0) dr8[64 + xg * 8 + j] = s;
           }
           __syncthreads();
-          if (tid < 64 && sh.mu[tid] > 0) {
-            double s = 0;
-            for (int w = 0; w < NW; w++) s += reinterpret_cast<double*>(sh.red[w])[64 + tid];
-            const double Fh = -(sh.mx[tid] + log(s));
-            const double F = sh.F0[tid] + (double)fast_log2(sh.u[tid]) * kLn2;
-            const double Fp = sh.F0[tid] + (double)sh.lup[tid] * kLn2;
-            const double Fn = sh.cacc ? sh.ca * F + sh.cb * Fh + sh.cd * Fp : Fh;
-            sh.F0[tid] = Fn;
-            sh.lup[tid] = (float)((F - Fn) * kLog2e);
+          if (tid < 64) {
+            float lp = 0.f;
+            if (sh.mu[tid] > 0) {
+              double s = 0;
+              for (int w = 0; w < NW; w++) s += reinterpret_cast<double*>(sh.red[w])[64 + tid];
+              const double Fh = -(sh.mx[tid] + log(s));
+              // uw was left unchanged by x_update on this path
+              const double F = sh.F0[tid] + (double)fast_log2(uw[tid]) * kLn2;
+              const double Fp = sh.F0[tid] + (double)lup * kLn2;
+              const double Fn = xu.acc ? xu.a * F + xu.b * Fh + xu.d * Fp : Fh;
+              sh.F0[tid] = Fn;
+              lp = (float)((F - Fn) * kLog2e);
+            }
+            sh.lupx[tid] = lp;
           }
           __syncthreads();
+          lup = sh.lupx[lane];
           absorb();
         }
         if (it == p.newton_after && phase == 0) {
@@ -898,7 +955,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
           // F0 + log u; the stored potential (alpha) stays for the safeguard
           if (tid < 64)
             p.defer_F[(int64_t)cell * 64 + tid] =
-                sh.mu[tid] > 0 ? sh.F0[tid] + log((double)sh.u[tid]) : 0.0;
+                sh.mu[tid] > 0 ? sh.F0[tid] + log((double)uw[tid]) : 0.0;
           if (tid == 0) {
             const unsigned long long slot =
                 atomicAdd(reinterpret_cast<unsigned long long*>(&p.misc[3]), 1ull);
@@ -909,6 +966,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
           break;
         }
       }
+      __syncthreads();  // every wave has left the loop before the tile or F0 change
       if (deferred) break;
       loops_all += it;
       if (phase == 0) {
@@ -916,21 +974,18 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
         if (phases > 1) status |= 4;
         continue;
       }
-      if (phase == 1 && sh.err == sh.err) continue;  // always return to eps
+      if (phase == 1 && err_last == err_last) continue;  // always return to eps
       break;
     }
-    if (deferred) {
-      __syncthreads();
-      continue;
-    }
-    if (!converged) status |= (sh.err == sh.err) ? 1 : 2;
+    if (deferred) continue;
+    if (!converged) status |= (err_last == err_last) ? 1 : 2;
 
     // ---- final: split of the last Y-iteration by basic cell, cost, objective
     float sl_t, sl_b, sr_t, sr_b, cp;
     {
       float uu[8], v[8];
 #pragma unroll
-      for (int j = 0; j < 8; j++) uu[j] = sh.u[xg * 8 + j];
+      for (int j = 0; j < 8; j++) uu[j] = uw[xg * 8 + j];
 #pragma unroll
       for (int t = 0; t < 8; t++) {
         float s = 0.f;
@@ -985,8 +1040,8 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
     const double cost = block_sum_d(cost_y, sh.out.red);
     double objx = 0;
     if (tid < 64 && sh.mu[tid] > 0) {
-      const double F = sh.F0[tid] + log((double)sh.u[tid]);
-      objx = (double)sh.u[tid] * (double)sh.r[tid] * F;
+      const double F = sh.F0[tid] + log((double)uw[tid]);
+      objx = (double)uw[tid] * (double)r_last * F;
     }
     const double obj = block_sum_d(obj_y + objx, sh.out.red);
     if (tid < 4) sh.out.cnt[tid] = 0;
@@ -1001,14 +1056,14 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
         }
       p.r_cost[cell] = cost;
       p.r_obj[cell] = p.eps * obj;
-      p.r_err[cell] = sh.err;
+      p.r_err[cell] = err_last;
       p.r_loops[cell] = loops_all;
       p.r_status[cell] = status;
       p.r_evals[cell] = (long long)loops_all * 16 * g.nq * U;
     }
     if (tid < 64 && sh.mu[tid] > 0) {
       const int i = tid >> 3, j = tid & 7;
-      p.alpha[(int64_t)(g.R0 + i) * p.W + g.C0 + j] = p.eps * (sh.F0[tid] + log((double)sh.u[tid]));
+      p.alpha[(int64_t)(g.R0 + i) * p.W + g.C0 + j] = p.eps * (sh.F0[tid] + log((double)uw[tid]));
     }
     __syncthreads();
   }
@@ -2066,7 +2121,7 @@ __global__ __launch_bounds__(1024) void k_stats(HalfParams p, IterStatsDev* out)
 
 // ------------------------------------------------------------ launchers
 
-void launch_sweep(const HalfParams& p, const SweepStreams& s, int grid_cap, hipEvent_t* ev) {
+void launch_sweep(const HalfParams& p, const SweepStreams& s, const SweepGrid& gr, hipEvent_t* ev) {
   auto pre = [&](int k, hipStream_t st) {
     if (ev) hipEventRecord(ev[2 * k], st);
   };
@@ -2077,9 +2132,8 @@ void launch_sweep(const HalfParams& p, const SweepStreams& s, int grid_cap, hipE
   pre(0, st);
   hipLaunchKernelGGL(k_scan_T, dim3(1), dim3(1024), 0, st, p);
   post(0, st);
-  const int g = p.n_cells < grid_cap ? p.n_cells : grid_cap;
   pre(1, st);
-  hipLaunchKernelGGL(k_union, dim3(g), dim3(kUnionThreads), 0, st, p);
+  hipLaunchKernelGGL(k_union, dim3(gr.other), dim3(kUnionThreads), 0, st, p);
   post(1, st);
   pre(2, st);
   hipLaunchKernelGGL(k_scan_out, dim3(1), dim3(1024), 0, st, p);
@@ -2087,27 +2141,27 @@ void launch_sweep(const HalfParams& p, const SweepStreams& s, int grid_cap, hipE
   // fork: the heaviest bins on their own streams, the light ones on main
   hipEventRecord(s.fork, st);
   for (int i = 0; i < 3; i++) hipStreamWaitEvent(s.aux[i], s.fork, 0);
-  const int gs = g < p.stream_wgs ? g : p.stream_wgs;  // one tile buffer per workgroup
+  const int gs = gr.bin[5] < p.stream_wgs ? gr.bin[5] : p.stream_wgs;  // one tile buffer per workgroup
   pre(8, s.aux[0]);
   if (gs > 0) hipLaunchKernelGGL(k_solve_stream, dim3(gs), dim3(kSlab), 0, s.aux[0], p);
   post(8, s.aux[0]);
   pre(9, s.aux[0]);
-  hipLaunchKernelGGL(k_solve_big, dim3(g), dim3(kBigThreads), 0, s.aux[0], p, 0);
+  hipLaunchKernelGGL(k_solve_big, dim3(gr.bin[6]), dim3(kBigThreads), 0, s.aux[0], p, 0);
   post(9, s.aux[0]);
   pre(7, s.aux[1]);
-  hipLaunchKernelGGL(k_solve_reg<16>, dim3(g), dim3(1024), 0, s.aux[1], p, 4);
+  hipLaunchKernelGGL(k_solve_reg<16>, dim3(gr.bin[4]), dim3(1024), 0, s.aux[1], p, 4);
   post(7, s.aux[1]);
   pre(6, s.aux[2]);
-  hipLaunchKernelGGL(k_solve_reg<8>, dim3(g), dim3(512), 0, s.aux[2], p, 3);
+  hipLaunchKernelGGL(k_solve_reg<8>, dim3(gr.bin[3]), dim3(512), 0, s.aux[2], p, 3);
   post(6, s.aux[2]);
   pre(5, st);
-  hipLaunchKernelGGL(k_solve_reg<4>, dim3(g), dim3(256), 0, st, p, 2);
+  hipLaunchKernelGGL(k_solve_reg<4>, dim3(gr.bin[2]), dim3(256), 0, st, p, 2);
   post(5, st);
   pre(4, st);
-  hipLaunchKernelGGL(k_solve_reg<2>, dim3(g), dim3(128), 0, st, p, 1);
+  hipLaunchKernelGGL(k_solve_reg<2>, dim3(gr.bin[1]), dim3(128), 0, st, p, 1);
   post(4, st);
   pre(3, st);
-  hipLaunchKernelGGL(k_solve_reg<1>, dim3(g), dim3(64), 0, st, p, 0);
+  hipLaunchKernelGGL(k_solve_reg<1>, dim3(gr.bin[0]), dim3(64), 0, st, p, 0);
   post(3, st);
   // join, then the cells handed over by the register solvers
   for (int i = 0; i < 3; i++) {
@@ -2115,7 +2169,7 @@ void launch_sweep(const HalfParams& p, const SweepStreams& s, int grid_cap, hipE
     hipStreamWaitEvent(st, s.join[i], 0);
   }
   pre(10, st);
-  hipLaunchKernelGGL(k_solve_big, dim3(g), dim3(kBigThreads), 0, st, p, 1);
+  hipLaunchKernelGGL(k_solve_big, dim3(gr.newton), dim3(kBigThreads), 0, st, p, 1);
   post(10, st);
 }
 
@@ -2229,17 +2283,22 @@ __global__ void k_diag_scatter(const int64_t* row_off, const int* row_len, const
   for (int k = threadIdx.x; k < row_len[b]; k += blockDim.x) atomicAdd(&acc[col[o + k]], val[o + k]);
 }
 
-__global__ __launch_bounds__(1024) void k_diag_reduce(const int64_t* row_off, const int* row_len,
+// Partial sums of the diagnostics, one slot per block (grid-stride over
+// pixels and basic cells), then a fixed-order sum of the slots.
+__global__ __launch_bounds__(256) void k_diag_partial(const int64_t* row_off, const int* row_len,
                                                       const double* val, const double* mu,
                                                       const double* nu, const double* acc, int H,
-                                                      int W, int bw, int n_basic, double* out3) {
+                                                      int W, int bw, int n_basic, double* part) {
   __shared__ double sh[16];
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   double ey = 0, dm = 0, nnz = 0;
-  for (long long i = threadIdx.x; i < (long long)H * W; i += 1024) ey += fabs(acc[i] - nu[i]);
-  for (int b = threadIdx.x; b < n_basic; b += 1024) {
+  for (long long i = t0; i < (long long)H * W; i += stride) ey += fabs(acc[i] - nu[i]);
+  for (long long b = t0; b < n_basic; b += stride) {
     double m = 0, mm = 0;
-    for (int k = 0; k < row_len[b]; k++) m += val[row_off[b] + k];
-    int br = b / bw, bc = b % bw;
+    const int64_t o = row_off[b];
+    for (int k = 0; k < row_len[b]; k++) m += val[o + k];
+    const int br = (int)(b / bw), bc = (int)(b % bw);
     for (int i = 0; i < kS; i++)
       for (int j = 0; j < kS; j++) mm += mu[(long long)(br * kS + i) * W + bc * kS + j];
     dm += fabs(m - mm);
@@ -2249,9 +2308,17 @@ __global__ __launch_bounds__(1024) void k_diag_reduce(const int64_t* row_off, co
   dm = block_sum_d(dm, sh);
   nnz = block_sum_d(nnz, sh);
   if (threadIdx.x == 0) {
-    out3[0] = ey;
-    out3[1] = dm;
-    out3[2] = nnz;
+    part[3 * blockIdx.x] = ey;
+    part[3 * blockIdx.x + 1] = dm;
+    part[3 * blockIdx.x + 2] = nnz;
+  }
+}
+
+__global__ void k_diag_final(const double* part, int n, double* out3) {
+  if (threadIdx.x < 3) {
+    double s = 0;
+    for (int k = 0; k < n; k++) s += part[3 * k + threadIdx.x];
+    out3[threadIdx.x] = s;
   }
 }
 
@@ -2261,8 +2328,11 @@ void launch_diag(const int64_t* row_off, const int* row_len, const int* col, con
   hipMemsetAsync(scratch_px, 0, sizeof(double) * (size_t)H * W, st);
   hipLaunchKernelGGL(k_diag_scatter, dim3(n_basic), dim3(64), 0, st, row_off, row_len, col, val,
                      n_basic, scratch_px);
-  hipLaunchKernelGGL(k_diag_reduce, dim3(1), dim3(1024), 0, st, row_off, row_len, val, mu, nu,
-                     scratch_px, H, W, bw, n_basic, out3);
+  // the slots live behind the H*W accumulator (scratch_px holds H*W + 3*kDiagBlocks)
+  double* part = scratch_px + (size_t)H * W;
+  hipLaunchKernelGGL(k_diag_partial, dim3(kDiagBlocks), dim3(256), 0, st, row_off, row_len, val,
+                     mu, nu, scratch_px, H, W, bw, n_basic, part);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, st, part, kDiagBlocks, out3);
 }
 
 // ------------------------------------------------------------ export

@@ -560,6 +560,19 @@ static dd_status ensure_stream(dd_ctx* c, int n_cells) {
   return DD_OK;
 }
 
+// Workgroups per solver launch: every workgroup loops over its bin's queue,
+// so a launch needs no more workgroups than the GPU holds at once (8 per
+// compute unit) or than its bin has cells.  (Sharing the wave slots out in
+// proportion to each bin's work in the previous sweep was measured slower.)
+static ddk::SweepGrid plan_grid(const dd_ctx* c, int n_cells) {
+  ddk::SweepGrid gr{};
+  const int g = std::max(1, std::min(n_cells, c->grid_cap));
+  for (int b = 0; b < ddk::kNBins; b++) gr.bin[b] = g;
+  gr.newton = std::max(1, std::min(n_cells, 2 * c->n_cu));
+  gr.other = g;
+  return gr;
+}
+
 extern "C" dd_status dd_half_iterate(dd_ctx* c, int part, dd_iter_stats* out) {
   if (!c) return DD_EINVAL;
   if (part != 0 && part != 1) return fail(c, DD_EINVAL, "partition must be 0 or 1");
@@ -574,7 +587,7 @@ extern "C" dd_status dd_half_iterate(dd_ctx* c, int part, dd_iter_stats* out) {
   HIPCHK(c, hipMemsetAsync(c->queue, 0, sizeof(int) * 8, c->st));
   HIPCHK(c, hipEventRecord(c->ev0, c->st));
   hipEvent_t* kev = c->opt.timing ? c->kev : nullptr;
-  ddk::launch_sweep(p, c->ss, c->grid_cap, kev);
+  ddk::launch_sweep(p, c->ss, plan_grid(c, p.n_cells), kev);
   HIPCHK(c, hipGetLastError());
   ddk::launch_stats(p, c->dstats, c->st, kev ? kev + 2 * (DD_N_KERNELS - 1) : nullptr);
   HIPCHK(c, hipGetLastError());
@@ -824,7 +837,7 @@ extern "C" dd_status dd_run_schedule(dd_ctx* c, dd_run_stats* out) {
 extern "C" dd_status dd_cost(dd_ctx* c, dd_cost_report* r) {
   if (!c || !r) return DD_EINVAL;
   const Level& l = c->L[c->lev];
-  dd_status s = ensure_px(c, (int64_t)l.H * l.W);
+  dd_status s = ensure_px(c, (int64_t)l.H * l.W + 3 * ddk::kDiagBlocks);
   if (s) return s;
   ddk::launch_diag(c->row_off, c->row_len, c->col, c->val, l.mu, l.nu, l.H, l.W, l.bw, c->nb,
                    c->px_scratch, c->dscal, c->st);
