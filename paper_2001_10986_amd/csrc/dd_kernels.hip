@@ -1565,7 +1565,9 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(HalfParams p) {
 // backtracking Armijo search on the increase of Phi evaluated as
 //   <g, a> - sum_y nu_J log(sum_x p_x (e^(a - c_y))),  c_y = sum_x p_x a,
 // (two non-negative sums) and, if no trial passes, a plain X-iteration.
-constexpr int kBigThreads = 1024;
+constexpr int kBigWaves = 8;
+constexpr int kBigThreads = kBigWaves * 64;
+constexpr int kNChunk = kBigThreads / 16;  // support points per Newton chunk (16 threads each)
 constexpr int kNewtonMaxSteps = 100;
 constexpr double kNewtonStepCap = 8.0;
 constexpr int kNewtonTrials = 10;
@@ -1580,12 +1582,12 @@ struct BigShared {
   int xr[64], xc[64];
   union {
     struct {
-      double pm[16][64], ps[16][64];
-    } lse;                 // Sinkhorn X-marginal partials
-    float q[64][65];       // Newton: p_x(y) sqrt(nu_J(y)) of one chunk of 64 support points
-    double racc[16][64];   // Newton: X-marginal partials per wave
+      double pm[kBigWaves][64], ps[kBigWaves][64];
+    } lse;                       // Sinkhorn X-marginal partials
+    float q[64][kNChunk + 1];    // Newton: p_x(y) sqrt(nu_J(y)) of one chunk of support points
+    double racc[kBigWaves][64];  // Newton: X-marginal partials per wave
   } u;
-  float Wm[64][65];        // Newton: weights, then the GTH elimination in place
+  float Wm[64][65];              // Newton: weights W(x,x')
   double err, slope;
   int last;                // last active pixel (ground of the Laplacian system)
   int nact;                // active pixels (mu > 0)
@@ -1597,6 +1599,23 @@ struct BigShared {
 DEVI double phi1(double b) {
   if (fabs(b) < 1e-3) return b * b * (0.5 + b * (1.0 / 6 + b * (1.0 / 24 + b / 120)));
   return expm1(b) - b;
+}
+
+// Sum / max over the 16 lanes of a DPP row (quad swaps and row rotations, so
+// every lane ends with the result).
+DEVI double row16_sum(double v) {
+  v += dpp_d<0xb1>(v);
+  v += dpp_d<0x4e>(v);
+  v += dpp_d<0x124>(v);
+  v += dpp_d<0x128>(v);
+  return v;
+}
+DEVI double row16_max(double v) {
+  v = fmax(v, dpp_d<0xb1>(v));
+  v = fmax(v, dpp_d<0x4e>(v));
+  v = fmax(v, dpp_d<0x124>(v));
+  v = fmax(v, dpp_d<0x128>(v));
+  return v;
 }
 
 // Conditional plan of support point yi for the 4 pixels xs + 16k of this
@@ -1612,19 +1631,14 @@ DEVI double cond_plan(const BigShared& sh, int r, int c, int xs, double lam, dou
     e[k] = sh.Fmu[x] - lam * (double)(dr * dr + dc * dc);
     m = e[k] > m ? e[k] : m;
   }
-#pragma unroll
-  for (int o = 1; o < 16; o <<= 1) {
-    const double v = __shfl_xor(m, o, 64);
-    m = v > m ? v : m;
-  }
+  m = row16_max(m);
   double v[4], s = 0;
 #pragma unroll
   for (int k = 0; k < 4; k++) {
     v[k] = e[k] == -INFINITY ? 0.0 : (double)fast_exp2((float)((e[k] - m) * kLog2e));
     s += v[k];
   }
-#pragma unroll
-  for (int o = 1; o < 16; o <<= 1) s += __shfl_xor(s, o, 64);
+  s = row16_sum(s);
 #pragma unroll
   for (int k = 0; k < 4; k++) pk[k] = v[k] / s;
   return m + log(s);
@@ -1633,7 +1647,7 @@ DEVI double cond_plan(const BigShared& sh, int r, int c, int xs, double lam, dou
 __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mode) {
   __shared__ BigShared sh;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int yl = tid >> 4, xs = tid & 15;  // Newton layout: 64 support points x 16 threads
+  const int yl = tid >> 4, xs = tid & 15;  // Newton layout: kNChunk support points x 16 threads
   const bool deferred = mode == 1;
   const int count = deferred ? (int)p.misc[3] : p.bin_count[kNBins - 1];
   const double invW = 1.0 / p.W;
@@ -1723,7 +1737,7 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mod
         {
           const int x = lane;
           double m = -INFINITY, s = 0;
-          for (int yi = wave; yi < U; yi += 16) {
+          for (int yi = wave; yi < U; yi += kBigWaves) {
             int r, c;
             split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
             const int dr = r - sh.xr[x], dc = c - sh.xc[x];
@@ -1742,9 +1756,9 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mod
         __syncthreads();
         if (wave == 0) {
           double m = -INFINITY;
-          for (int w = 0; w < 16; w++) m = sh.u.lse.pm[w][lane] > m ? sh.u.lse.pm[w][lane] : m;
+          for (int w = 0; w < kBigWaves; w++) m = sh.u.lse.pm[w][lane] > m ? sh.u.lse.pm[w][lane] : m;
           double s = 0;
-          for (int w = 0; w < 16; w++)
+          for (int w = 0; w < kBigWaves; w++)
             if (sh.u.lse.ps[w][lane] > 0) s += sh.u.lse.ps[w][lane] * exp(sh.u.lse.pm[w][lane] - m);
           const double Fh = -(m + log(s));
           sh.Fh[lane] = Fh;
@@ -1786,8 +1800,9 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mod
           const bool build_w = nst < kNewtonMaxSteps && n_act > 1;
           // ---- Y-iteration with conditional plans, X-marginal r, weights W
           double racc[4] = {0, 0, 0, 0};
-          float wacc[4] = {0.f, 0.f, 0.f, 0.f};
-          for (int y0 = 0; y0 < U; y0 += 64) {
+          float wacc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+          const int wrow = tid >> 3, wcg = tid & 7;  // W entries (wrow, wcg + 8k)
+          for (int y0 = 0; y0 < U; y0 += kNChunk) {
             const int yi = y0 + yl;
             double pk[4] = {0, 0, 0, 0};
             double sq = 0;
@@ -1805,12 +1820,12 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mod
 #pragma unroll
               for (int k = 0; k < 4; k++) sh.u.q[xs + 16 * k][yl] = (float)(pk[k] * sq);
               __syncthreads();
-              const float* qa = sh.u.q[yl];  // row x = yl of W
+              const float* qa = sh.u.q[wrow];
 #pragma unroll 4
-              for (int l = 0; l < 64; l++) {
+              for (int l = 0; l < kNChunk; l++) {
                 const float a = qa[l];
 #pragma unroll
-                for (int k = 0; k < 4; k++) wacc[k] = fmaf(a, sh.u.q[xs + 16 * k][l], wacc[k]);
+                for (int k = 0; k < 8; k++) wacc[k] = fmaf(a, sh.u.q[wcg + 8 * k][l], wacc[k]);
               }
               __syncthreads();
             }
@@ -1825,18 +1840,15 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mod
             for (int k = 0; k < 4; k++) sh.u.racc[wave][lane + 16 * k] = racc[k];
           if (build_w)
 #pragma unroll
-            for (int k = 0; k < 4; k++) {
-              const int x2 = xs + 16 * k;
-              sh.Wm[yl][x2] = x2 == yl ? 0.f : wacc[k];
-            }
+            for (int k = 0; k < 8; k++) sh.Wm[wrow][wcg + 8 * k] = wacc[k];
           __syncthreads();
           if (wave == 0) {
             double r = 0;
-            for (int w = 0; w < 16; w++) r += sh.u.racc[w][lane];
+            for (int w = 0; w < kBigWaves; w++) r += sh.u.racc[w][lane];
             const double mu = sh.mu[lane];
             if (!(mu > 0)) r = 0;
             sh.r[lane] = r;
-            const double e = wave_sum(mu > 0 ? fabs(r - mu) : 0.0);
+            const double e = wave_sum_dpp(mu > 0 ? fabs(r - mu) : 0.0);
             if (lane == 0) sh.err = e;
           }
           __syncthreads();
@@ -1851,40 +1863,61 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mod
           if (build_w) {
             nst++;
             if (wave == 0) {
-              // right side g - r sum(g)/sum(r), g = mu - r, then GTH elimination
+              // right side g - r sum(g)/sum(r), g = mu - r; then GTH elimination with
+              // row `lane` of W in registers (W is symmetric, its diagonal is never read)
               const double mu = sh.mu[lane], r = sh.r[lane];
               const double gx = mu > 0 ? mu - r : 0.0;
-              const double sg = wave_sum(gx), sr = wave_sum(r);
-              sh.b[lane] = gx - r * (sg / sr);
+              const double sg = wave_sum_dpp(gx), sr = wave_sum_dpp(r);
+              double bb = gx - r * (sg / sr);
               const int last = sh.last;
-              wave_sync();
-              for (int k = 0; k < last; k++) {
-                const double dk = wave_sum(lane > k ? (double)sh.Wm[k][lane] : 0.0);
-                if (lane == 0) sh.piv[k] = dk;
-                if (dk > 0 && lane > k) {
-                  const float cf = (float)((double)sh.Wm[lane][k] / dk);
-                  if (cf != 0.f) {
-                    sh.b[lane] += (double)cf * sh.b[k];
-                    float* row = sh.Wm[lane];
-                    const float* prow = sh.Wm[k];
-                    for (int j = k + 1; j < 64; j++)
-                      if (j != lane) row[j] = fmaf(cf, prow[j], row[j]);
+              float w[64];
+#pragma unroll
+              for (int j = 0; j < 64; j++) w[j] = sh.Wm[j][lane];
+              double piv = 0;  // lane k: pivot k
+#pragma unroll
+              for (int k = 0; k < 63; k++) {
+                if (k < last) {
+                  // pivot: remaining weights of row k (taken from column k by symmetry)
+                  const double dk = wave_sum_dpp(lane > k ? (double)w[k] : 0.0);
+                  if (lane == k) piv = dk;
+                  if (dk > 0) {
+                    const float cf = lane > k ? (float)((double)w[k] / dk) : 0.f;
+                    const double bk = __builtin_bit_cast(
+                        double, ((long long)__builtin_amdgcn_readlane(
+                                     (int)(__builtin_bit_cast(long long, bb) >> 32), k)
+                                 << 32) |
+                                    (unsigned int)__builtin_amdgcn_readlane(
+                                        (int)(__builtin_bit_cast(long long, bb) & 0xffffffffll), k));
+                    bb += (double)cf * bk;
+#pragma unroll
+                    for (int j = k + 1; j < 64; j++) {
+                      const float wkj = __builtin_bit_cast(
+                          float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, w[j]), k));
+                      w[j] = fmaf(cf, wkj, w[j]);
+                    }
                   }
                 }
-                wave_sync();
               }
-              sh.dl[lane] = 0.0;
-              wave_sync();
-              for (int k = last - 1; k >= 0; k--) {
-                const double s = wave_sum(lane > k ? (double)sh.Wm[k][lane] * sh.dl[lane] : 0.0);
-                if (lane == 0) sh.dl[k] = sh.piv[k] > 0 ? (sh.b[k] + s) / sh.piv[k] : 0.0;
-                wave_sync();
+              // back substitution from the ground down: d_k = (b_k + sum_{j>k} W(k,j) d_j) / piv_k
+              const double inv = piv > 0 ? 1.0 / piv : 0.0;
+              double acc = 0, dl = 0;
+#pragma unroll
+              for (int k = 62; k >= 0; k--) {
+                if (k < last) {
+                  const double own = lane == k ? (bb + acc) * inv : 0.0;
+                  const long long q = __builtin_bit_cast(long long, own);
+                  const double dk = __builtin_bit_cast(
+                      double, ((long long)__builtin_amdgcn_readlane((int)(q >> 32), k) << 32) |
+                                  (unsigned int)__builtin_amdgcn_readlane((int)(q & 0xffffffffll), k));
+                  if (lane == k) dl = dk;
+                  acc += (double)w[k] * dk;
+                }
               }
-              double dx = sh.dl[lane];
+              double dx = dl;
               const double dm = wave_max(fabs(dx));
               if (dm > kNewtonStepCap) dx *= kNewtonStepCap / dm;
               sh.dl[lane] = dx;
-              const double sl = wave_sum(gx * dx);
+              const double sl = wave_sum_dpp(gx * dx);
               if (lane == 0) sh.slope = sl;
             }
             __syncthreads();
@@ -1892,7 +1925,7 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mod
             if (slope > 0) {
               for (int trial = 0; trial < kNewtonTrials; trial++) {
                 double loc = 0;
-                for (int y0 = 0; y0 < U; y0 += 64) {
+                for (int y0 = 0; y0 < U; y0 += kNChunk) {
                   const int yi = y0 + yl;
                   if (yi < U) {
                     int r, c;
@@ -1905,14 +1938,12 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mod
                       a[k] = t * sh.dl[xs + 16 * k];
                       cy += pk[k] * a[k];
                     }
+                    cy = row16_sum(cy);
+                    double sp = 0;
 #pragma unroll
-                    for (int o = 1; o < 16; o <<= 1) cy += __shfl_xor(cy, o, 64);
-                    double s = 0;
-#pragma unroll
-                    for (int k = 0; k < 4; k++) s += pk[k] > 0 ? pk[k] * phi1(a[k] - cy) : 0.0;
-#pragma unroll
-                    for (int o = 1; o < 16; o <<= 1) s += __shfl_xor(s, o, 64);
-                    if (xs == 0) loc -= p.uni_nu[ub + yi] * log1p(s);
+                    for (int k = 0; k < 4; k++) sp += pk[k] > 0 ? pk[k] * phi1(a[k] - cy) : 0.0;
+                    sp = row16_sum(sp);
+                    if (xs == 0) loc -= p.uni_nu[ub + yi] * log1p(sp);
                   }
                 }
                 if (tid < 64) {
