@@ -78,7 +78,7 @@ typedef struct {
                               stopping test, same fixed point), 0: plain Sinkhorn; default 1 */
   int newton_after;        /* >0: a cell not converged after this many loops continues with
                               damped Newton steps on its X potential (same stopping test, same
-                              fixed point); 0: never; default 128 */
+                              fixed point); 0: never; default 256 */
   int inputs_on_device;    /* 1: mu, nu passed to dd_init are device pointers; default 0 */
   int timing;              /* 1: record HIP events around every kernel of a sweep; default 0 */
   void* stream;            /* hipStream_t for all work of the context; default NULL */

@@ -47,13 +47,14 @@ struct HalfParams {
   int* r_loops;
   int* r_status;
   long long* r_evals;
-  long long* misc;             // [0] nnz_in, [1] out entries, [2] bad-row flag, [3] deferred cells
-  int* queue;                  // per solver launch: next cell of its list (kNBins + 1 counters)
+  long long* misc;             // [0] nnz_in, [1] out entries, [2] bad-row flag,
+                               // [4 + g] cells handed to Newton steps in group g
+  int* queue;                  // next cell of each solver launch's list (kNBins + groups)
   float* stream_tile;          // streamed solver: kStreamTileFloats per workgroup
   float* stream_S;             // streamed solver: S(y), kStreamMaxU per workgroup
   float* stream_nu;            // streamed solver: nu_J(y) in FP32, kStreamMaxU per workgroup
   int stream_wgs;              // workgroups the streamed-solver buffers are sized for
-  int* defer_list;             // cells handed from the register solver to the Newton solver
+  int* defer_list;             // cells handed to the Newton solver, n_cells per group
   double* defer_F;             // their potentials (units of eps), 64 per cell, indexed by cell
   long long capE;              // entry buffer capacity (rows are checked against it)
 };
@@ -76,8 +77,13 @@ struct SweepStreams {
 };
 constexpr int kNKernels = 12;  // scan, union, scan_out, 5 register, streamed, big, newton, stats
 
-// Kernel launchers (all asynchronous).  ev: nullptr, or 2*kNKernels events;
-// ev[2k] and ev[2k+1] are recorded around kernel k on the stream it runs on.
+constexpr int kNDeferGroups = 4;  // Newton launches per sweep (one per stream)
+constexpr int kNEvents = 2 * (kNKernels + kNDeferGroups - 1);
+
+// Kernel launchers (all asynchronous).  ev: nullptr, or kNEvents events;
+// ev[2k] and ev[2k+1] are recorded around kernel k on the stream it runs on;
+// kernel 10 (Newton) is launched once per stream, the launches on the
+// auxiliary streams take the slots kNKernels .. kNKernels + 2.
 // Workgroups per solver launch (each loops over its bin's work queue).
 struct SweepGrid {
   int bin[kNBins];   // solver launches of bins 0..kNBins-1

@@ -155,6 +155,12 @@ __global__ __launch_bounds__(1024) void k_scan_T(HalfParams p) {
   if (threadIdx.x == 0) p.misc[0] = carry;
 }
 
+// Cells handed to Newton steps are collected per group of solver launches
+// that share a stream, so that each group's Newton launch can follow its
+// producers on that stream: bins 0-2 (main stream), 3, 4, and the streamed
+// solver (bin 5).
+DEVI int defer_group(int bin) { return bin <= 2 ? 0 : bin - 2; }
+
 DEVI int bin_of(int U) {
   if (U <= 64) return 0;
   if (U <= 128) return 1;
@@ -957,9 +963,11 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
             p.defer_F[(int64_t)cell * 64 + tid] =
                 sh.mu[tid] > 0 ? sh.F0[tid] + log((double)uw[tid]) : 0.0;
           if (tid == 0) {
+            const int grp = defer_group(bin);
             const unsigned long long slot =
-                atomicAdd(reinterpret_cast<unsigned long long*>(&p.misc[3]), 1ull);
-            if (slot < (unsigned long long)p.n_cells) p.defer_list[slot] = cell;
+                atomicAdd(reinterpret_cast<unsigned long long*>(&p.misc[4 + grp]), 1ull);
+            if (slot < (unsigned long long)p.n_cells)
+              p.defer_list[(int64_t)grp * p.n_cells + slot] = cell;
             p.r_loops[cell] = it;
           }
           deferred = true;
@@ -1420,9 +1428,11 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(HalfParams p) {
             p.defer_F[(int64_t)cell * 64 + tid] =
                 sh.mu[tid] > 0 ? sh.F0[tid] + log((double)sh.u[tid]) : 0.0;
           if (tid == 0) {
+            const int grp = defer_group(bin);
             const unsigned long long slot =
-                atomicAdd(reinterpret_cast<unsigned long long*>(&p.misc[3]), 1ull);
-            if (slot < (unsigned long long)p.n_cells) p.defer_list[slot] = cell;
+                atomicAdd(reinterpret_cast<unsigned long long*>(&p.misc[4 + grp]), 1ull);
+            if (slot < (unsigned long long)p.n_cells)
+              p.defer_list[(int64_t)grp * p.n_cells + slot] = cell;
             p.r_loops[cell] = it;
           }
           deferred = true;
@@ -1595,10 +1605,29 @@ struct BigShared {
   CellOutSh out;
 };
 
-// e^b - 1 - b without cancellation for small |b|
-DEVI double phi1(double b) {
-  if (fabs(b) < 1e-3) return b * b * (0.5 + b * (1.0 / 6 + b * (1.0 / 24 + b / 120)));
-  return expm1(b) - b;
+// e^b - 1 - b >= 0 without cancellation, in FP32 (relative error ~1e-7):
+// Taylor series through b^9 for |b| < 1/2, else exp - 1 - b
+DEVI float phi1f(float b) {
+  if (fabsf(b) < 0.5f) {
+    float t = 1.f / 362880.f;
+    t = fmaf(t, b, 1.f / 40320.f);
+    t = fmaf(t, b, 1.f / 5040.f);
+    t = fmaf(t, b, 1.f / 720.f);
+    t = fmaf(t, b, 1.f / 120.f);
+    t = fmaf(t, b, 1.f / 24.f);
+    t = fmaf(t, b, 1.f / 6.f);
+    t = fmaf(t, b, 0.5f);
+    return b * b * t;
+  }
+  return (fast_exp2(b * (float)kLog2e) - 1.f) - b;
+}
+
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float floatx16 __attribute__((ext_vector_type(16)));
+// FP32 -> BF16, round to nearest even (finite inputs)
+DEVI short bf16_rn(float f) {
+  const unsigned u = __float_as_uint(f);
+  return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
 }
 
 // Sum / max over the 16 lanes of a DPP row (quad swaps and row rotations, so
@@ -1639,8 +1668,9 @@ DEVI double cond_plan(const BigShared& sh, int r, int c, int xs, double lam, dou
     s += v[k];
   }
   s = row16_sum(s);
+  const double inv = 1.0 / s;
 #pragma unroll
-  for (int k = 0; k < 4; k++) pk[k] = v[k] / s;
+  for (int k = 0; k < 4; k++) pk[k] = v[k] * inv;
   return m + log(s);
 }
 
@@ -1648,15 +1678,17 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mod
   __shared__ BigShared sh;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int yl = tid >> 4, xs = tid & 15;  // Newton layout: kNChunk support points x 16 threads
-  const bool deferred = mode == 1;
-  const int count = deferred ? (int)p.misc[3] : p.bin_count[kNBins - 1];
+  const bool deferred = mode >= 1;
+  const int grp = mode - 1;  // Newton group of the handed-over cells
+  const int count = deferred ? (int)p.misc[4 + grp] : p.bin_count[kNBins - 1];
   const double invW = 1.0 / p.W;
   for (;;) {
-    if (tid == 0) sh.next = atomicAdd(&p.queue[deferred ? kNBins : kNBins - 1], 1);
+    if (tid == 0) sh.next = atomicAdd(&p.queue[deferred ? kNBins + grp : kNBins - 1], 1);
     __syncthreads();
     const int ci = sh.next;
     if (ci >= count) break;
-    const int cell = deferred ? p.defer_list[ci] : p.bin_list[(kNBins - 1) * p.n_cells + ci];
+    const int cell = deferred ? p.defer_list[(int64_t)grp * p.n_cells + ci]
+                              : p.bin_list[(kNBins - 1) * p.n_cells + ci];
     const CellGeo g = load_geo(p, cell);
     const int U = p.cell_U[cell];
     const int64_t ub = p.cell_toff[cell];
@@ -1800,8 +1832,10 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mod
           const bool build_w = nst < kNewtonMaxSteps && n_act > 1;
           // ---- Y-iteration with conditional plans, X-marginal r, weights W
           double racc[4] = {0, 0, 0, 0};
-          float wacc[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-          const int wrow = tid >> 3, wcg = tid & 7;  // W entries (wrow, wcg + 8k)
+          // W = Q Q^T by BF16 matrix cores (FP32 accumulation): waves 0..3 own
+          // the 32x32 quadrant (wave>>1, wave&1); W only steers the Newton step,
+          // the error and the line search stay in FP32/FP64
+          floatx16 wacc = {};
           for (int y0 = 0; y0 < U; y0 += kNChunk) {
             const int yi = y0 + yl;
             double pk[4] = {0, 0, 0, 0};
@@ -1814,18 +1848,26 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mod
 #pragma unroll
               for (int k = 0; k < 4; k++) racc[k] += nu * pk[k];
               if (xs == 0) G[yi] = -lse + (nu > 0 ? log(nu) : -INFINITY);
-              sq = sqrt(nu);
+              sq = (double)sqrtf((float)nu);
             }
             if (build_w) {
 #pragma unroll
               for (int k = 0; k < 4; k++) sh.u.q[xs + 16 * k][yl] = (float)(pk[k] * sq);
               __syncthreads();
-              const float* qa = sh.u.q[wrow];
-#pragma unroll 4
-              for (int l = 0; l < kNChunk; l++) {
-                const float a = qa[l];
+              if (wave < 4) {
+                const float* qa = sh.u.q[32 * (wave >> 1) + (lane & 31)];
+                const float* qb = sh.u.q[32 * (wave & 1) + (lane & 31)];
+                const int kh = 4 * (lane >> 5);
 #pragma unroll
-                for (int k = 0; k < 8; k++) wacc[k] = fmaf(a, sh.u.q[wcg + 8 * k][l], wacc[k]);
+                for (int k0 = 0; k0 < kNChunk; k0 += 8) {
+                  short4_t a, b;
+#pragma unroll
+                  for (int t = 0; t < 4; t++) {
+                    a[t] = bf16_rn(qa[k0 + kh + t]);
+                    b[t] = bf16_rn(qb[k0 + kh + t]);
+                  }
+                  wacc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, wacc, 0, 0, 0);
+                }
               }
               __syncthreads();
             }
@@ -1838,9 +1880,11 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mod
           if (lane < 16)
 #pragma unroll
             for (int k = 0; k < 4; k++) sh.u.racc[wave][lane + 16 * k] = racc[k];
-          if (build_w)
+          if (build_w && wave < 4)
 #pragma unroll
-            for (int k = 0; k < 8; k++) sh.Wm[wrow][wcg + 8 * k] = wacc[k];
+            for (int v = 0; v < 16; v++)  // D(i,j): i = 8(v/4) + 4(lane/32) + v%4, j = lane%32
+              sh.Wm[32 * (wave >> 1) + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)]
+                   [32 * (wave & 1) + (lane & 31)] = wacc[v];
           __syncthreads();
           if (wave == 0) {
             double r = 0;
@@ -1941,7 +1985,8 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mod
                     cy = row16_sum(cy);
                     double sp = 0;
 #pragma unroll
-                    for (int k = 0; k < 4; k++) sp += pk[k] > 0 ? pk[k] * phi1(a[k] - cy) : 0.0;
+                    for (int k = 0; k < 4; k++)
+                      sp += pk[k] > 0 ? pk[k] * (double)phi1f((float)(a[k] - cy)) : 0.0;
                     sp = row16_sum(sp);
                     if (xs == 0) loc -= p.uni_nu[ub + yi] * log1p(sp);
                   }
@@ -2169,7 +2214,9 @@ void launch_sweep(const HalfParams& p, const SweepStreams& s, const SweepGrid& g
   pre(2, st);
   hipLaunchKernelGGL(k_scan_out, dim3(1), dim3(1024), 0, st, p);
   post(2, st);
-  // fork: the heaviest bins on their own streams, the light ones on main
+  // fork: the heaviest bins on their own streams, the light ones on main; each
+  // stream ends with the Newton launch for the cells its solvers handed over
+  // (events kNKernels + i of ev for the three auxiliary ones)
   hipEventRecord(s.fork, st);
   for (int i = 0; i < 3; i++) hipStreamWaitEvent(s.aux[i], s.fork, 0);
   const int gs = gr.bin[5] < p.stream_wgs ? gr.bin[5] : p.stream_wgs;  // one tile buffer per workgroup
@@ -2179,12 +2226,21 @@ void launch_sweep(const HalfParams& p, const SweepStreams& s, const SweepGrid& g
   pre(9, s.aux[0]);
   hipLaunchKernelGGL(k_solve_big, dim3(gr.bin[6]), dim3(kBigThreads), 0, s.aux[0], p, 0);
   post(9, s.aux[0]);
+  pre(kNKernels + 0, s.aux[0]);
+  hipLaunchKernelGGL(k_solve_big, dim3(gr.newton), dim3(kBigThreads), 0, s.aux[0], p, 1 + 3);
+  post(kNKernels + 0, s.aux[0]);
   pre(7, s.aux[1]);
   hipLaunchKernelGGL(k_solve_reg<16>, dim3(gr.bin[4]), dim3(1024), 0, s.aux[1], p, 4);
   post(7, s.aux[1]);
+  pre(kNKernels + 1, s.aux[1]);
+  hipLaunchKernelGGL(k_solve_big, dim3(gr.newton), dim3(kBigThreads), 0, s.aux[1], p, 1 + 2);
+  post(kNKernels + 1, s.aux[1]);
   pre(6, s.aux[2]);
   hipLaunchKernelGGL(k_solve_reg<8>, dim3(gr.bin[3]), dim3(512), 0, s.aux[2], p, 3);
   post(6, s.aux[2]);
+  pre(kNKernels + 2, s.aux[2]);
+  hipLaunchKernelGGL(k_solve_big, dim3(gr.newton), dim3(kBigThreads), 0, s.aux[2], p, 1 + 1);
+  post(kNKernels + 2, s.aux[2]);
   pre(5, st);
   hipLaunchKernelGGL(k_solve_reg<4>, dim3(gr.bin[2]), dim3(256), 0, st, p, 2);
   post(5, st);
@@ -2194,14 +2250,14 @@ void launch_sweep(const HalfParams& p, const SweepStreams& s, const SweepGrid& g
   pre(3, st);
   hipLaunchKernelGGL(k_solve_reg<1>, dim3(gr.bin[0]), dim3(64), 0, st, p, 0);
   post(3, st);
-  // join, then the cells handed over by the register solvers
+  pre(10, st);
+  hipLaunchKernelGGL(k_solve_big, dim3(gr.newton), dim3(kBigThreads), 0, st, p, 1 + 0);
+  post(10, st);
+  // join
   for (int i = 0; i < 3; i++) {
     hipEventRecord(s.join[i], s.aux[i]);
     hipStreamWaitEvent(st, s.join[i], 0);
   }
-  pre(10, st);
-  hipLaunchKernelGGL(k_solve_big, dim3(gr.newton), dim3(kBigThreads), 0, st, p, 1);
-  post(10, st);
 }
 
 size_t sweep_max_static_lds() {
