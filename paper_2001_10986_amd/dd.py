@@ -18,7 +18,10 @@ DD_EINVAL, DD_ENOMEM, DD_EHIP, DD_ECAPACITY, DD_ESTATE = -1, -2, -3, -4, -5
 
 EXPORTED = ["dd_options_default", "dd_init", "dd_half_iterate", "dd_set_eps", "dd_refine",
             "dd_run_schedule", "dd_cost", "dd_export_plan", "dd_import_state",
-            "dd_cell_results", "dd_level_info", "dd_free", "dd_last_error"]
+            "dd_cell_results", "dd_level_info", "dd_free", "dd_last_error",
+            "dd_mlp_create", "dd_mlp_free", "dd_mlp_last_error", "dd_mlp_shape",
+            "dd_mlp_set_params", "dd_mlp_get_params", "dd_mlp_forward", "dd_mlp_forward_bf16",
+            "dd_mlp_loss_grad", "dd_mlp_train_step"]
 
 
 class Stage(C.Structure):
