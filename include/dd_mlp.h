@@ -49,6 +49,43 @@ dd_status dd_mlp_loss_grad(dd_mlp* net, const float* x_dev, const float* t_dev,
 /* one Adam step (beta 0.9 / 0.999, eps 1e-8) on that loss; loss of the batch before the step */
 dd_status dd_mlp_train_step(dd_mlp* net, const float* x_dev, const float* t_dev,
                             const float* mask_dev, int n_rows, float lr, float* loss);
+/* the hipStream_t the network's work runs on */
+void* dd_mlp_get_stream(const dd_mlp* net);
+
+/* ---- use with a domain-decomposition context (include/dd.h) ----
+ *
+ * Cell features (768 per cell, the network's input): 64 mu_J / |mu_J| on the
+ * cell's 8x8 pixel block; 256 nu_J / |nu_J| on a 24x24 pixel window around
+ * the block moved by the cell's integer shift d_J = round(mean_nu - mean_mu);
+ * log(h^2/eps); the nu_J mass outside the window; d_J / 8; and the potential
+ * the solve would start from (the previous sweep's), in units of eps, with
+ * the linear part 2 (h^2/eps) (x - x_c).d_J of the shift added, centred over
+ * the pixels of positive mass and divided by 16 h^2/eps.  Output (64): the
+ * change of that centred potential which the solve makes, in the same units;
+ * a zero output gives back the plain warm start.  Only cells whose Y-support
+ * has at most 512 points are eligible; the others keep the plain start.
+ *
+ * dd_set_warm_start: attach a network (n_in 768, n_out 64) or detach it
+ * (net NULL).  policy 1: predict the start of every eligible cell on the
+ * first sweep of each partition after dd_init, dd_refine or an eps change;
+ * policy 2: on every sweep; 0: never.  On such a sweep the prediction replaces
+ * the start of a cell only if the RMS of its predicted change (output units,
+ * over the pixels of positive mass) is at least min_rms.  The network must
+ * outlive its use.  The cell solves still run to the stopping tolerance of
+ * Sec. 6.2.  dd_warm_start_count: sweeps that ran the network and cells that
+ * took its start, since dd_init.
+ *
+ * dd_collect_cells: training samples of the last half-iteration: for every
+ * eligible cell that converged, its features built from the potentials the
+ * sweep started from (row of x_dev, 768 floats), the change of the centred
+ * potential that its solve made (t_dev, 64 floats) and the mask of pixels
+ * with positive mass (mask_dev, 64 floats) and, if cell_dev is not NULL, the
+ * cell's index in its partition (int32); at most cap rows in an unspecified
+ * order (device buffers of the caller); *n_out = rows written.  Synchronises. */
+dd_status dd_set_warm_start(dd_ctx* ctx, dd_mlp* net, int policy, float min_rms);
+dd_status dd_warm_start_count(dd_ctx* ctx, int* n_sweeps, long long* n_cells);
+dd_status dd_collect_cells(dd_ctx* ctx, float* x_dev, float* t_dev, float* mask_dev,
+                           int* cell_dev, int cap, int* n_out);
 
 #ifdef __cplusplus
 }

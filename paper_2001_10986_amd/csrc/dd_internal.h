@@ -14,6 +14,9 @@ constexpr int kStreamSlabs = 8;                // streamed solver: slabs of 1024
 constexpr int kStreamMaxU = kStreamSlabs * 1024;
 constexpr size_t kStreamTileFloats = (size_t)kStreamMaxU * 64;  // tile buffer per workgroup
 constexpr int kNBins = kNRegBins + 2;          // + streamed solver + log-domain solver
+constexpr int kFeatIn = 768;                   // warm-start network input width
+constexpr int kWarmMaxU = 512;                 // cells with larger unions keep the plain start
+constexpr double kWarmScale = 16.0;            // network output unit: 16 lam (h^2/eps)
 
 // Everything one sweep over one partition needs.  Device pointers.
 struct HalfParams {
@@ -90,7 +93,12 @@ struct SweepGrid {
   int newton;        // the launch for the cells handed over to Newton steps
   int other;         // union kernel
 };
-void launch_sweep(const HalfParams& p, const SweepStreams& s, const SweepGrid& gr, hipEvent_t* ev);
+// A sweep is prep (cell sizes, unions, bins) then solve (the concurrent solver
+// launches and the Newton launches); a warm start may run in between.
+void launch_sweep_prep(const HalfParams& p, const SweepStreams& s, const SweepGrid& gr,
+                       hipEvent_t* ev);
+void launch_sweep_solve(const HalfParams& p, const SweepStreams& s, const SweepGrid& gr,
+                        hipEvent_t* ev);
 void launch_stats(const HalfParams& p, IterStatsDev* out, hipStream_t st, hipEvent_t* ev2);
 size_t sweep_max_static_lds();
 
@@ -113,6 +121,16 @@ void launch_export(const int64_t* row_off, const int* row_len, const int* col, c
                    int n_basic, int64_t* row_ptr_dev, int* col_out, double* val_out,
                    hipStream_t st);
 void launch_scan_rows(const int* row_len, int n, int64_t* row_ptr, hipStream_t st);
+
+// Warm start: features of every cell (BF16 rows of kFeatIn, zero for cells
+// above kWarmMaxU); then the network output applied to alpha.
+void launch_warm_features(const HalfParams& p, unsigned short* X, hipStream_t st);
+void launch_warm_apply(const HalfParams& p, const float* Y, float min_rms, int* n_applied,
+                       hipStream_t st);
+// Training samples of the last sweep (FP32 features from the potentials the
+// sweep started from, targets = the solve's change of the potential, masks).
+void launch_collect(const HalfParams& p, const double* alpha_prev, float* X, float* T, float* M,
+                    int* ids, int cap, int* count, hipStream_t st);
 
 // Refinement.
 struct RefineParams {

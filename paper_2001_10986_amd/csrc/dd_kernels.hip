@@ -2111,6 +2111,203 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mod
   }
 }
 
+// ------------------------------------------------------------ warm-start features
+
+// Features of one composite cell problem for the warm-start network, 256
+// threads per cell.  Positions are in pixels of the level; the cell's integer
+// shift d_J = round(mean_nu(y) - mean_mu(x)) moves the nu window onto the
+// cell, and the X potentials are written for the problem with cost
+// |x - (y - d_J)|^2: F~ = F + 2 lam (x - x_c).d_J, centred over the pixels of
+// positive mass (x_c the block centre, lam = h^2/eps), so that they carry no
+// bulk linear trend.  The network predicts the change of F~ that the cell
+// solve will make to the potential it starts from (zero output = the plain
+// warm start).
+//   [0, 64)     64 mu(x) / |mu_J| on the 8x8 block (0 where a quadrant is absent)
+//   [64, 640)   256 nu_J(y) / |nu_J| on the 24x24 window whose rows start at
+//               R0 - 8 + d_r and columns at C0 - 8 + d_c
+//   640         log lam,  641  nu_J mass outside the window / |nu_J|,
+//   642, 643    d_J / 8
+//   [644, 708)  F~ of the starting potential / (kWarmScale lam)
+//   rest 0
+// Leaves the features in sh.f, d_J in *dr, *dc and the centred F~ of the
+// potential `alpha` (units of eps) of this thread's pixel (threads < 64) in
+// *ft (0 for pixels without mass).
+struct FeatShared {
+  float f[kFeatIn];
+  double red[8];
+};
+
+DEVI void cell_features(const HalfParams& p, const CellGeo& g, int U, int64_t ub,
+                        const double* alpha, FeatShared& sh, int* dr_out, int* dc_out,
+                        double* ft_out) {
+  const int tid = threadIdx.x;
+  const double invW = 1.0 / p.W;
+  for (int k = tid; k < kFeatIn; k += blockDim.x) sh.f[k] = 0.f;
+  // mu block: mass and mass-weighted position
+  double mu = 0, mr = 0, mc = 0;
+  int64_t px = 0;
+  if (tid < 64) {
+    const int i = tid >> 3, j = tid & 7;
+    const int qa = (i >> 2) * 2 + (j >> 2);
+    const int bq = qa == 0 ? g.bq[0] : qa == 1 ? g.bq[1] : qa == 2 ? g.bq[2] : g.bq[3];
+    px = (int64_t)(g.R0 + i) * p.W + g.C0 + j;
+    if (bq >= 0) {
+      mu = p.mu[px];
+      mr = mu * i;
+      mc = mu * j;
+    }
+  }
+  const double mm = block_sum_d(mu, sh.red);
+  mr = block_sum_d(mr, sh.red);
+  mc = block_sum_d(mc, sh.red);
+  // nu_J: mass and mass-weighted position (relative to the block origin)
+  double nm = 0, nr = 0, nc = 0;
+  for (int y = tid; y < U; y += blockDim.x) {
+    int r, c;
+    split_key(p.uni_key[ub + y], p.W, invW, &r, &c);
+    const double v = p.uni_nu[ub + y];
+    nm += v;
+    nr += v * (r - g.R0);
+    nc += v * (c - g.C0);
+  }
+  nm = block_sum_d(nm, sh.red);
+  nr = block_sum_d(nr, sh.red);
+  nc = block_sum_d(nc, sh.red);
+  const int dr = (int)rint(nm > 0 && mm > 0 ? nr / nm - mr / mm : 0.0);
+  const int dc = (int)rint(nm > 0 && mm > 0 ? nc / nm - mc / mm : 0.0);
+  // starting potential, shift-compensated and centred
+  double ft = 0, act = 0;
+  if (tid < 64 && mu > 0) {
+    const int i = tid >> 3, j = tid & 7;
+    ft = alpha[px] / p.eps + 2.0 * p.lam * ((i - 3.5) * dr + (j - 3.5) * dc);
+    act = 1;
+  }
+  const double fsum = block_sum_d(ft, sh.red), na = block_sum_d(act, sh.red);
+  if (act > 0) ft -= fsum / na;
+  if (tid < 64 && mm > 0) {
+    sh.f[tid] = (float)(64.0 * mu / mm);
+    sh.f[644 + tid] = (float)(ft / (kWarmScale * p.lam));
+  }
+  double out = 0;
+  for (int y = tid; y < U; y += blockDim.x) {
+    int r, c;
+    split_key(p.uni_key[ub + y], p.W, invW, &r, &c);
+    const double v = nm > 0 ? p.uni_nu[ub + y] / nm : 0.0;
+    const int wr = r - (g.R0 - 8 + dr), wc = c - (g.C0 - 8 + dc);
+    if (wr >= 0 && wr < 24 && wc >= 0 && wc < 24)
+      sh.f[64 + wr * 24 + wc] = (float)(256.0 * v);  // keys are unique: one point per pixel
+    else
+      out += v;
+  }
+  out = block_sum_d(out, sh.red);
+  if (tid == 0) {
+    sh.f[640] = (float)log(p.lam);
+    sh.f[641] = (float)out;
+    sh.f[642] = dr * 0.125f;
+    sh.f[643] = dc * 0.125f;
+  }
+  __syncthreads();
+  *dr_out = dr;
+  *dc_out = dc;
+  *ft_out = act > 0 ? ft : 0.0;
+}
+
+DEVI unsigned short bf16_bits_rn(float f) {
+  const unsigned u = __float_as_uint(f);
+  return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// Inference input of a sweep: one BF16 row per cell (zero for cells whose
+// union exceeds kWarmMaxU), from the potentials the sweep starts from.
+__global__ __launch_bounds__(256) void k_warm_features(HalfParams p, unsigned short* X) {
+  __shared__ FeatShared sh;
+  for (int cell = blockIdx.x; cell < p.n_cells; cell += gridDim.x) {
+    const int U = p.cell_U[cell];
+    if (U > kWarmMaxU) {
+      for (int k = threadIdx.x; k < kFeatIn; k += blockDim.x) X[(size_t)cell * kFeatIn + k] = 0;
+      continue;  // uniform
+    }
+    const CellGeo g = load_geo(p, cell);
+    int dr, dc;
+    double ft;
+    cell_features(p, g, U, p.cell_toff[cell], p.alpha, sh, &dr, &dc, &ft);
+    for (int k = threadIdx.x; k < kFeatIn; k += blockDim.x)
+      X[(size_t)cell * kFeatIn + k] = bf16_bits_rn(sh.f[k]);
+    __syncthreads();
+  }
+}
+
+// Warm start of eligible cells: the network output Y is the change of the
+// centred F~ in units of kWarmScale lam, so F0 = alpha / eps + kWarmScale lam Y
+// (the shift's linear part cancels), written over alpha for the cell's pixels
+// of positive mass -- for cells whose predicted change has an RMS of at least
+// min_rms (in output units) only; the others keep the plain start.
+__global__ __launch_bounds__(64) void k_warm_apply(HalfParams p, const float* Y, float min_rms,
+                                                   int* n_applied) {
+  const int cell = blockIdx.x;
+  if (cell >= p.n_cells || p.cell_U[cell] > kWarmMaxU) return;  // uniform
+  const CellGeo g = load_geo(p, cell);
+  const int i = threadIdx.x >> 3, j = threadIdx.x & 7;
+  const int qa = (i >> 2) * 2 + (j >> 2);
+  const int bq = qa == 0 ? g.bq[0] : qa == 1 ? g.bq[1] : qa == 2 ? g.bq[2] : g.bq[3];
+  const int64_t px = (int64_t)(g.R0 + i) * p.W + g.C0 + j;
+  const bool act = bq >= 0 && p.mu[px] > 0;
+  const double y = act ? (double)Y[(size_t)cell * 64 + threadIdx.x] : 0.0;
+  const double ss = wave_sum_dpp(y * y), na = wave_sum_dpp(act ? 1.0 : 0.0);
+  if (!(na > 0) || ss < (double)min_rms * min_rms * na) return;  // uniform
+  if (act) p.alpha[px] += p.eps * kWarmScale * p.lam * y;
+  if (threadIdx.x == 0) atomicAdd(n_applied, 1);
+}
+
+// Training samples of the last sweep: the features of each converged cell
+// with U <= kWarmMaxU built from the potentials the sweep started from
+// (alpha_prev), the change of the centred F~ that the solve made (alpha after
+// the sweep minus alpha_prev, in units of kWarmScale lam) and the mask of
+// pixels with positive mass; rows appended at an atomic counter.
+__global__ __launch_bounds__(256) void k_collect(HalfParams p, const double* alpha_prev, float* X,
+                                                 float* T, float* M, int* ids, int cap,
+                                                 int* count) {
+  __shared__ FeatShared sh;
+  __shared__ int slot;
+  for (int cell = blockIdx.x; cell < p.n_cells; cell += gridDim.x) {
+    const int U = p.cell_U[cell];
+    if (U > kWarmMaxU || p.r_status[cell] != 0) continue;  // uniform
+    const CellGeo g = load_geo(p, cell);
+    int dr, dc;
+    double f0, f1;
+    cell_features(p, g, U, p.cell_toff[cell], p.alpha, sh, &dr, &dc, &f1);  // converged F~
+    __syncthreads();
+    cell_features(p, g, U, p.cell_toff[cell], alpha_prev, sh, &dr, &dc, &f0);  // start
+    if (threadIdx.x == 0) slot = atomicAdd(count, 1);
+    __syncthreads();
+    const int s = slot;
+    if (s < cap) {
+      if (ids && threadIdx.x == 0) ids[s] = cell;
+      for (int k = threadIdx.x; k < kFeatIn; k += blockDim.x) X[(size_t)s * kFeatIn + k] = sh.f[k];
+      if (threadIdx.x < 64) {
+        const bool a = sh.f[threadIdx.x] > 0.f;  // mu > 0
+        T[(size_t)s * 64 + threadIdx.x] = a ? (float)((f1 - f0) / (kWarmScale * p.lam)) : 0.f;
+        M[(size_t)s * 64 + threadIdx.x] = a ? 1.f : 0.f;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+void launch_warm_features(const HalfParams& p, unsigned short* X, hipStream_t st) {
+  hipLaunchKernelGGL(k_warm_features, dim3(p.n_cells < 4096 ? p.n_cells : 4096), dim3(256), 0, st,
+                     p, X);
+}
+void launch_warm_apply(const HalfParams& p, const float* Y, float min_rms, int* n_applied,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(k_warm_apply, dim3(p.n_cells), dim3(64), 0, st, p, Y, min_rms, n_applied);
+}
+void launch_collect(const HalfParams& p, const double* alpha_prev, float* X, float* T, float* M,
+                    int* ids, int cap, int* count, hipStream_t st) {
+  hipLaunchKernelGGL(k_collect, dim3(p.n_cells < 4096 ? p.n_cells : 4096), dim3(256), 0, st, p,
+                     alpha_prev, X, T, M, ids, cap, count);
+}
+
 // ------------------------------------------------------------ stats
 
 __global__ __launch_bounds__(1024) void k_stats(HalfParams p, IterStatsDev* out) {
@@ -2197,7 +2394,8 @@ __global__ __launch_bounds__(1024) void k_stats(HalfParams p, IterStatsDev* out)
 
 // ------------------------------------------------------------ launchers
 
-void launch_sweep(const HalfParams& p, const SweepStreams& s, const SweepGrid& gr, hipEvent_t* ev) {
+void launch_sweep_prep(const HalfParams& p, const SweepStreams& s, const SweepGrid& gr,
+                       hipEvent_t* ev) {
   auto pre = [&](int k, hipStream_t st) {
     if (ev) hipEventRecord(ev[2 * k], st);
   };
@@ -2214,6 +2412,17 @@ void launch_sweep(const HalfParams& p, const SweepStreams& s, const SweepGrid& g
   pre(2, st);
   hipLaunchKernelGGL(k_scan_out, dim3(1), dim3(1024), 0, st, p);
   post(2, st);
+}
+
+void launch_sweep_solve(const HalfParams& p, const SweepStreams& s, const SweepGrid& gr,
+                        hipEvent_t* ev) {
+  auto pre = [&](int k, hipStream_t st) {
+    if (ev) hipEventRecord(ev[2 * k], st);
+  };
+  auto post = [&](int k, hipStream_t st) {
+    if (ev) hipEventRecord(ev[2 * k + 1], st);
+  };
+  hipStream_t st = s.main;
   // fork: the heaviest bins on their own streams, the light ones on main; each
   // stream ends with the Newton launch for the cells its solvers handed over
   // (events kNKernels + i of ev for the three auxiliary ones)

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/dd.h"
+#include "../../include/dd_mlp.h"
 #include "dd_internal.h"
 
 using ddk::HalfParams;
@@ -94,6 +95,20 @@ struct dd_ctx {
   static_assert(DD_N_KERNELS == ddk::kNKernels, "kernel count of the ABI and the launcher");
   ddk::SweepStreams ss{};
   int* queue = nullptr;
+  // warm start by the network
+  dd_mlp* warm_net = nullptr;
+  int warm_policy = 0;
+  float warm_min_rms = 0.f;
+  int* warm_count = nullptr;        // cells warm-started, summed over sweeps (device)
+  int warm_fresh[2] = {1, 1};     // no sweep of this partition since init/refine/eps change
+  unsigned short* warm_X = nullptr;
+  float* warm_Y = nullptr;
+  int warm_rows = 0;
+  double* alpha_prev = nullptr;   // potentials of the partition at the start of the last sweep
+  int64_t alpha_prev_cap = 0;
+  int* dcount = nullptr;
+  hipEvent_t warm_ev[2] = {};
+  int n_warm_sweeps = 0;
   int n_cu = 0;
   int stream_wgs = 0;
   float* stream_tile = nullptr;
@@ -294,6 +309,11 @@ extern "C" void dd_free(dd_ctx* c) {
   hipFree(c->defer_F);
   hipFree(c->misc);
   hipFree(c->queue);
+  hipFree(c->warm_X);
+  hipFree(c->warm_Y);
+  hipFree(c->warm_count);
+  hipFree(c->alpha_prev);
+  hipFree(c->dcount);
   hipFree(c->stream_tile);
   hipFree(c->stream_S);
   hipFree(c->stream_nu);
@@ -312,6 +332,8 @@ extern "C" void dd_free(dd_ctx* c) {
     if (c->ss.join[i]) hipEventDestroy(c->ss.join[i]);
   }
   if (c->ss.fork) hipEventDestroy(c->ss.fork);
+  for (auto& e : c->warm_ev)
+    if (e) hipEventDestroy(e);
   for (auto& e : c->kev)
     if (e) hipEventDestroy(e);
   delete c;
@@ -483,6 +505,7 @@ extern "C" dd_status dd_init(const double* mu, const double* nu, int H, int W, i
 extern "C" dd_status dd_set_eps(dd_ctx* c, double eps) {
   if (!c) return DD_EINVAL;
   if (!(eps > 0)) return fail(c, DD_EINVAL, "eps must be positive");
+  if (eps != c->eps) c->warm_fresh[0] = c->warm_fresh[1] = 1;
   c->eps = eps;
   return DD_OK;
 }
@@ -541,10 +564,13 @@ static HalfParams make_params(dd_ctx* c, int part) {
   return p;
 }
 
-// Tile buffers of the streamed solver: one per workgroup, two workgroups per
-// compute unit at most (2 MiB each).
+// Tile buffers of the streamed solver: one per workgroup (2 MiB each).  The
+// workgroups loop over the bin's queue, so fewer of them than cells is still
+// correct; size for the bin's cells in the previous sweep plus a margin (64
+// before any sweep), at most two per compute unit.
 static dd_status ensure_stream(dd_ctx* c, int n_cells) {
-  const int want = std::min(n_cells, 2 * c->n_cu);
+  const int prev = c->last.n_cells > 0 ? c->last.cells_bin[ddk::kNBins - 2] + 16 : 64;
+  const int want = std::min(std::min(n_cells, 2 * c->n_cu), prev);
   if (want <= c->stream_wgs) return DD_OK;
   hipFree(c->stream_tile);
   hipFree(c->stream_S);
@@ -573,6 +599,87 @@ static ddk::SweepGrid plan_grid(const dd_ctx* c, int n_cells) {
   return gr;
 }
 
+// Warm start of the eligible cells of this sweep: features (BF16 rows), the
+// network's forward pass on its own stream (ordered with ours through events),
+// and the predicted potential written over alpha.
+static dd_status warm_start(dd_ctx* c, const HalfParams& p) {
+  const int rows = (p.n_cells + 63) / 64 * 64;
+  if (rows > c->warm_rows) {
+    hipFree(c->warm_X);
+    hipFree(c->warm_Y);
+    c->warm_X = nullptr;
+    c->warm_Y = nullptr;
+    c->warm_rows = 0;
+    HIPCHK(c, dmalloc(&c->warm_X, (size_t)rows * ddk::kFeatIn));
+    HIPCHK(c, dmalloc(&c->warm_Y, (size_t)rows * 64));
+    HIPCHK(c, hipMemsetAsync(c->warm_X, 0, sizeof(unsigned short) * rows * ddk::kFeatIn, c->st));
+    c->warm_rows = rows;
+  }
+  if (!c->warm_ev[0]) {
+    HIPCHK(c, hipEventCreateWithFlags(&c->warm_ev[0], hipEventDisableTiming));
+    HIPCHK(c, hipEventCreateWithFlags(&c->warm_ev[1], hipEventDisableTiming));
+  }
+  ddk::launch_warm_features(p, c->warm_X, c->st);
+  hipStream_t ns = (hipStream_t)dd_mlp_get_stream(c->warm_net);
+  HIPCHK(c, hipEventRecord(c->warm_ev[0], c->st));
+  HIPCHK(c, hipStreamWaitEvent(ns, c->warm_ev[0], 0));
+  if (dd_mlp_forward_bf16(c->warm_net, c->warm_X, rows, c->warm_Y) != DD_OK)
+    return fail(c, DD_EHIP, "warm-start network: %s", dd_mlp_last_error(c->warm_net));
+  HIPCHK(c, hipEventRecord(c->warm_ev[1], ns));
+  HIPCHK(c, hipStreamWaitEvent(c->st, c->warm_ev[1], 0));
+  if (!c->warm_count) {
+    HIPCHK(c, dmalloc(&c->warm_count, 1));
+    HIPCHK(c, hipMemsetAsync(c->warm_count, 0, sizeof(int), c->st));
+  }
+  ddk::launch_warm_apply(p, c->warm_Y, c->warm_min_rms, c->warm_count, c->st);
+  HIPCHK(c, hipGetLastError());
+  return DD_OK;
+}
+
+extern "C" dd_status dd_set_warm_start(dd_ctx* c, dd_mlp* net, int policy, float min_rms) {
+  if (!c || policy < 0 || policy > 2 || !(min_rms >= 0)) return DD_EINVAL;
+  if (net) {
+    int n_in = 0, n_out = 0;
+    dd_mlp_shape(net, &n_in, &n_out, nullptr, nullptr);
+    if (n_in != ddk::kFeatIn || n_out != 64)
+      return fail(c, DD_EINVAL, "warm-start network must map %d features to 64 outputs",
+                  ddk::kFeatIn);
+  }
+  c->warm_net = net;
+  c->warm_policy = net ? policy : 0;
+  c->warm_min_rms = min_rms;
+  c->warm_fresh[0] = c->warm_fresh[1] = 1;
+  return DD_OK;
+}
+
+extern "C" dd_status dd_warm_start_count(dd_ctx* c, int* n_sweeps, long long* n_cells) {
+  if (!c) return DD_EINVAL;
+  int n = 0;
+  if (c->warm_count) {
+    HIPCHK(c, hipMemcpyAsync(&n, c->warm_count, sizeof(int), hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));
+  }
+  if (n_sweeps) *n_sweeps = c->n_warm_sweeps;
+  if (n_cells) *n_cells = n;
+  return DD_OK;
+}
+
+extern "C" dd_status dd_collect_cells(dd_ctx* c, float* x_dev, float* t_dev, float* mask_dev,
+                                      int* cell_dev, int cap, int* n_out) {
+  if (!c || !n_out || cap < 0 || (cap > 0 && (!x_dev || !t_dev || !mask_dev))) return DD_EINVAL;
+  if (c->last_part < 0) return fail(c, DD_ESTATE, "no half-iteration on this level yet");
+  if (!c->dcount) HIPCHK(c, dmalloc(&c->dcount, 1));
+  HIPCHK(c, hipMemsetAsync(c->dcount, 0, sizeof(int), c->st));
+  HalfParams p = make_params(c, c->last_part);
+  ddk::launch_collect(p, c->alpha_prev, x_dev, t_dev, mask_dev, cell_dev, cap, c->dcount, c->st);
+  HIPCHK(c, hipGetLastError());
+  int n = 0;
+  HIPCHK(c, hipMemcpyAsync(&n, c->dcount, sizeof(int), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  *n_out = n < cap ? n : cap;
+  return DD_OK;
+}
+
 extern "C" dd_status dd_half_iterate(dd_ctx* c, int part, dd_iter_stats* out) {
   if (!c) return DD_EINVAL;
   if (part != 0 && part != 1) return fail(c, DD_EINVAL, "partition must be 0 or 1");
@@ -587,7 +694,31 @@ extern "C" dd_status dd_half_iterate(dd_ctx* c, int part, dd_iter_stats* out) {
   HIPCHK(c, hipMemsetAsync(c->queue, 0, sizeof(int) * 16, c->st));
   HIPCHK(c, hipEventRecord(c->ev0, c->st));
   hipEvent_t* kev = c->opt.timing ? c->kev : nullptr;
-  ddk::launch_sweep(p, c->ss, plan_grid(c, p.n_cells), kev);
+  const ddk::SweepGrid gr = plan_grid(c, p.n_cells);
+  {
+    // keep the starting potentials of this sweep (training samples, dd_collect_cells)
+    const Level& l = c->L[c->lev];
+    const int64_t npx = (int64_t)l.H * l.W;
+    if (npx > c->alpha_prev_cap) {
+      hipFree(c->alpha_prev);
+      c->alpha_prev = nullptr;
+      c->alpha_prev_cap = 0;
+      HIPCHK(c, dmalloc(&c->alpha_prev, npx));
+      c->alpha_prev_cap = npx;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->alpha_prev, c->alpha[part], sizeof(double) * npx,
+                             hipMemcpyDeviceToDevice, c->st));
+  }
+  ddk::launch_sweep_prep(p, c->ss, gr, kev);
+  const bool warm = c->warm_net && c->warm_policy > 0 &&
+                    (c->warm_policy == 2 || c->warm_fresh[part]);
+  if (warm) {
+    dd_status ws = warm_start(c, p);
+    if (ws) return ws;
+    c->n_warm_sweeps++;
+  }
+  c->warm_fresh[part] = 0;
+  ddk::launch_sweep_solve(p, c->ss, gr, kev);
   HIPCHK(c, hipGetLastError());
   ddk::launch_stats(p, c->dstats, c->st, kev ? kev + 2 * (DD_N_KERNELS - 1) : nullptr);
   HIPCHK(c, hipGetLastError());
@@ -797,6 +928,7 @@ extern "C" dd_status dd_refine(dd_ctx* c) {
   c->lev++;
   c->nb = nbf;
   c->last_part = -1;
+  c->warm_fresh[0] = c->warm_fresh[1] = 1;
   return upload_cells(c);
 }
 

@@ -111,11 +111,12 @@ extern "C" dd_status dd_mlp_create(int n_in, int n_out, int width, unsigned long
     dd_mlp_free(n);
     return DD_ENOMEM;
   }
-  // He initialisation (normal, std sqrt(2/fan_in)), zero biases, from a fixed seed
+  // He initialisation (normal, std sqrt(2/fan_in)), zero biases, from a fixed
+  // seed; the output layer starts 10x smaller (a near-zero initial output)
   std::vector<float> h(off, 0.f);
   std::mt19937_64 rng(seed);
   for (int l = 0; l < 4; l++) {
-    std::normal_distribution<float> nd(0.f, std::sqrt(2.f / d[l]) * (l == 3 ? 0.5f : 1.f));
+    std::normal_distribution<float> nd(0.f, std::sqrt(2.f / d[l]) * (l == 3 ? 0.1f : 1.f));
     for (size_t k = 0; k < (size_t)d[l] * d[l + 1]; k++) h[n->off_w[l] + k] = nd(rng);
   }
   dd_status s = dd_mlp_set_params(n, h.data(), off);
@@ -144,6 +145,8 @@ extern "C" void dd_mlp_free(dd_mlp* n) {
 }
 
 extern "C" const char* dd_mlp_last_error(const dd_mlp* n) { return n ? n->err.c_str() : ""; }
+
+extern "C" void* dd_mlp_get_stream(const dd_mlp* n) { return n ? (void*)n->st : nullptr; }
 
 extern "C" dd_status dd_mlp_shape(const dd_mlp* n, int* n_in, int* n_out, int* width,
                                   size_t* n_params) {

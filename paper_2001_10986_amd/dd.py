@@ -21,7 +21,8 @@ EXPORTED = ["dd_options_default", "dd_init", "dd_half_iterate", "dd_set_eps", "d
             "dd_cell_results", "dd_level_info", "dd_free", "dd_last_error",
             "dd_mlp_create", "dd_mlp_free", "dd_mlp_last_error", "dd_mlp_shape",
             "dd_mlp_set_params", "dd_mlp_get_params", "dd_mlp_forward", "dd_mlp_forward_bf16",
-            "dd_mlp_loss_grad", "dd_mlp_train_step"]
+            "dd_mlp_loss_grad", "dd_mlp_train_step", "dd_mlp_get_stream", "dd_set_warm_start",
+            "dd_collect_cells", "dd_warm_start_count"]
 
 
 class Stage(C.Structure):
@@ -113,6 +114,14 @@ def _load():
     lib.dd_free.restype = None
     lib.dd_last_error.argtypes = [C.c_void_p]
     lib.dd_last_error.restype = C.c_char_p
+    lib.dd_set_warm_start.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_float]
+    lib.dd_warm_start_count.argtypes = [C.c_void_p, P(C.c_int), P(C.c_longlong)]
+    lib.dd_warm_start_count.restype = C.c_int
+    lib.dd_collect_cells.argtypes = [C.c_void_p] + [C.c_void_p] * 4 + [C.c_int, P(C.c_int)]
+    lib.dd_mlp_get_stream.argtypes = [C.c_void_p]
+    lib.dd_mlp_get_stream.restype = C.c_void_p
+    for name in ("dd_set_warm_start", "dd_collect_cells"):
+        getattr(lib, name).restype = C.c_int
     for name in ("dd_init", "dd_half_iterate", "dd_set_eps", "dd_refine", "dd_run_schedule",
                  "dd_cost", "dd_export_plan", "dd_import_state", "dd_cell_results",
                  "dd_level_info"):
@@ -264,6 +273,33 @@ class Problem:
         self._chk(lib.dd_cell_results(self._h, _p(cost), _p(obj), _p(err), _p(loops),
                                       _p(status)), "dd_cell_results")
         return {"cost": cost, "obj": obj, "err_x": err, "loops": loops, "status": status}
+
+    def set_warm_start(self, net, policy=1, min_rms=0.0):
+        """Attach a warm-start network (paper_2001_10986_amd.mlp.MLP; None detaches).
+        policy 1: first sweep of each partition after init/refine/eps change; 2: every
+        sweep; a cell takes the prediction if its predicted change has RMS >= min_rms."""
+        self._warm_net = net  # keep it alive while attached
+        self._chk(lib.dd_set_warm_start(self._h, None if net is None else net.handle,
+                                        policy if net is not None else 0, float(min_rms)),
+                  "dd_set_warm_start")
+
+    def warm_start_count(self):
+        """(sweeps that ran the network, cells that took its start) since init."""
+        a, b = C.c_int(), C.c_longlong()
+        self._chk(lib.dd_warm_start_count(self._h, C.byref(a), C.byref(b)), "dd_warm_start_count")
+        return a.value, b.value
+
+    def collect_cells(self, x, t, m, ids=None):
+        """Training samples of the last half-iteration into the torch CUDA tensors
+        x (cap x 768), t (cap x 64), m (cap x 64) and optionally ids (cap, int32:
+        cell index per row); returns the number of rows."""
+        n = C.c_int()
+        cap = x.shape[0]
+        self._chk(lib.dd_collect_cells(self._h, C.c_void_p(x.data_ptr()), C.c_void_p(t.data_ptr()),
+                                       C.c_void_p(m.data_ptr()),
+                                       None if ids is None else C.c_void_p(ids.data_ptr()), cap,
+                                       C.byref(n)), "dd_collect_cells")
+        return n.value
 
     def basic_marginals(self):
         e = self.export()
