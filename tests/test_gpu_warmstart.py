@@ -80,10 +80,10 @@ def test_collected_samples_match_cpu_recompute(torch):
     from paper_2001_10986_amd import dd
     N = 64
     mu, nu = datagen.small_pair(N, 4, seed=9)
-    eps = 4.0 / N ** 2
+    eps = 1.0 / N ** 2
     g = dd.Problem(mu, nu, [(0, eps, 4)], s=4, n_levels=1)
     o = ddo.Oracle(mu, nu, s=4, n_levels=1, eps=eps)
-    for k in range(4):  # from the product coupling every union is the whole image
+    for k in range(6):  # from the product coupling every union is the whole image
         g.half_iterate(k & 1)
     for part in (0, 1, 0):
         prev = g.export()
