@@ -17,6 +17,30 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP32_FMA_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12  # 78.6: non-packed FP32 FMA issue rate
 
+# HBM bytes per launch of the solver kernels on the 1024x1024 schedule, from
+# rocprofv3 FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch, FETCH scaled by
+# 2.0 and WRITE by 1.0, the factors a plain 256 MiB device copy gives); the
+# summary is kept under profiles/.  Valid only for the kernel source the
+# counters were taken on, identified by its hash.
+TRAFFIC_KERNEL_SHA256 = "5397b0b26b18938b5116e0bf7d0a1510455c8666d0ad5929cb91f486730af311"
+TRAFFIC_BYTES_PER_LAUNCH = {
+    "solve_reg_16w": (2.0 * 73093 + 228981) * 1024,
+    "solve_reg_8w": (2.0 * 8482 + 15291) * 1024,
+    "solve_stream": (2.0 * 2328310 + 245373) * 1024,
+}
+
+
+def kernel_traffic(name, config):
+    """Measured HBM bytes per launch, or None if not measured for this build."""
+    import hashlib
+    if config != 3 or name not in TRAFFIC_BYTES_PER_LAUNCH:
+        return None
+    src = os.path.join(ROOT, "paper_2001_10986_amd", "csrc", "dd_kernels.hip")
+    with open(src, "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != TRAFFIC_KERNEL_SHA256:
+            return None
+    return TRAFFIC_BYTES_PER_LAUNCH[name]
+
 
 def main():
     ap = argparse.ArgumentParser()
@@ -107,7 +131,8 @@ def main():
     achieved = flops / (tot_ms[solver] / 1000) / 1e12 if tot_ms[solver] > 0 else 0.0
     roof = {"kernel": dd.KERNEL_NAMES[solver], "bound": "alu", "achieved": achieved,
             "peak": PEAK_FP32_FMA_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_FMA_TFLOPS,
-            "traffic": None, "launches": launches,
+            "traffic": kernel_traffic(dd.KERNEL_NAMES[solver], args.config),
+            "traffic_unit": "HBM bytes per launch", "launches": launches,
             "avg_launch_ms": tot_ms[solver] / max(launches, 1),
             "flops_per_launch": flops / max(launches, 1)}
     kernel_ms = {dd.KERNEL_NAMES[k]: tot_ms[k] / args.steps for k in range(dd.N_KERNELS)}

@@ -122,7 +122,8 @@ typedef struct {
   int64_t nnz_max;
   double ms_total;         /* wall time of the whole schedule (ms) */
   double ms_kernel[DD_N_KERNELS];   /* summed per-kernel device time when timing is on */
-  int launches_bin[DD_N_BINS];      /* solver launches that had cells, per bin */
+  int launches_bin[DD_N_BINS];      /* solver launches per bin (one per sweep, also when
+                                       the bin is empty: such a launch exits at once) */
   int64_t evals_bin[DD_N_BINS];
 } dd_run_stats;
 

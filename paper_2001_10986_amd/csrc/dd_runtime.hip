@@ -960,7 +960,7 @@ extern "C" dd_status dd_run_schedule(dd_ctx* c, dd_run_stats* out) {
       rs.nnz_max = std::max(rs.nnz_max, it.nnz);
       for (int b = 0; b < DD_N_KERNELS; b++) rs.ms_kernel[b] += it.ms_kernel[b];
       for (int b = 0; b < DD_N_BINS; b++) {
-        rs.launches_bin[b] += it.cells_bin[b] > 0;
+        rs.launches_bin[b] += 1;  // every bin's solver is launched each sweep
         rs.evals_bin[b] += it.evals_bin[b];
       }
     }
