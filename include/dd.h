@@ -176,7 +176,9 @@ dd_status dd_init(const double* mu, const double* nu, int height, int width, int
 
 /* One sweep of Algorithm 2 over all composite cells of partition 0 (A) or
  * 1 (B) on the current level.  stats (nullable) receives the per-sweep
- * counters; the call synchronises the context stream. */
+ * counters; the call synchronises the context stream.  DD_ECAPACITY if the
+ * level has more than 2^21 cells in the partition (images above ~11500^2);
+ * DD_ESTATE while the context belongs to a batch. */
 dd_status dd_half_iterate(dd_ctx* ctx, int partition, dd_iter_stats* stats);
 
 /* Change eps; the potentials f = eps*log u stay as they are (end of Sec. 6.4). */
@@ -216,6 +218,62 @@ void dd_free(dd_ctx* ctx);
 
 /* Message of the last error on ctx (or of the last failed dd_init when ctx is NULL). */
 const char* dd_last_error(const dd_ctx* ctx);
+
+/* ---- Batches of independent problems ----------------------------------
+ * The composite cells of one partition are independent subproblems
+ * (Algorithm 2), and so are the cells of different problems.  A batch runs
+ * the sweeps of several problems together: one set of solver launches per
+ * sweep takes the cells of every problem, binned by Y-support size, so that
+ * many small images fill the GPU as one large one does.  Each problem keeps
+ * its own state, eps, level and schedule; the results are the ones its own
+ * dd_half_iterate would give (the kernels and their order per cell are the
+ * same).
+ *
+ * The contexts stay owned by the caller and must outlive the batch; they
+ * must share one stream (dd_options.stream).  While the batch exists their
+ * own dd_half_iterate and dd_run_schedule return DD_ESTATE (every other call
+ * stays valid), and a context belongs to at most one batch.  The network
+ * warm start (dd_set_warm_start) is not applied to batched sweeps. */
+typedef struct dd_batch dd_batch;
+
+/* Flags of dd_batch_create. */
+#define DD_BATCH_GRAPH 1 /* capture the launches of a sweep in a HIP graph and replay
+                            it while the sweep's shape (problems, level sizes, buffer
+                            capacities) stays the same; the per-problem parameters are
+                            read from device memory, refreshed before every replay */
+
+/* Create a batch of n (1 <= n <= 1024) distinct contexts.  DD_EINVAL for a
+ * NULL or repeated context, one already in a batch, or mixed streams. */
+dd_status dd_batch_create(dd_ctx* const* ctxs, int n, int flags, dd_batch** out);
+
+/* One sweep of partition 0 (A) or 1 (B) over every problem of the batch.
+ * stats: NULL or n entries (problem order of dd_batch_create); ms and
+ * ms_kernel there are those of the whole batched sweep. */
+dd_status dd_batch_half_iterate(dd_batch* batch, int partition, dd_iter_stats* stats);
+
+/* Run every problem's own dd_init schedule from its current stage, in
+ * lockstep: sweep t of the batch runs sweep t of every problem that has one
+ * left, after that problem's refinements and eps changes; problems whose
+ * schedule has ended drop out.  stats: NULL or n entries. */
+dd_status dd_batch_run_schedule(dd_batch* batch, dd_run_stats* stats);
+
+/* One step of dd_batch_run_schedule: a single lockstep sweep.  *n_active
+ * receives the number of problems that took part (0 once every schedule has
+ * ended); stats: NULL or n entries, zero for problems not in the sweep.  A
+ * caller can interleave its own work (progress, checkpoints) between steps;
+ * a context taken out of the batch resumes its schedule at the start of the
+ * stage it was in. */
+dd_status dd_batch_schedule_step(dd_batch* batch, dd_iter_stats* stats, int* n_active);
+
+/* Sweeps run and graph captures made by the batch so far (nullable outputs). */
+dd_status dd_batch_info(const dd_batch* batch, int* n_problems, long long* n_sweeps,
+                        int* n_captures);
+
+/* Release the batch (not its contexts, which return to their own sweeps). */
+void dd_batch_free(dd_batch* batch);
+
+/* Message of the last error on the batch. */
+const char* dd_batch_last_error(const dd_batch* batch);
 
 #ifdef __cplusplus
 }

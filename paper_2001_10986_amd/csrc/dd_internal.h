@@ -50,21 +50,38 @@ struct HalfParams {
   int* r_loops;
   int* r_status;
   long long* r_evals;
-  long long* misc;             // [0] nnz_in, [1] out entries, [2] bad-row flag,
-                               // [4 + g] cells handed to Newton steps in group g
-  int* queue;                  // next cell of each solver launch's list (kNBins + groups)
+  long long* misc;             // [0] nnz_in, [1] out entries, [2] bad-row flag
+  double* defer_F;             // potentials of cells handed to Newton steps (units of eps),
+                               // 64 per cell, indexed by cell
+  long long capE;              // entry buffer capacity (rows are checked against it)
+};
+
+constexpr int kNDeferGroups = 4;  // Newton launches per sweep (one per stream)
+
+// A sweep runs the cells of one or more problems (each with its own
+// HalfParams, in a device array) through the same solver launches.  A work
+// item names a problem and one of its cells.
+constexpr int kItemShift = 21;
+constexpr int kItemCellMask = (1 << kItemShift) - 1;
+constexpr int kMaxProblems = 1 << (31 - kItemShift);
+struct SweepSched {
+  int n_prob;
+  int cap;                     // items each bin list / Newton list can hold
+  int* bin_count;              // kNBins: items per bin over all problems
+  int* bin_list;               // kNBins * cap items, problem-major within a bin
+  int* queue;                  // next item of each solver launch (kNBins + kNDeferGroups)
+  int* defer_count;            // kNDeferGroups: items handed to Newton steps per group
+  int* defer_list;             // kNDeferGroups * cap items
   float* stream_tile;          // streamed solver: kStreamTileFloats per workgroup
   float* stream_S;             // streamed solver: S(y), kStreamMaxU per workgroup
   float* stream_nu;            // streamed solver: nu_J(y) in FP32, kStreamMaxU per workgroup
   int stream_wgs;              // workgroups the streamed-solver buffers are sized for
-  int* defer_list;             // cells handed to the Newton solver, n_cells per group
-  double* defer_F;             // their potentials (units of eps), 64 per cell, indexed by cell
-  long long capE;              // entry buffer capacity (rows are checked against it)
 };
 
 struct IterStatsDev {
   double cost, obj, err;
   long long loops_total, evals, nnz;
+  long long out_entries, bad_rows;  // entries the sweep wrote; rows found out of range
   int loops_max, n_failed, n_safeguard, n_newton, n_cells;
   long long evals_bin[kNBins];
   int cells_bin[kNBins];
@@ -80,7 +97,6 @@ struct SweepStreams {
 };
 constexpr int kNKernels = 12;  // scan, union, scan_out, 5 register, streamed, big, newton, stats
 
-constexpr int kNDeferGroups = 4;  // Newton launches per sweep (one per stream)
 constexpr int kNEvents = 2 * (kNKernels + kNDeferGroups - 1);
 
 // Kernel launchers (all asynchronous).  ev: nullptr, or kNEvents events;
@@ -91,15 +107,18 @@ constexpr int kNEvents = 2 * (kNKernels + kNDeferGroups - 1);
 struct SweepGrid {
   int bin[kNBins];   // solver launches of bins 0..kNBins-1
   int newton;        // the launch for the cells handed over to Newton steps
-  int other;         // union kernel
+  int other;         // union kernel: workgroups per problem
 };
-// A sweep is prep (cell sizes, unions, bins) then solve (the concurrent solver
-// launches and the Newton launches); a warm start may run in between.
-void launch_sweep_prep(const HalfParams& p, const SweepStreams& s, const SweepGrid& gr,
-                       hipEvent_t* ev);
-void launch_sweep_solve(const HalfParams& p, const SweepStreams& s, const SweepGrid& gr,
-                        hipEvent_t* ev);
-void launch_stats(const HalfParams& p, IterStatsDev* out, hipStream_t st, hipEvent_t* ev2);
+// A sweep is prep (cell sizes, unions, per-problem bins, then the merged work
+// lists) and solve (the concurrent solver launches and the Newton launches);
+// a warm start may run in between.  P: device array of s.n_prob HalfParams.
+void launch_sweep_prep(const HalfParams* P, const SweepSched& s, const SweepStreams& ss,
+                       const SweepGrid& gr, hipEvent_t* ev);
+void launch_sweep_solve(const HalfParams* P, const SweepSched& s, const SweepStreams& ss,
+                        const SweepGrid& gr, hipEvent_t* ev);
+// Per-problem statistics of the sweep: out[k] for problem k.
+void launch_stats(const HalfParams* P, int n_prob, IterStatsDev* out, hipStream_t st,
+                  hipEvent_t* ev2);
 size_t sweep_max_static_lds();
 
 void launch_validate(const double* mu, const double* nu, int H, int W, double* out4,

@@ -134,8 +134,10 @@ DEVI void split_key(int key, int W, double invW, int* r, int* c) {
 // ------------------------------------------------------------ scans over cells
 
 // cell_toff = exclusive scan of T_J = sum of the row lengths of J's basic cells
-__global__ __launch_bounds__(1024) void k_scan_T(HalfParams p) {
+__global__ __launch_bounds__(1024) void k_scan_T(const HalfParams* __restrict__ P) {
   __shared__ long long sh[16];
+  const HalfParams& p = P[blockIdx.x];
+  if (threadIdx.x == 0) p.misc[2] = 0;  // bad-row flag, raised by the union kernel
   long long carry = 0;
   for (int base = 0; base < p.n_cells; base += 1024) {
     int i = base + threadIdx.x;
@@ -172,7 +174,8 @@ DEVI int bin_of(int U) {
 }
 
 // cell_ooff = exclusive scan of |J| * U_J; stable lists of cells per size bin
-__global__ __launch_bounds__(1024) void k_scan_out(HalfParams p) {
+__global__ __launch_bounds__(1024) void k_scan_out(const HalfParams* __restrict__ P) {
+  const HalfParams& p = P[blockIdx.x];
   __shared__ long long sh[16];
   __shared__ int swc[16][kNBins];
   __shared__ int srun[kNBins];
@@ -220,6 +223,31 @@ __global__ __launch_bounds__(1024) void k_scan_out(HalfParams p) {
   if (threadIdx.x == 0) p.misc[1] = carry;
 }
 
+// Work lists of the sweep: the per-problem bin lists concatenated in problem
+// order (workgroup k copies problem k's items), and the launch counters
+// cleared (a kernel rather than a memset, so that a captured graph holds no
+// memset nodes).
+__global__ __launch_bounds__(256) void k_sched(const HalfParams* __restrict__ P, SweepSched s) {
+  const int k = blockIdx.x;
+  const HalfParams& p = P[k];
+  if (k == 0 && threadIdx.x < kNBins + kNDeferGroups) {
+    s.queue[threadIdx.x] = 0;
+    if (threadIdx.x < kNDeferGroups) s.defer_count[threadIdx.x] = 0;
+  }
+  for (int b = 0; b < kNBins; b++) {
+    int off = 0, tot = 0;
+    for (int j = 0; j < s.n_prob; j++) {
+      const int c = P[j].bin_count[b];
+      off += j < k ? c : 0;
+      tot += c;
+    }
+    if (k == 0 && threadIdx.x == 0) s.bin_count[b] = tot;
+    const int n = p.bin_count[b];
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+      s.bin_list[(int64_t)b * s.cap + off + i] = (k << kItemShift) | p.bin_list[b * p.n_cells + i];
+  }
+}
+
 // ------------------------------------------------------------ union (gather)
 
 // Sorted union of up to four sorted rows and the summed masses.  The keys are
@@ -230,7 +258,8 @@ __global__ __launch_bounds__(1024) void k_scan_out(HalfParams p) {
 constexpr int kUnionThreads = 256;
 constexpr int kBitWords = 2048;  // 65536 bits per band
 
-__global__ __launch_bounds__(kUnionThreads) void k_union(HalfParams p) {
+__global__ __launch_bounds__(kUnionThreads) void k_union(const HalfParams* __restrict__ P) {
+  const HalfParams& p = P[blockIdx.y];
   __shared__ uint32_t bits[kBitWords];
   __shared__ int wpre[kBitWords];
   __shared__ int shi[8];
@@ -702,23 +731,26 @@ DEVI XUpdate x_update(float r, double mu, float u, float* lup, float* unew_out, 
 }
 
 template <int NW>
-__global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
+__global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restrict__ P,
+                                                       SweepSched s, int bin) {
   __shared__ RegShared<NW> sh;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int xg = lane & 7, yg = lane >> 3;
   const int ybase = wave * 64 + yg * 8;  // first of the lane's 8 support points
-  const int count = p.bin_count[bin];
-  const double invW = 1.0 / p.W;
+  const int count = s.bin_count[bin];
   float* rd = sh.red[wave];
   float* uw = sh.uw[wave];
   for (;;) {
-    // next cell of this bin (a work queue, so that slow cells do not hold up
+    // next item of this bin (a work queue, so that slow cells do not hold up
     // the cells behind them)
-    if (tid == 0) sh.next = atomicAdd(&p.queue[bin], 1);
+    if (tid == 0) sh.next = atomicAdd(&s.queue[bin], 1);
     __syncthreads();
     const int ci = sh.next;
     if (ci >= count) break;
-    const int cell = p.bin_list[bin * p.n_cells + ci];
+    const int item = __builtin_amdgcn_readfirstlane(s.bin_list[(int64_t)bin * s.cap + ci]);
+    const HalfParams& p = P[item >> kItemShift];
+    const int cell = item & kItemCellMask;
+    const double invW = 1.0 / p.W;
     const CellGeo g = load_geo(p, cell);
     const int U = p.cell_U[cell];
     const int64_t ub = p.cell_toff[cell];
@@ -964,10 +996,8 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(HalfParams p, int bin) {
                 sh.mu[tid] > 0 ? sh.F0[tid] + log((double)uw[tid]) : 0.0;
           if (tid == 0) {
             const int grp = defer_group(bin);
-            const unsigned long long slot =
-                atomicAdd(reinterpret_cast<unsigned long long*>(&p.misc[4 + grp]), 1ull);
-            if (slot < (unsigned long long)p.n_cells)
-              p.defer_list[(int64_t)grp * p.n_cells + slot] = cell;
+            const int slot = atomicAdd(&s.defer_count[grp], 1);  // < cap: one per item
+            s.defer_list[(int64_t)grp * s.cap + slot] = item;
             p.r_loops[cell] = it;
           }
           deferred = true;
@@ -1113,24 +1143,27 @@ DEVI float4* tile_at(float* base, int slab, int wave, int k, int lane) {
   return reinterpret_cast<float4*>(base) + ((size_t)((slab * kSW + wave) * 16 + k) * 64 + lane);
 }
 
-__global__ __launch_bounds__(kSlab) void k_solve_stream(HalfParams p) {
+__global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __restrict__ P,
+                                                        SweepSched s) {
   __shared__ StreamShared sh;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int xg = lane & 7, yg = lane >> 3;
   const int yoff = wave * 64 + yg * 8;  // first of the lane's 8 points within a slab
   const int bin = kNBins - 2;
-  const int count = p.bin_count[bin];
-  const double invW = 1.0 / p.W;
+  const int count = s.bin_count[bin];
   float* rd = sh.red[wave];
-  float* tileb = p.stream_tile + (size_t)blockIdx.x * kStreamTileFloats;
-  float* Sg = p.stream_S + (size_t)blockIdx.x * kStreamMaxU;
-  float* nug = p.stream_nu + (size_t)blockIdx.x * kStreamMaxU;
+  float* tileb = s.stream_tile + (size_t)blockIdx.x * kStreamTileFloats;
+  float* Sg = s.stream_S + (size_t)blockIdx.x * kStreamMaxU;
+  float* nug = s.stream_nu + (size_t)blockIdx.x * kStreamMaxU;
   for (;;) {
-    if (tid == 0) sh.next = atomicAdd(&p.queue[bin], 1);
+    if (tid == 0) sh.next = atomicAdd(&s.queue[bin], 1);
     __syncthreads();
     const int ci = sh.next;
     if (ci >= count) break;
-    const int cell = p.bin_list[bin * p.n_cells + ci];
+    const int item = __builtin_amdgcn_readfirstlane(s.bin_list[(int64_t)bin * s.cap + ci]);
+    const HalfParams& p = P[item >> kItemShift];
+    const int cell = item & kItemCellMask;
+    const double invW = 1.0 / p.W;
     const CellGeo g = load_geo(p, cell);
     const int U = min(p.cell_U[cell], kStreamMaxU);  // the bin holds U <= kStreamMaxU only
     const int nslab = (U + kSlab - 1) / kSlab;
@@ -1429,10 +1462,8 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(HalfParams p) {
                 sh.mu[tid] > 0 ? sh.F0[tid] + log((double)sh.u[tid]) : 0.0;
           if (tid == 0) {
             const int grp = defer_group(bin);
-            const unsigned long long slot =
-                atomicAdd(reinterpret_cast<unsigned long long*>(&p.misc[4 + grp]), 1ull);
-            if (slot < (unsigned long long)p.n_cells)
-              p.defer_list[(int64_t)grp * p.n_cells + slot] = cell;
+            const int slot = atomicAdd(&s.defer_count[grp], 1);  // < cap: one per item
+            s.defer_list[(int64_t)grp * s.cap + slot] = item;
             p.r_loops[cell] = it;
           }
           deferred = true;
@@ -1594,10 +1625,10 @@ struct BigShared {
     struct {
       double pm[kBigWaves][64], ps[kBigWaves][64];
     } lse;                       // Sinkhorn X-marginal partials
-    float q[64][kNChunk + 1];    // Newton: p_x(y) sqrt(nu_J(y)) of one chunk of support points
+    double q[64][kNChunk + 1];   // Newton: p_x(y) sqrt(nu_J(y)) of one chunk of support points
     double racc[kBigWaves][64];  // Newton: X-marginal partials per wave
   } u;
-  float Wm[64][65];              // Newton: weights W(x,x')
+  double Wm[64][65];             // Newton: weights W(x,x'), eliminated in place
   double err, slope;
   int last;                // last active pixel (ground of the Laplacian system)
   int nact;                // active pixels (mu > 0)
@@ -1622,13 +1653,7 @@ DEVI float phi1f(float b) {
   return (fast_exp2(b * (float)kLog2e) - 1.f) - b;
 }
 
-typedef short short4_t __attribute__((ext_vector_type(4)));
-typedef float floatx16 __attribute__((ext_vector_type(16)));
-// FP32 -> BF16, round to nearest even (finite inputs)
-DEVI short bf16_rn(float f) {
-  const unsigned u = __float_as_uint(f);
-  return (short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
-}
+typedef double doublex4 __attribute__((ext_vector_type(4)));
 
 // Sum / max over the 16 lanes of a DPP row (quad swaps and row rotations, so
 // every lane ends with the result).
@@ -1664,7 +1689,9 @@ DEVI double cond_plan(const BigShared& sh, int r, int c, int xs, double lam, dou
   double v[4], s = 0;
 #pragma unroll
   for (int k = 0; k < 4; k++) {
-    v[k] = e[k] == -INFINITY ? 0.0 : (double)fast_exp2((float)((e[k] - m) * kLog2e));
+    // FP64: the plans of far-apart pixels underflow FP32, and the Newton
+    // system needs exactly those weak couplings
+    v[k] = e[k] == -INFINITY ? 0.0 : exp(e[k] - m);
     s += v[k];
   }
   s = row16_sum(s);
@@ -1674,21 +1701,25 @@ DEVI double cond_plan(const BigShared& sh, int r, int c, int xs, double lam, dou
   return m + log(s);
 }
 
-__global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mode) {
+__global__ __launch_bounds__(kBigThreads) void k_solve_big(const HalfParams* __restrict__ P,
+                                                           SweepSched s, int mode) {
   __shared__ BigShared sh;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int yl = tid >> 4, xs = tid & 15;  // Newton layout: kNChunk support points x 16 threads
   const bool deferred = mode >= 1;
   const int grp = mode - 1;  // Newton group of the handed-over cells
-  const int count = deferred ? (int)p.misc[4 + grp] : p.bin_count[kNBins - 1];
-  const double invW = 1.0 / p.W;
+  const int count = deferred ? s.defer_count[grp] : s.bin_count[kNBins - 1];
   for (;;) {
-    if (tid == 0) sh.next = atomicAdd(&p.queue[deferred ? kNBins + grp : kNBins - 1], 1);
+    if (tid == 0) sh.next = atomicAdd(&s.queue[deferred ? kNBins + grp : kNBins - 1], 1);
     __syncthreads();
     const int ci = sh.next;
     if (ci >= count) break;
-    const int cell = deferred ? p.defer_list[(int64_t)grp * p.n_cells + ci]
-                              : p.bin_list[(kNBins - 1) * p.n_cells + ci];
+    const int item = __builtin_amdgcn_readfirstlane(
+        deferred ? s.defer_list[(int64_t)grp * s.cap + ci]
+                 : s.bin_list[(int64_t)(kNBins - 1) * s.cap + ci]);
+    const HalfParams& p = P[item >> kItemShift];
+    const int cell = item & kItemCellMask;
+    const double invW = 1.0 / p.W;
     const CellGeo g = load_geo(p, cell);
     const int U = p.cell_U[cell];
     const int64_t ub = p.cell_toff[cell];
@@ -1832,10 +1863,14 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mod
           const bool build_w = nst < kNewtonMaxSteps && n_act > 1;
           // ---- Y-iteration with conditional plans, X-marginal r, weights W
           double racc[4] = {0, 0, 0, 0};
-          // W = Q Q^T by BF16 matrix cores (FP32 accumulation): waves 0..3 own
-          // the 32x32 quadrant (wave>>1, wave&1); W only steers the Newton step,
-          // the error and the line search stay in FP32/FP64
-          floatx16 wacc = {};
+          // W = Q Q^T by FP64 matrix cores: wave w owns the 16x16 tiles
+          // (w>>1, 2(w&1)) and (w>>1, 2(w&1)+1).  The couplings of far-apart
+          // pixels are tiny and the Newton step follows the smallest
+          // eigenvalues of the Laplacian, so W is formed and eliminated in FP64.
+          doublex4 wacc0 = {}, wacc1 = {};
+          const int wr = 16 * (wave >> 1) + (lane & 15);       // row of Q for operand A
+          const int wc = 16 * (2 * (wave & 1)) + (lane & 15);  // row of Q for operand B
+          const int wk = lane >> 4;                            // k within a step of 4
           for (int y0 = 0; y0 < U; y0 += kNChunk) {
             const int yi = y0 + yl;
             double pk[4] = {0, 0, 0, 0};
@@ -1848,26 +1883,18 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mod
 #pragma unroll
               for (int k = 0; k < 4; k++) racc[k] += nu * pk[k];
               if (xs == 0) G[yi] = -lse + (nu > 0 ? log(nu) : -INFINITY);
-              sq = (double)sqrtf((float)nu);
+              sq = sqrt(nu);
             }
             if (build_w) {
 #pragma unroll
-              for (int k = 0; k < 4; k++) sh.u.q[xs + 16 * k][yl] = (float)(pk[k] * sq);
+              for (int k = 0; k < 4; k++) sh.u.q[xs + 16 * k][yl] = pk[k] * sq;
               __syncthreads();
-              if (wave < 4) {
-                const float* qa = sh.u.q[32 * (wave >> 1) + (lane & 31)];
-                const float* qb = sh.u.q[32 * (wave & 1) + (lane & 31)];
-                const int kh = 4 * (lane >> 5);
 #pragma unroll
-                for (int k0 = 0; k0 < kNChunk; k0 += 8) {
-                  short4_t a, b;
-#pragma unroll
-                  for (int t = 0; t < 4; t++) {
-                    a[t] = bf16_rn(qa[k0 + kh + t]);
-                    b[t] = bf16_rn(qb[k0 + kh + t]);
-                  }
-                  wacc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, b, wacc, 0, 0, 0);
-                }
+              for (int k0 = 0; k0 < kNChunk; k0 += 4) {
+                const double a = sh.u.q[wr][k0 + wk];
+                wacc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sh.u.q[wc][k0 + wk], wacc0, 0, 0, 0);
+                wacc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sh.u.q[wc + 16][k0 + wk], wacc1, 0,
+                                                             0, 0);
               }
               __syncthreads();
             }
@@ -1880,11 +1907,14 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mod
           if (lane < 16)
 #pragma unroll
             for (int k = 0; k < 4; k++) sh.u.racc[wave][lane + 16 * k] = racc[k];
-          if (build_w && wave < 4)
+          if (build_w)
 #pragma unroll
-            for (int v = 0; v < 16; v++)  // D(i,j): i = 8(v/4) + 4(lane/32) + v%4, j = lane%32
-              sh.Wm[32 * (wave >> 1) + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3)]
-                   [32 * (wave & 1) + (lane & 31)] = wacc[v];
+            for (int v = 0; v < 4; v++) {  // D(i,j): i = 4v + lane/16, j = lane%16
+              const int i = 16 * (wave >> 1) + 4 * v + (lane >> 4);
+              const int j = 32 * (wave & 1) + (lane & 15);
+              sh.Wm[i][j] = wacc0[v];
+              sh.Wm[i][j + 16] = wacc1[v];
+            }
           __syncthreads();
           if (wave == 0) {
             double r = 0;
@@ -1906,57 +1936,43 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(HalfParams p, int mod
           double t = 1.0;
           if (build_w) {
             nst++;
+            // right side g - r sum(g)/sum(r), g = mu - r
             if (wave == 0) {
-              // right side g - r sum(g)/sum(r), g = mu - r; then GTH elimination with
-              // row `lane` of W in registers (W is symmetric, its diagonal is never read)
               const double mu = sh.mu[lane], r = sh.r[lane];
               const double gx = mu > 0 ? mu - r : 0.0;
               const double sg = wave_sum_dpp(gx), sr = wave_sum_dpp(r);
-              double bb = gx - r * (sg / sr);
-              const int last = sh.last;
-              float w[64];
-#pragma unroll
-              for (int j = 0; j < 64; j++) w[j] = sh.Wm[j][lane];
-              double piv = 0;  // lane k: pivot k
-#pragma unroll
-              for (int k = 0; k < 63; k++) {
-                if (k < last) {
-                  // pivot: remaining weights of row k (taken from column k by symmetry)
-                  const double dk = wave_sum_dpp(lane > k ? (double)w[k] : 0.0);
-                  if (lane == k) piv = dk;
-                  if (dk > 0) {
-                    const float cf = lane > k ? (float)((double)w[k] / dk) : 0.f;
-                    const double bk = __builtin_bit_cast(
-                        double, ((long long)__builtin_amdgcn_readlane(
-                                     (int)(__builtin_bit_cast(long long, bb) >> 32), k)
-                                 << 32) |
-                                    (unsigned int)__builtin_amdgcn_readlane(
-                                        (int)(__builtin_bit_cast(long long, bb) & 0xffffffffll), k));
-                    bb += (double)cf * bk;
-#pragma unroll
-                    for (int j = k + 1; j < 64; j++) {
-                      const float wkj = __builtin_bit_cast(
-                          float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, w[j]), k));
-                      w[j] = fmaf(cf, wkj, w[j]);
-                    }
-                  }
+              sh.b[lane] = gx - r * (sg / sr);
+            }
+            __syncthreads();
+            // subtraction-free (GTH) elimination of the Laplacian of W in LDS,
+            // grounded at the last active pixel: the pivot of row k is the sum
+            // of its remaining weights (every wave reduces it itself), then the
+            // trailing weights take W(i,k) W(k,j) / d_k, one row per wave
+            const int last = sh.last;
+            for (int k = 0; k < last; k++) {
+              const double dk = wave_sum_dpp(lane > k ? sh.Wm[k][lane] : 0.0);
+              if (tid == 0) sh.piv[k] = dk;
+              if (dk > 0) {
+                const double inv = 1.0 / dk;
+                if (wave == 0 && lane > k) sh.b[lane] += sh.Wm[lane][k] * inv * sh.b[k];
+                for (int i = k + 1 + wave; i < 64; i += kBigWaves) {
+                  const double c = sh.Wm[i][k] * inv;
+                  if (lane > k && lane != i && c != 0) sh.Wm[i][lane] += c * sh.Wm[k][lane];
                 }
               }
-              // back substitution from the ground down: d_k = (b_k + sum_{j>k} W(k,j) d_j) / piv_k
-              const double inv = piv > 0 ? 1.0 / piv : 0.0;
-              double acc = 0, dl = 0;
-#pragma unroll
-              for (int k = 62; k >= 0; k--) {
-                if (k < last) {
-                  const double own = lane == k ? (bb + acc) * inv : 0.0;
-                  const long long q = __builtin_bit_cast(long long, own);
-                  const double dk = __builtin_bit_cast(
-                      double, ((long long)__builtin_amdgcn_readlane((int)(q >> 32), k) << 32) |
-                                  (unsigned int)__builtin_amdgcn_readlane((int)(q & 0xffffffffll), k));
-                  if (lane == k) dl = dk;
-                  acc += (double)w[k] * dk;
-                }
+              __syncthreads();
+            }
+            if (wave == 0) {
+              // back substitution from the ground down: d_k = (b_k + sum_{j>k} W(k,j) d_j) / d_k
+              double dl = 0;  // lane k: d_k
+              for (int k = last - 1; k >= 0; k--) {
+                const double sk = wave_sum_dpp(lane > k ? sh.Wm[k][lane] * dl : 0.0);
+                const double pv = sh.piv[k];
+                const double dk = pv > 0 ? (sh.b[k] + sk) / pv : 0.0;
+                if (lane == k) dl = dk;
               }
+              const double mu = sh.mu[lane];
+              const double gx = mu > 0 ? mu - sh.r[lane] : 0.0;
               double dx = dl;
               const double dm = wave_max(fabs(dx));
               if (dm > kNewtonStepCap) dx *= kNewtonStepCap / dm;
@@ -2310,7 +2326,10 @@ void launch_collect(const HalfParams& p, const double* alpha_prev, float* X, flo
 
 // ------------------------------------------------------------ stats
 
-__global__ __launch_bounds__(1024) void k_stats(HalfParams p, IterStatsDev* out) {
+__global__ __launch_bounds__(1024) void k_stats(const HalfParams* __restrict__ P,
+                                                IterStatsDev* out) {
+  const HalfParams& p = P[blockIdx.x];
+  out += blockIdx.x;
   __shared__ double shd[16];
   __shared__ long long shl[16];
   double c = 0, o = 0, e = 0;
@@ -2380,6 +2399,8 @@ __global__ __launch_bounds__(1024) void k_stats(HalfParams p, IterStatsDev* out)
     out->loops_total = lt;
     out->evals = ev;
     out->nnz = nnz;
+    out->out_entries = p.misc[1];
+    out->bad_rows = p.misc[2];
     out->loops_max = (int)m;
     out->n_failed = nf;
     out->n_safeguard = ns;
@@ -2394,78 +2415,79 @@ __global__ __launch_bounds__(1024) void k_stats(HalfParams p, IterStatsDev* out)
 
 // ------------------------------------------------------------ launchers
 
-void launch_sweep_prep(const HalfParams& p, const SweepStreams& s, const SweepGrid& gr,
-                       hipEvent_t* ev) {
+void launch_sweep_prep(const HalfParams* P, const SweepSched& s, const SweepStreams& ss,
+                       const SweepGrid& gr, hipEvent_t* ev) {
   auto pre = [&](int k, hipStream_t st) {
     if (ev) hipEventRecord(ev[2 * k], st);
   };
   auto post = [&](int k, hipStream_t st) {
     if (ev) hipEventRecord(ev[2 * k + 1], st);
   };
-  hipStream_t st = s.main;
+  hipStream_t st = ss.main;
   pre(0, st);
-  hipLaunchKernelGGL(k_scan_T, dim3(1), dim3(1024), 0, st, p);
+  hipLaunchKernelGGL(k_scan_T, dim3(s.n_prob), dim3(1024), 0, st, P);
   post(0, st);
   pre(1, st);
-  hipLaunchKernelGGL(k_union, dim3(gr.other), dim3(kUnionThreads), 0, st, p);
+  hipLaunchKernelGGL(k_union, dim3(gr.other, s.n_prob), dim3(kUnionThreads), 0, st, P);
   post(1, st);
   pre(2, st);
-  hipLaunchKernelGGL(k_scan_out, dim3(1), dim3(1024), 0, st, p);
+  hipLaunchKernelGGL(k_scan_out, dim3(s.n_prob), dim3(1024), 0, st, P);
+  hipLaunchKernelGGL(k_sched, dim3(s.n_prob), dim3(256), 0, st, P, s);
   post(2, st);
 }
 
-void launch_sweep_solve(const HalfParams& p, const SweepStreams& s, const SweepGrid& gr,
-                        hipEvent_t* ev) {
+void launch_sweep_solve(const HalfParams* P, const SweepSched& s, const SweepStreams& ss,
+                        const SweepGrid& gr, hipEvent_t* ev) {
   auto pre = [&](int k, hipStream_t st) {
     if (ev) hipEventRecord(ev[2 * k], st);
   };
   auto post = [&](int k, hipStream_t st) {
     if (ev) hipEventRecord(ev[2 * k + 1], st);
   };
-  hipStream_t st = s.main;
+  hipStream_t st = ss.main;
   // fork: the heaviest bins on their own streams, the light ones on main; each
   // stream ends with the Newton launch for the cells its solvers handed over
   // (events kNKernels + i of ev for the three auxiliary ones)
-  hipEventRecord(s.fork, st);
-  for (int i = 0; i < 3; i++) hipStreamWaitEvent(s.aux[i], s.fork, 0);
-  const int gs = gr.bin[5] < p.stream_wgs ? gr.bin[5] : p.stream_wgs;  // one tile buffer per workgroup
-  pre(8, s.aux[0]);
-  if (gs > 0) hipLaunchKernelGGL(k_solve_stream, dim3(gs), dim3(kSlab), 0, s.aux[0], p);
-  post(8, s.aux[0]);
-  pre(9, s.aux[0]);
-  hipLaunchKernelGGL(k_solve_big, dim3(gr.bin[6]), dim3(kBigThreads), 0, s.aux[0], p, 0);
-  post(9, s.aux[0]);
-  pre(kNKernels + 0, s.aux[0]);
-  hipLaunchKernelGGL(k_solve_big, dim3(gr.newton), dim3(kBigThreads), 0, s.aux[0], p, 1 + 3);
-  post(kNKernels + 0, s.aux[0]);
-  pre(7, s.aux[1]);
-  hipLaunchKernelGGL(k_solve_reg<16>, dim3(gr.bin[4]), dim3(1024), 0, s.aux[1], p, 4);
-  post(7, s.aux[1]);
-  pre(kNKernels + 1, s.aux[1]);
-  hipLaunchKernelGGL(k_solve_big, dim3(gr.newton), dim3(kBigThreads), 0, s.aux[1], p, 1 + 2);
-  post(kNKernels + 1, s.aux[1]);
-  pre(6, s.aux[2]);
-  hipLaunchKernelGGL(k_solve_reg<8>, dim3(gr.bin[3]), dim3(512), 0, s.aux[2], p, 3);
-  post(6, s.aux[2]);
-  pre(kNKernels + 2, s.aux[2]);
-  hipLaunchKernelGGL(k_solve_big, dim3(gr.newton), dim3(kBigThreads), 0, s.aux[2], p, 1 + 1);
-  post(kNKernels + 2, s.aux[2]);
+  hipEventRecord(ss.fork, st);
+  for (int i = 0; i < 3; i++) hipStreamWaitEvent(ss.aux[i], ss.fork, 0);
+  const int gs = gr.bin[5] < s.stream_wgs ? gr.bin[5] : s.stream_wgs;  // one tile buffer per workgroup
+  pre(8, ss.aux[0]);
+  if (gs > 0) hipLaunchKernelGGL(k_solve_stream, dim3(gs), dim3(kSlab), 0, ss.aux[0], P, s);
+  post(8, ss.aux[0]);
+  pre(9, ss.aux[0]);
+  hipLaunchKernelGGL(k_solve_big, dim3(gr.bin[6]), dim3(kBigThreads), 0, ss.aux[0], P, s, 0);
+  post(9, ss.aux[0]);
+  pre(kNKernels + 0, ss.aux[0]);
+  hipLaunchKernelGGL(k_solve_big, dim3(gr.newton), dim3(kBigThreads), 0, ss.aux[0], P, s, 1 + 3);
+  post(kNKernels + 0, ss.aux[0]);
+  pre(7, ss.aux[1]);
+  hipLaunchKernelGGL(k_solve_reg<16>, dim3(gr.bin[4]), dim3(1024), 0, ss.aux[1], P, s, 4);
+  post(7, ss.aux[1]);
+  pre(kNKernels + 1, ss.aux[1]);
+  hipLaunchKernelGGL(k_solve_big, dim3(gr.newton), dim3(kBigThreads), 0, ss.aux[1], P, s, 1 + 2);
+  post(kNKernels + 1, ss.aux[1]);
+  pre(6, ss.aux[2]);
+  hipLaunchKernelGGL(k_solve_reg<8>, dim3(gr.bin[3]), dim3(512), 0, ss.aux[2], P, s, 3);
+  post(6, ss.aux[2]);
+  pre(kNKernels + 2, ss.aux[2]);
+  hipLaunchKernelGGL(k_solve_big, dim3(gr.newton), dim3(kBigThreads), 0, ss.aux[2], P, s, 1 + 1);
+  post(kNKernels + 2, ss.aux[2]);
   pre(5, st);
-  hipLaunchKernelGGL(k_solve_reg<4>, dim3(gr.bin[2]), dim3(256), 0, st, p, 2);
+  hipLaunchKernelGGL(k_solve_reg<4>, dim3(gr.bin[2]), dim3(256), 0, st, P, s, 2);
   post(5, st);
   pre(4, st);
-  hipLaunchKernelGGL(k_solve_reg<2>, dim3(gr.bin[1]), dim3(128), 0, st, p, 1);
+  hipLaunchKernelGGL(k_solve_reg<2>, dim3(gr.bin[1]), dim3(128), 0, st, P, s, 1);
   post(4, st);
   pre(3, st);
-  hipLaunchKernelGGL(k_solve_reg<1>, dim3(gr.bin[0]), dim3(64), 0, st, p, 0);
+  hipLaunchKernelGGL(k_solve_reg<1>, dim3(gr.bin[0]), dim3(64), 0, st, P, s, 0);
   post(3, st);
   pre(10, st);
-  hipLaunchKernelGGL(k_solve_big, dim3(gr.newton), dim3(kBigThreads), 0, st, p, 1 + 0);
+  hipLaunchKernelGGL(k_solve_big, dim3(gr.newton), dim3(kBigThreads), 0, st, P, s, 1 + 0);
   post(10, st);
   // join
   for (int i = 0; i < 3; i++) {
-    hipEventRecord(s.join[i], s.aux[i]);
-    hipStreamWaitEvent(st, s.join[i], 0);
+    hipEventRecord(ss.join[i], ss.aux[i]);
+    hipStreamWaitEvent(st, ss.join[i], 0);
   }
 }
 
@@ -2481,9 +2503,10 @@ size_t sweep_max_static_lds() {
   return mx;
 }
 
-void launch_stats(const HalfParams& p, IterStatsDev* out, hipStream_t st, hipEvent_t* ev2) {
+void launch_stats(const HalfParams* P, int n_prob, IterStatsDev* out, hipStream_t st,
+                  hipEvent_t* ev2) {
   if (ev2) hipEventRecord(ev2[0], st);
-  hipLaunchKernelGGL(k_stats, dim3(1), dim3(1024), 0, st, p, out);
+  hipLaunchKernelGGL(k_stats, dim3(n_prob), dim3(1024), 0, st, P, out);
   if (ev2) hipEventRecord(ev2[1], st);
 }
 

@@ -44,6 +44,178 @@ hipError_t dmalloc(T** p, size_t n) {
   return hipMalloc((void**)p, sizeof(T) * n);
 }
 
+// Work lists, streams and events through which the sweeps of one or more
+// problems run: a context runs its own sweeps through one, a batch of
+// contexts through another.
+struct Runner {
+  hipStream_t main = nullptr;
+  ddk::SweepStreams ss{};
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  hipEvent_t kev[ddk::kNEvents] = {};
+  bool timing = false;
+  int n_cu = 64;
+  int grid_cap = 2048;
+  int n_cap = 0;                   // problems the parameter and statistics arrays hold
+  HalfParams* dP = nullptr;        // per-problem parameters (device)
+  HalfParams* hP = nullptr;        // their pinned host staging
+  IterStatsDev* dstats = nullptr;  // per-problem statistics of the last sweep (device)
+  IterStatsDev* hstats = nullptr;  // pinned host copy
+  int cap = 0;                     // items each work list holds
+  int* bin_count = nullptr;
+  int* bin_list = nullptr;
+  int* queue = nullptr;
+  int* defer_count = nullptr;
+  int* defer_list = nullptr;
+  int stream_wgs = 0;
+  int stream_prev = -1;            // streamed-solver cells of the last sweep (-1: none yet)
+  float* stream_tile = nullptr;
+  float* stream_S = nullptr;
+  float* stream_nu = nullptr;
+};
+
+static void runner_free(Runner& r) {
+  if (r.main) (void)hipStreamSynchronize(r.main);
+  for (int i = 0; i < 3; i++) {
+    if (r.ss.aux[i]) (void)hipStreamSynchronize(r.ss.aux[i]);
+    if (r.ss.aux[i]) (void)hipStreamDestroy(r.ss.aux[i]);
+    if (r.ss.join[i]) (void)hipEventDestroy(r.ss.join[i]);
+  }
+  if (r.ss.fork) (void)hipEventDestroy(r.ss.fork);
+  if (r.ev0) (void)hipEventDestroy(r.ev0);
+  if (r.ev1) (void)hipEventDestroy(r.ev1);
+  for (auto& e : r.kev)
+    if (e) (void)hipEventDestroy(e);
+  (void)hipFree(r.dP);
+  (void)hipFree(r.dstats);
+  if (r.hP) (void)hipHostFree(r.hP);
+  if (r.hstats) (void)hipHostFree(r.hstats);
+  (void)hipFree(r.bin_count);
+  (void)hipFree(r.bin_list);
+  (void)hipFree(r.queue);
+  (void)hipFree(r.defer_count);
+  (void)hipFree(r.defer_list);
+  (void)hipFree(r.stream_tile);
+  (void)hipFree(r.stream_S);
+  (void)hipFree(r.stream_nu);
+  r = Runner();
+}
+
+// Streams (default priority; ordered with `main` through events only),
+// events and the fixed-size counters.
+static hipError_t runner_init(Runner& r, hipStream_t main, bool timing) {
+  r.main = main;
+  r.ss.main = main;
+  r.timing = timing;
+  hipError_t e;
+  if ((e = hipEventCreateWithFlags(&r.ss.fork, hipEventDisableTiming)) != hipSuccess) return e;
+  for (int i = 0; i < 3; i++) {
+    if ((e = hipStreamCreateWithFlags(&r.ss.aux[i], hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&r.ss.join[i], hipEventDisableTiming)) != hipSuccess) return e;
+  }
+  if ((e = hipEventCreate(&r.ev0)) != hipSuccess || (e = hipEventCreate(&r.ev1)) != hipSuccess)
+    return e;
+  if (timing)
+    for (auto& ev : r.kev)
+      if ((e = hipEventCreate(&ev)) != hipSuccess) return e;
+  int dev = 0, n_cu = 0;
+  if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
+  if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
+    return e;
+  if (n_cu > 0) {
+    r.n_cu = n_cu;
+    r.grid_cap = 8 * n_cu;
+  }
+  if ((e = dmalloc(&r.bin_count, ddk::kNBins)) != hipSuccess) return e;
+  if ((e = dmalloc(&r.queue, ddk::kNBins + ddk::kNDeferGroups)) != hipSuccess) return e;
+  return dmalloc(&r.defer_count, ddk::kNDeferGroups);
+}
+
+// Room for n_prob problems and `items` cells per sweep.
+static hipError_t runner_reserve(Runner& r, int n_prob, int items) {
+  hipError_t e;
+  if (n_prob > r.n_cap) {
+    hipFree(r.dP);
+    hipFree(r.dstats);
+    if (r.hP) hipHostFree(r.hP);
+    if (r.hstats) hipHostFree(r.hstats);
+    r.dP = nullptr;
+    r.dstats = nullptr;
+    r.hP = nullptr;
+    r.hstats = nullptr;
+    r.n_cap = 0;
+    if ((e = dmalloc(&r.dP, n_prob)) != hipSuccess) return e;
+    if ((e = dmalloc(&r.dstats, n_prob)) != hipSuccess) return e;
+    if ((e = hipHostMalloc((void**)&r.hP, sizeof(HalfParams) * n_prob)) != hipSuccess) return e;
+    if ((e = hipHostMalloc((void**)&r.hstats, sizeof(IterStatsDev) * n_prob)) != hipSuccess)
+      return e;
+    r.n_cap = n_prob;
+  }
+  if (items > r.cap) {
+    hipFree(r.bin_list);
+    hipFree(r.defer_list);
+    r.bin_list = nullptr;
+    r.defer_list = nullptr;
+    r.cap = 0;
+    if ((e = dmalloc(&r.bin_list, (size_t)items * ddk::kNBins)) != hipSuccess) return e;
+    if ((e = dmalloc(&r.defer_list, (size_t)items * ddk::kNDeferGroups)) != hipSuccess) return e;
+    r.cap = items;
+  }
+  return hipSuccess;
+}
+
+// Tile buffers of the streamed solver: one per workgroup (2 MiB each).  The
+// workgroups loop over the bin's queue, so fewer of them than cells is still
+// correct; size for the bin's cells in the previous sweep plus a margin (64
+// before any sweep), at most two per compute unit.
+static hipError_t runner_stream(Runner& r, int n_cells) {
+  const int prev = r.stream_prev >= 0 ? r.stream_prev + 16 : 64;
+  const int want = std::min(std::min(n_cells, 2 * r.n_cu), prev);
+  if (want <= r.stream_wgs) return hipSuccess;
+  hipFree(r.stream_tile);
+  hipFree(r.stream_S);
+  hipFree(r.stream_nu);
+  r.stream_tile = nullptr;
+  r.stream_S = nullptr;
+  r.stream_nu = nullptr;
+  r.stream_wgs = 0;
+  hipError_t e;
+  if ((e = dmalloc(&r.stream_tile, (size_t)want * ddk::kStreamTileFloats)) != hipSuccess) return e;
+  if ((e = dmalloc(&r.stream_S, (size_t)want * ddk::kStreamMaxU)) != hipSuccess) return e;
+  if ((e = dmalloc(&r.stream_nu, (size_t)want * ddk::kStreamMaxU)) != hipSuccess) return e;
+  r.stream_wgs = want;
+  return hipSuccess;
+}
+
+static ddk::SweepSched runner_sched(const Runner& r, int n_prob) {
+  ddk::SweepSched sc{};
+  sc.n_prob = n_prob;
+  sc.cap = r.cap;
+  sc.bin_count = r.bin_count;
+  sc.bin_list = r.bin_list;
+  sc.queue = r.queue;
+  sc.defer_count = r.defer_count;
+  sc.defer_list = r.defer_list;
+  sc.stream_tile = r.stream_tile;
+  sc.stream_S = r.stream_S;
+  sc.stream_nu = r.stream_nu;
+  sc.stream_wgs = r.stream_wgs;
+  return sc;
+}
+
+// Workgroups per solver launch: every workgroup loops over its bin's queue,
+// so a launch needs no more workgroups than the GPU holds at once (8 per
+// compute unit) or than its bin has cells.  (Sharing the wave slots out in
+// proportion to each bin's work in the previous sweep was measured slower.)
+// The union kernel runs a row of workgroups per problem.
+static ddk::SweepGrid plan_grid(const Runner& r, int total_cells, int max_cells, int n_prob) {
+  ddk::SweepGrid gr{};
+  const int g = std::max(1, std::min(total_cells, r.grid_cap));
+  for (int b = 0; b < ddk::kNBins; b++) gr.bin[b] = g;
+  gr.newton = std::max(1, std::min(total_cells, 2 * r.n_cu));
+  gr.other = std::max(1, std::min(max_cells, std::max(64, r.grid_cap / std::max(n_prob, 1))));
+  return gr;
+}
+
 }  // namespace
 
 struct dd_ctx {
@@ -76,25 +248,19 @@ struct dd_ctx {
   double *r_cost = nullptr, *r_obj = nullptr, *r_err = nullptr;
   int *r_loops = nullptr, *r_status = nullptr;
   long long* r_evals = nullptr;
-  int* defer_list = nullptr;
   double* defer_F = nullptr;
   long long* misc = nullptr;
   int* uni_key = nullptr;
   double* uni_nu = nullptr;
   double* uni_G = nullptr;
   int64_t capU = 0;
-  IterStatsDev* dstats = nullptr;
-  IterStatsDev* hstats = nullptr;
   double* dscal = nullptr;
   double* hscal = nullptr;
   double* px_scratch = nullptr;
   int64_t px_cap = 0;
   dd_iter_stats last{};
-  hipEvent_t ev0 = nullptr, ev1 = nullptr;
-  hipEvent_t kev[ddk::kNEvents] = {};
   static_assert(DD_N_KERNELS == ddk::kNKernels, "kernel count of the ABI and the launcher");
-  ddk::SweepStreams ss{};
-  int* queue = nullptr;
+  Runner run;  // this context's own sweeps
   // warm start by the network
   dd_mlp* warm_net = nullptr;
   int warm_policy = 0;
@@ -109,12 +275,8 @@ struct dd_ctx {
   int* dcount = nullptr;
   hipEvent_t warm_ev[2] = {};
   int n_warm_sweeps = 0;
-  int n_cu = 0;
-  int stream_wgs = 0;
-  float* stream_tile = nullptr;
-  float* stream_S = nullptr;
-  float* stream_nu = nullptr;
-  int grid_cap = 2048;
+  bool in_batch = false;  // sweeps run through a batch (dd_batch_create .. dd_batch_free)
+  bool prev_valid = false;  // alpha_prev holds the starting potentials of the last sweep
 };
 
 static dd_status fail(dd_ctx* c, dd_status s, const char* fmt, ...) {
@@ -193,7 +355,6 @@ static dd_status upload_cells(dd_ctx* c) {
     hipFree(c->r_loops);
     hipFree(c->r_status);
     hipFree(c->r_evals);
-    hipFree(c->defer_list);
     hipFree(c->defer_F);
     HIPCHK(c, dmalloc(&c->cell_toff, need));
     HIPCHK(c, dmalloc(&c->cell_U, need));
@@ -205,7 +366,6 @@ static dd_status upload_cells(dd_ctx* c) {
     HIPCHK(c, dmalloc(&c->r_loops, need));
     HIPCHK(c, dmalloc(&c->r_status, need));
     HIPCHK(c, dmalloc(&c->r_evals, need));
-    HIPCHK(c, dmalloc(&c->defer_list, (size_t)need * ddk::kNDeferGroups));
     HIPCHK(c, dmalloc(&c->defer_F, (size_t)need * 64));
     c->cell_cap = need;
   }
@@ -305,36 +465,21 @@ extern "C" void dd_free(dd_ctx* c) {
   hipFree(c->r_loops);
   hipFree(c->r_status);
   hipFree(c->r_evals);
-  hipFree(c->defer_list);
   hipFree(c->defer_F);
   hipFree(c->misc);
-  hipFree(c->queue);
   hipFree(c->warm_X);
   hipFree(c->warm_Y);
   hipFree(c->warm_count);
   hipFree(c->alpha_prev);
   hipFree(c->dcount);
-  hipFree(c->stream_tile);
-  hipFree(c->stream_S);
-  hipFree(c->stream_nu);
   hipFree(c->uni_key);
   hipFree(c->uni_nu);
   hipFree(c->uni_G);
-  hipFree(c->dstats);
   hipFree(c->dscal);
   hipFree(c->px_scratch);
-  if (c->hstats) hipHostFree(c->hstats);
   if (c->hscal) hipHostFree(c->hscal);
-  if (c->ev0) hipEventDestroy(c->ev0);
-  if (c->ev1) hipEventDestroy(c->ev1);
-  for (int i = 0; i < 3; i++) {
-    if (c->ss.aux[i]) hipStreamDestroy(c->ss.aux[i]);
-    if (c->ss.join[i]) hipEventDestroy(c->ss.join[i]);
-  }
-  if (c->ss.fork) hipEventDestroy(c->ss.fork);
+  runner_free(c->run);
   for (auto& e : c->warm_ev)
-    if (e) hipEventDestroy(e);
-  for (auto& e : c->kev)
     if (e) hipEventDestroy(e);
   delete c;
 }
@@ -450,24 +595,13 @@ extern "C" dd_status dd_init(const double* mu, const double* nu, int H, int W, i
     }
   }
   if (dmalloc(&c->dscal, 8) != hipSuccess || hipHostMalloc((void**)&c->hscal, sizeof(double) * 8) != hipSuccess ||
-      dmalloc(&c->dstats, 1) != hipSuccess ||
-      hipHostMalloc((void**)&c->hstats, sizeof(IterStatsDev)) != hipSuccess ||
-      dmalloc(&c->misc, 8) != hipSuccess || dmalloc(&c->bin_count, ddk::kNBins) != hipSuccess ||
-      dmalloc(&c->queue, 16) != hipSuccess)
+      dmalloc(&c->misc, 8) != hipSuccess || dmalloc(&c->bin_count, ddk::kNBins) != hipSuccess)
     return bail(fail(c, DD_ENOMEM, "hipMalloc failed"));
-  hipEventCreate(&c->ev0);
-  hipEventCreate(&c->ev1);
-  // auxiliary streams of a sweep (default priority; ordered with the
-  // context's stream through events only)
-  c->ss.main = c->st;
-  if (hipEventCreateWithFlags(&c->ss.fork, hipEventDisableTiming) != hipSuccess)
-    return bail(fail(c, DD_EHIP, "event creation failed"));
-  for (int i = 0; i < 3; i++)
-    if (hipStreamCreateWithFlags(&c->ss.aux[i], hipStreamNonBlocking) != hipSuccess ||
-        hipEventCreateWithFlags(&c->ss.join[i], hipEventDisableTiming) != hipSuccess)
-      return bail(fail(c, DD_EHIP, "stream creation failed"));
-  if (c->opt.timing)
-    for (auto& e : c->kev) hipEventCreate(&e);
+  {
+    const hipError_t e = runner_init(c->run, c->st, c->opt.timing != 0);
+    if (e != hipSuccess)
+      return bail(fail(c, DD_EHIP, "stream/event setup failed: %s", hipGetErrorString(e)));
+  }
   // validation of the finest images
   {
     const Level& l = c->L[nlev - 1];
@@ -482,13 +616,10 @@ extern "C" dd_status dd_init(const double* mu, const double* nu, int H, int W, i
       return bail(fail(c, DD_EINVAL, "masses must sum to 1 (got %.17g, %.17g)", sm, sn));
     if (!(mn > 0)) return bail(fail(c, DD_EINVAL, "a basic cell of mu has zero mass"));
   }
-  int dev = 0, n_cu = 0, lds_max = 0;
+  int dev = 0, lds_max = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
-      hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
       hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
     return bail(fail(c, DD_EHIP, "no HIP device"));
-  if (n_cu > 0) c->grid_cap = n_cu * 8;
-  c->n_cu = n_cu > 0 ? n_cu : 64;
   {
     const size_t need = ddk::sweep_max_static_lds();
     if (need == 0 || need > (size_t)lds_max)
@@ -553,50 +684,9 @@ static HalfParams make_params(dd_ctx* c, int part) {
   p.r_status = c->r_status;
   p.r_evals = c->r_evals;
   p.misc = c->misc;
-  p.queue = c->queue;
-  p.stream_tile = c->stream_tile;
-  p.stream_S = c->stream_S;
-  p.stream_nu = c->stream_nu;
-  p.stream_wgs = c->stream_wgs;
-  p.defer_list = c->defer_list;
   p.defer_F = c->defer_F;
   p.capE = c->capE;
   return p;
-}
-
-// Tile buffers of the streamed solver: one per workgroup (2 MiB each).  The
-// workgroups loop over the bin's queue, so fewer of them than cells is still
-// correct; size for the bin's cells in the previous sweep plus a margin (64
-// before any sweep), at most two per compute unit.
-static dd_status ensure_stream(dd_ctx* c, int n_cells) {
-  const int prev = c->last.n_cells > 0 ? c->last.cells_bin[ddk::kNBins - 2] + 16 : 64;
-  const int want = std::min(std::min(n_cells, 2 * c->n_cu), prev);
-  if (want <= c->stream_wgs) return DD_OK;
-  hipFree(c->stream_tile);
-  hipFree(c->stream_S);
-  hipFree(c->stream_nu);
-  c->stream_tile = nullptr;
-  c->stream_S = nullptr;
-  c->stream_nu = nullptr;
-  c->stream_wgs = 0;
-  HIPCHK(c, dmalloc(&c->stream_tile, (size_t)want * ddk::kStreamTileFloats));
-  HIPCHK(c, dmalloc(&c->stream_S, (size_t)want * ddk::kStreamMaxU));
-  HIPCHK(c, dmalloc(&c->stream_nu, (size_t)want * ddk::kStreamMaxU));
-  c->stream_wgs = want;
-  return DD_OK;
-}
-
-// Workgroups per solver launch: every workgroup loops over its bin's queue,
-// so a launch needs no more workgroups than the GPU holds at once (8 per
-// compute unit) or than its bin has cells.  (Sharing the wave slots out in
-// proportion to each bin's work in the previous sweep was measured slower.)
-static ddk::SweepGrid plan_grid(const dd_ctx* c, int n_cells) {
-  ddk::SweepGrid gr{};
-  const int g = std::max(1, std::min(n_cells, c->grid_cap));
-  for (int b = 0; b < ddk::kNBins; b++) gr.bin[b] = g;
-  gr.newton = std::max(1, std::min(n_cells, 2 * c->n_cu));
-  gr.other = g;
-  return gr;
 }
 
 // Warm start of the eligible cells of this sweep: features (BF16 rows), the
@@ -668,6 +758,8 @@ extern "C" dd_status dd_collect_cells(dd_ctx* c, float* x_dev, float* t_dev, flo
                                       int* cell_dev, int cap, int* n_out) {
   if (!c || !n_out || cap < 0 || (cap > 0 && (!x_dev || !t_dev || !mask_dev))) return DD_EINVAL;
   if (c->last_part < 0) return fail(c, DD_ESTATE, "no half-iteration on this level yet");
+  if (!c->prev_valid)
+    return fail(c, DD_ESTATE, "the last sweep ran in a batch; its starting potentials are not kept");
   if (!c->dcount) HIPCHK(c, dmalloc(&c->dcount, 1));
   HIPCHK(c, hipMemsetAsync(c->dcount, 0, sizeof(int), c->st));
   HalfParams p = make_params(c, c->last_part);
@@ -680,58 +772,56 @@ extern "C" dd_status dd_collect_cells(dd_ctx* c, float* x_dev, float* t_dev, flo
   return DD_OK;
 }
 
-extern "C" dd_status dd_half_iterate(dd_ctx* c, int part, dd_iter_stats* out) {
-  if (!c) return DD_EINVAL;
-  if (part != 0 && part != 1) return fail(c, DD_EINVAL, "partition must be 0 or 1");
+// Host side of a sweep of one problem, before its kernels: buffer capacities
+// (the output of a sweep needs at most 4 entries per entry it reads), the
+// starting potentials kept for dd_collect_cells (keep_prev), and the kernel
+// parameters.
+static dd_status sweep_begin(dd_ctx* c, int part, bool keep_prev, HalfParams* p) {
   dd_status s = ensure_entries(c, 4 * c->nnz + 64);
   if (s) return s;
   s = ensure_union(c, c->nnz + 64);
   if (s) return s;
-  s = ensure_stream(c, c->cells[part].n);
-  if (s) return s;
-  HalfParams p = make_params(c, part);
-  HIPCHK(c, hipMemsetAsync(c->misc, 0, sizeof(long long) * 8, c->st));
-  HIPCHK(c, hipMemsetAsync(c->queue, 0, sizeof(int) * 16, c->st));
-  HIPCHK(c, hipEventRecord(c->ev0, c->st));
-  hipEvent_t* kev = c->opt.timing ? c->kev : nullptr;
-  const ddk::SweepGrid gr = plan_grid(c, p.n_cells);
-  {
-    // keep the starting potentials of this sweep (training samples, dd_collect_cells)
-    const Level& l = c->L[c->lev];
-    const int64_t npx = (int64_t)l.H * l.W;
-    if (npx > c->alpha_prev_cap) {
-      hipFree(c->alpha_prev);
-      c->alpha_prev = nullptr;
-      c->alpha_prev_cap = 0;
-      HIPCHK(c, dmalloc(&c->alpha_prev, npx));
-      c->alpha_prev_cap = npx;
-    }
-    HIPCHK(c, hipMemcpyAsync(c->alpha_prev, c->alpha[part], sizeof(double) * npx,
-                             hipMemcpyDeviceToDevice, c->st));
+  *p = make_params(c, part);
+  if (p->n_cells > ddk::kItemCellMask + 1)
+    return fail(c, DD_ECAPACITY, "%d cells exceed the %d one sweep can address", p->n_cells,
+                ddk::kItemCellMask + 1);
+  c->prev_valid = keep_prev;
+  if (!keep_prev) return DD_OK;
+  const Level& l = c->L[c->lev];
+  const int64_t npx = (int64_t)l.H * l.W;
+  if (npx > c->alpha_prev_cap) {
+    hipFree(c->alpha_prev);
+    c->alpha_prev = nullptr;
+    c->alpha_prev_cap = 0;
+    HIPCHK(c, dmalloc(&c->alpha_prev, npx));
+    c->alpha_prev_cap = npx;
   }
-  ddk::launch_sweep_prep(p, c->ss, gr, kev);
-  const bool warm = c->warm_net && c->warm_policy > 0 &&
-                    (c->warm_policy == 2 || c->warm_fresh[part]);
-  if (warm) {
-    dd_status ws = warm_start(c, p);
-    if (ws) return ws;
-    c->n_warm_sweeps++;
+  HIPCHK(c, hipMemcpyAsync(c->alpha_prev, c->alpha[part], sizeof(double) * npx,
+                           hipMemcpyDeviceToDevice, c->st));
+  return DD_OK;
+}
+
+// Per-kernel times of the last sweep of a runner (timing mode).
+static void runner_kernel_ms(const Runner& r, double* ms_kernel) {
+  for (int k = 0; k < DD_N_KERNELS; k++) {
+    float t = 0;
+    hipEventElapsedTime(&t, r.kev[2 * k], r.kev[2 * k + 1]);
+    ms_kernel[k] = t;
+    if (k == 10)  // the Newton launches on the auxiliary streams
+      for (int i = 0; i < ddk::kNDeferGroups - 1; i++) {
+        float t2 = 0;
+        hipEventElapsedTime(&t2, r.kev[2 * (ddk::kNKernels + i)],
+                            r.kev[2 * (ddk::kNKernels + i) + 1]);
+        ms_kernel[k] += t2;
+      }
   }
-  c->warm_fresh[part] = 0;
-  ddk::launch_sweep_solve(p, c->ss, gr, kev);
-  HIPCHK(c, hipGetLastError());
-  ddk::launch_stats(p, c->dstats, c->st, kev ? kev + 2 * (DD_N_KERNELS - 1) : nullptr);
-  HIPCHK(c, hipGetLastError());
-  HIPCHK(c, hipEventRecord(c->ev1, c->st));
-  HIPCHK(c, hipMemcpyAsync(c->hstats, c->dstats, sizeof(IterStatsDev), hipMemcpyDeviceToHost, c->st));
-  long long hmisc[3] = {0, 0, 0};
-  HIPCHK(c, hipMemcpyAsync(hmisc, c->misc, sizeof(long long) * 3, hipMemcpyDeviceToHost, c->st));
-  HIPCHK(c, hipStreamSynchronize(c->st));
-  if (hmisc[2]) return fail(c, DD_ESTATE, "corrupt basic-cell rows detected");
-  if (hmisc[1] > c->capE) return fail(c, DD_ECAPACITY, "output entries exceed capacity");
-  float ms = 0;
-  hipEventElapsedTime(&ms, c->ev0, c->ev1);
-  const IterStatsDev& d = *c->hstats;
+}
+
+// Host side of a sweep of one problem, after its statistics came back.
+static dd_status sweep_finish(dd_ctx* c, int part, const IterStatsDev& d, float ms,
+                              const double* ms_kernel, dd_iter_stats* out) {
+  if (d.bad_rows) return fail(c, DD_ESTATE, "corrupt basic-cell rows detected");
+  if (d.out_entries > c->capE) return fail(c, DD_ECAPACITY, "output entries exceed capacity");
   dd_iter_stats r{};
   r.n_cells = d.n_cells;
   r.loops_max = d.loops_max;
@@ -749,23 +839,53 @@ extern "C" dd_status dd_half_iterate(dd_ctx* c, int part, dd_iter_stats* out) {
     r.cells_bin[k] = d.cells_bin[k];
     r.evals_bin[k] = d.evals_bin[k];
   }
-  if (kev)
-    for (int k = 0; k < DD_N_KERNELS; k++) {
-      float t = 0;
-      hipEventElapsedTime(&t, kev[2 * k], kev[2 * k + 1]);
-      r.ms_kernel[k] = t;
-      if (k == 10)  // the Newton launches on the auxiliary streams
-        for (int i = 0; i < ddk::kNDeferGroups - 1; i++) {
-          float t2 = 0;
-          hipEventElapsedTime(&t2, kev[2 * (ddk::kNKernels + i)], kev[2 * (ddk::kNKernels + i) + 1]);
-          r.ms_kernel[k] += t2;
-        }
-    }
+  if (ms_kernel)
+    for (int k = 0; k < DD_N_KERNELS; k++) r.ms_kernel[k] = ms_kernel[k];
   c->nnz = d.nnz;
   c->last = r;
   c->last_part = part;
   if (out) *out = r;
   return d.n_failed > 0 ? DD_ENOTCONV : DD_OK;
+}
+
+extern "C" dd_status dd_half_iterate(dd_ctx* c, int part, dd_iter_stats* out) {
+  if (!c) return DD_EINVAL;
+  if (part != 0 && part != 1) return fail(c, DD_EINVAL, "partition must be 0 or 1");
+  if (c->in_batch) return fail(c, DD_ESTATE, "the context belongs to a batch");
+  HalfParams p;
+  dd_status s = sweep_begin(c, part, true, &p);
+  if (s) return s;
+  Runner& r = c->run;
+  HIPCHK(c, runner_reserve(r, 1, p.n_cells));
+  HIPCHK(c, runner_stream(r, p.n_cells));
+  r.hP[0] = p;
+  HIPCHK(c, hipMemcpyAsync(r.dP, r.hP, sizeof(HalfParams), hipMemcpyHostToDevice, c->st));
+  const ddk::SweepSched sc = runner_sched(r, 1);
+  const ddk::SweepGrid gr = plan_grid(r, p.n_cells, p.n_cells, 1);
+  hipEvent_t* kev = r.timing ? r.kev : nullptr;
+  HIPCHK(c, hipEventRecord(r.ev0, c->st));
+  ddk::launch_sweep_prep(r.dP, sc, r.ss, gr, kev);
+  const bool warm = c->warm_net && c->warm_policy > 0 &&
+                    (c->warm_policy == 2 || c->warm_fresh[part]);
+  if (warm) {
+    dd_status ws = warm_start(c, p);
+    if (ws) return ws;
+    c->n_warm_sweeps++;
+  }
+  c->warm_fresh[part] = 0;
+  ddk::launch_sweep_solve(r.dP, sc, r.ss, gr, kev);
+  HIPCHK(c, hipGetLastError());
+  ddk::launch_stats(r.dP, 1, r.dstats, c->st, kev ? kev + 2 * (DD_N_KERNELS - 1) : nullptr);
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipEventRecord(r.ev1, c->st));
+  HIPCHK(c, hipMemcpyAsync(r.hstats, r.dstats, sizeof(IterStatsDev), hipMemcpyDeviceToHost, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  float ms = 0;
+  hipEventElapsedTime(&ms, r.ev0, r.ev1);
+  double mk[DD_N_KERNELS];
+  if (kev) runner_kernel_ms(r, mk);
+  r.stream_prev = r.hstats[0].cells_bin[ddk::kNBins - 2];
+  return sweep_finish(c, part, r.hstats[0], ms, kev ? mk : nullptr, out);
 }
 
 // Least-squares gluing potential on the cells of partition A (Sec. 6.3):
@@ -934,6 +1054,7 @@ extern "C" dd_status dd_refine(dd_ctx* c) {
 
 extern "C" dd_status dd_run_schedule(dd_ctx* c, dd_run_stats* out) {
   if (!c) return DD_EINVAL;
+  if (c->in_batch) return fail(c, DD_ESTATE, "the context belongs to a batch");
   dd_run_stats rs{};
   const auto t0 = std::chrono::steady_clock::now();
   dd_status worst = DD_OK;
@@ -1104,4 +1225,347 @@ extern "C" dd_status dd_cell_results(dd_ctx* c, double* cost, double* obj, doubl
   if (status) HIPCHK(c, hipMemcpyAsync(status, c->r_status, sizeof(int) * n, hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
   return DD_OK;
+}
+
+// ------------------------------------------------------------ batches
+
+namespace {
+
+// What a captured sweep depends on besides the parameter array's contents.
+struct GraphKey {
+  int n_prob = 0, total = 0, max_cells = 0, cap = 0, stream_wgs = 0;
+  const void* ptr[7] = {};
+  bool operator==(const GraphKey& o) const {
+    if (n_prob != o.n_prob || total != o.total || max_cells != o.max_cells || cap != o.cap ||
+        stream_wgs != o.stream_wgs)
+      return false;
+    for (int i = 0; i < 7; i++)
+      if (ptr[i] != o.ptr[i]) return false;
+    return true;
+  }
+};
+
+struct GraphEntry {
+  GraphKey key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  long long last_use = 0;
+};
+
+constexpr size_t kGraphCache = 8;  // captured sweep shapes kept (A and B of a few levels)
+
+// Position of a problem in its schedule.
+struct SchedCursor {
+  size_t stage = 0;
+  int k = 0;            // sweeps done in the stage
+  bool begun = false;   // the stage's refinements and eps change are applied
+};
+
+}  // namespace
+
+struct dd_batch {
+  std::string err;
+  std::vector<dd_ctx*> cs;
+  int flags = 0;
+  // The batched launches run on a stream of the batch (a capturable one,
+  // whatever the contexts' stream is), ordered with the contexts' stream
+  // through events at the start and the end of every sweep.
+  hipStream_t user_st = nullptr;
+  hipStream_t own_st = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  Runner run;
+  long long n_sweeps = 0;
+  int n_captures = 0;
+  std::vector<GraphEntry> graphs;
+  std::vector<SchedCursor> cur;  // schedule positions (dd_batch_schedule_step)
+  bool cur_set = false;
+};
+
+static dd_status bfail(dd_batch* b, dd_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  b->err = buf;
+  return s;
+}
+
+#define BHIPCHK(b, x)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (x);                                                                \
+    if (e_ != hipSuccess)                                                               \
+      return bfail((b), e_ == hipErrorOutOfMemory ? DD_ENOMEM : DD_EHIP, "%s: %s (%s:%d)", \
+                   #x, hipGetErrorString(e_), __FILE__, __LINE__);                      \
+  } while (0)
+
+static void drop_graph(GraphEntry& g) {
+  if (g.exec) (void)hipGraphExecDestroy(g.exec);
+  if (g.graph) (void)hipGraphDestroy(g.graph);
+  g.exec = nullptr;
+  g.graph = nullptr;
+}
+
+// One sweep over the problems with parts[i] >= 0 (partition of problem i).
+static dd_status batch_sweep(dd_batch* b, const int* parts, dd_iter_stats* out) {
+  Runner& r = b->run;
+  const int n = (int)b->cs.size();
+  std::vector<int> act;
+  std::vector<HalfParams> hp;
+  int total = 0, mx = 0;
+  for (int i = 0; i < n; i++) {
+    if (parts[i] < 0) continue;
+    dd_ctx* c = b->cs[i];
+    HalfParams p;
+    const dd_status s = sweep_begin(c, parts[i], false, &p);
+    if (s) return bfail(b, s, "problem %d: %s", i, c->err.c_str());
+    act.push_back(i);
+    hp.push_back(p);
+    total += p.n_cells;
+    mx = std::max(mx, p.n_cells);
+  }
+  const int na = (int)act.size();
+  if (na == 0) return DD_OK;
+  BHIPCHK(b, hipEventRecord(b->ev_in, b->user_st));
+  BHIPCHK(b, hipStreamWaitEvent(r.main, b->ev_in, 0));
+  BHIPCHK(b, runner_reserve(r, na, total));
+  BHIPCHK(b, runner_stream(r, total));
+  memcpy(r.hP, hp.data(), sizeof(HalfParams) * na);
+  BHIPCHK(b, hipMemcpyAsync(r.dP, r.hP, sizeof(HalfParams) * na, hipMemcpyHostToDevice, r.main));
+  const ddk::SweepSched sc = runner_sched(r, na);
+  const ddk::SweepGrid gr = plan_grid(r, total, mx, na);
+  const bool graph = (b->flags & DD_BATCH_GRAPH) != 0;
+  hipEvent_t* kev = (!graph && r.timing) ? r.kev : nullptr;
+  if (graph) {
+    GraphKey key;
+    key.n_prob = na;
+    key.total = total;
+    key.max_cells = mx;
+    key.cap = r.cap;
+    key.stream_wgs = r.stream_wgs;
+    const void* ptrs[7] = {r.dP, r.dstats, r.bin_list, r.defer_list, r.stream_tile, r.stream_S,
+                           r.stream_nu};
+    for (int i = 0; i < 7; i++) key.ptr[i] = ptrs[i];
+    GraphEntry* ge = nullptr;
+    for (auto& g : b->graphs)
+      if (g.exec && g.key == key) ge = &g;
+    if (!ge) {
+      // capture this shape, in place of the least recently used one when full
+      if (b->graphs.size() < kGraphCache) {
+        b->graphs.emplace_back();
+        ge = &b->graphs.back();
+      } else {
+        ge = &b->graphs[0];
+        for (auto& g : b->graphs)
+          if (g.last_use < ge->last_use) ge = &g;
+        drop_graph(*ge);
+      }
+      BHIPCHK(b, hipStreamBeginCapture(r.main, hipStreamCaptureModeThreadLocal));
+      ddk::launch_sweep_prep(r.dP, sc, r.ss, gr, nullptr);
+      ddk::launch_sweep_solve(r.dP, sc, r.ss, gr, nullptr);
+      ddk::launch_stats(r.dP, na, r.dstats, r.main, nullptr);
+      const hipError_t le = hipGetLastError();
+      hipGraph_t g = nullptr;
+      const hipError_t ce = hipStreamEndCapture(r.main, &g);
+      BHIPCHK(b, le);
+      BHIPCHK(b, ce);
+      ge->graph = g;
+      BHIPCHK(b, hipGraphInstantiate(&ge->exec, g, nullptr, nullptr, 0));
+      ge->key = key;
+      b->n_captures++;
+    }
+    ge->last_use = b->n_sweeps;
+    BHIPCHK(b, hipEventRecord(r.ev0, r.main));
+    BHIPCHK(b, hipGraphLaunch(ge->exec, r.main));
+  } else {
+    BHIPCHK(b, hipEventRecord(r.ev0, r.main));
+    ddk::launch_sweep_prep(r.dP, sc, r.ss, gr, kev);
+    ddk::launch_sweep_solve(r.dP, sc, r.ss, gr, kev);
+    BHIPCHK(b, hipGetLastError());
+    ddk::launch_stats(r.dP, na, r.dstats, r.main, kev ? kev + 2 * (DD_N_KERNELS - 1) : nullptr);
+  }
+  BHIPCHK(b, hipGetLastError());
+  BHIPCHK(b, hipEventRecord(r.ev1, r.main));
+  BHIPCHK(b, hipMemcpyAsync(r.hstats, r.dstats, sizeof(IterStatsDev) * na, hipMemcpyDeviceToHost,
+                            r.main));
+  BHIPCHK(b, hipEventRecord(b->ev_out, r.main));
+  BHIPCHK(b, hipStreamWaitEvent(b->user_st, b->ev_out, 0));
+  BHIPCHK(b, hipStreamSynchronize(r.main));
+  float ms = 0;
+  (void)hipEventElapsedTime(&ms, r.ev0, r.ev1);
+  double mk[DD_N_KERNELS];
+  if (kev) runner_kernel_ms(r, mk);
+  int sp = 0;
+  dd_status worst = DD_OK;
+  for (int k = 0; k < na; k++) {
+    const int i = act[k];
+    sp += r.hstats[k].cells_bin[ddk::kNBins - 2];
+    const dd_status s = sweep_finish(b->cs[i], parts[i], r.hstats[k], ms, kev ? mk : nullptr,
+                                     out ? &out[i] : nullptr);
+    if (s < 0) return bfail(b, s, "problem %d: %s", i, b->cs[i]->err.c_str());
+    if (s > 0) worst = s;
+  }
+  r.stream_prev = sp;
+  b->n_sweeps++;
+  return worst;
+}
+
+extern "C" dd_status dd_batch_create(dd_ctx* const* ctxs, int n, int flags, dd_batch** out) {
+  if (!out) return DD_EINVAL;
+  *out = nullptr;
+  if (!ctxs || n < 1 || n > ddk::kMaxProblems || (flags & ~DD_BATCH_GRAPH)) return DD_EINVAL;
+  for (int i = 0; i < n; i++) {
+    if (!ctxs[i] || ctxs[i]->in_batch || ctxs[i]->st != ctxs[0]->st) return DD_EINVAL;
+    for (int j = 0; j < i; j++)
+      if (ctxs[j] == ctxs[i]) return DD_EINVAL;
+  }
+  dd_batch* b = new dd_batch();
+  b->cs.assign(ctxs, ctxs + n);
+  b->flags = flags;
+  b->user_st = ctxs[0]->st;
+  bool timing = true;
+  for (int i = 0; i < n; i++) timing = timing && ctxs[i]->opt.timing;
+  hipError_t e = hipStreamCreateWithFlags(&b->own_st, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+  if (e == hipSuccess) e = runner_init(b->run, b->own_st, timing);
+  if (e != hipSuccess) {
+    dd_batch_free(b);
+    return DD_EHIP;
+  }
+  for (int i = 0; i < n; i++) ctxs[i]->in_batch = true;
+  *out = b;
+  return DD_OK;
+}
+
+extern "C" dd_status dd_batch_half_iterate(dd_batch* b, int part, dd_iter_stats* stats) {
+  if (!b) return DD_EINVAL;
+  if (part != 0 && part != 1) return bfail(b, DD_EINVAL, "partition must be 0 or 1");
+  std::vector<int> parts(b->cs.size(), part);
+  return batch_sweep(b, parts.data(), stats);
+}
+
+// Move a problem to its next pending sweep (applying stage transitions on
+// the way); false when its schedule is over.
+static dd_status sched_advance(dd_ctx* c, SchedCursor& cur, bool* pending) {
+  *pending = false;
+  while (cur.stage < c->sched.size()) {
+    const dd_stage& sg = c->sched[cur.stage];
+    if (!cur.begun) {
+      while (c->lev < sg.level) {
+        const dd_status s = dd_refine(c);
+        if (s < 0) return s;
+      }
+      if (sg.level != c->lev)
+        return fail(c, DD_ESTATE, "schedule level %d below current %d", sg.level, c->lev);
+      dd_set_eps(c, sg.eps);
+      cur.begun = true;
+    }
+    if (cur.k < sg.n_half_iters) {
+      *pending = true;
+      return DD_OK;
+    }
+    cur.stage++;
+    cur.k = 0;
+    cur.begun = false;
+  }
+  return DD_OK;
+}
+
+extern "C" dd_status dd_batch_schedule_step(dd_batch* b, dd_iter_stats* stats, int* n_active) {
+  if (!b) return DD_EINVAL;
+  const int n = (int)b->cs.size();
+  if (!b->cur_set) {
+    b->cur.assign(n, SchedCursor());
+    for (int i = 0; i < n; i++) b->cur[i].stage = b->cs[i]->next_stage;
+    b->cur_set = true;
+  }
+  std::vector<int> parts(n);
+  int na = 0;
+  for (int i = 0; i < n; i++) {
+    bool pending = false;
+    const dd_status s = sched_advance(b->cs[i], b->cur[i], &pending);
+    if (s < 0) return bfail(b, s, "problem %d: %s", i, b->cs[i]->err.c_str());
+    parts[i] = pending ? (b->cur[i].k & 1) : -1;
+    na += pending;
+    if (stats) memset(&stats[i], 0, sizeof(dd_iter_stats));
+  }
+  if (n_active) *n_active = na;
+  dd_status s = DD_OK;
+  if (na > 0) {
+    s = batch_sweep(b, parts.data(), stats);
+    if (s < 0) return s;
+    for (int i = 0; i < n; i++)
+      if (parts[i] >= 0) b->cur[i].k++;
+  }
+  for (int i = 0; i < n; i++) b->cs[i]->next_stage = b->cur[i].stage;
+  return s;
+}
+
+extern "C" dd_status dd_batch_run_schedule(dd_batch* b, dd_run_stats* out) {
+  if (!b) return DD_EINVAL;
+  const int n = (int)b->cs.size();
+  std::vector<dd_run_stats> rs(n);
+  for (int i = 0; i < n; i++) memset(&rs[i], 0, sizeof(dd_run_stats));
+  std::vector<dd_iter_stats> it(n);
+  const auto t0 = std::chrono::steady_clock::now();
+  dd_status worst = DD_OK;
+  for (;;) {
+    int na = 0;
+    const dd_status s = dd_batch_schedule_step(b, it.data(), &na);
+    if (s < 0) return s;
+    if (na == 0) break;
+    if (s > 0) worst = s;
+    for (int i = 0; i < n; i++) {
+      const dd_iter_stats& t = it[i];
+      if (t.n_cells == 0) continue;  // not in this sweep
+      dd_run_stats& r = rs[i];
+      r.n_half_iters++;
+      r.n_cell_solves += t.n_cells;
+      r.loops_total += t.loops_total;
+      r.entry_evals += t.entry_evals;
+      r.n_failed += t.n_failed;
+      r.n_safeguard += t.n_safeguard;
+      r.n_newton += t.n_newton;
+      r.nnz_max = std::max(r.nnz_max, t.nnz);
+      for (int k = 0; k < DD_N_KERNELS; k++) r.ms_kernel[k] += t.ms_kernel[k];
+      for (int k = 0; k < DD_N_BINS; k++) {
+        r.launches_bin[k] += 1;
+        r.evals_bin[k] += t.evals_bin[k];
+      }
+    }
+  }
+  const double ms =
+      std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  if (out)
+    for (int i = 0; i < n; i++) {
+      out[i] = rs[i];
+      out[i].ms_total = ms;
+    }
+  return worst;
+}
+
+extern "C" dd_status dd_batch_info(const dd_batch* b, int* n_problems, long long* n_sweeps,
+                                   int* n_captures) {
+  if (!b) return DD_EINVAL;
+  if (n_problems) *n_problems = (int)b->cs.size();
+  if (n_sweeps) *n_sweeps = b->n_sweeps;
+  if (n_captures) *n_captures = b->n_captures;
+  return DD_OK;
+}
+
+extern "C" void dd_batch_free(dd_batch* b) {
+  if (!b) return;
+  if (b->own_st) (void)hipStreamSynchronize(b->own_st);
+  for (auto& g : b->graphs) drop_graph(g);
+  runner_free(b->run);
+  if (b->own_st) (void)hipStreamDestroy(b->own_st);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  for (dd_ctx* c : b->cs) c->in_batch = false;
+  delete b;
+}
+
+extern "C" const char* dd_batch_last_error(const dd_batch* b) {
+  return b ? b->err.c_str() : "batch is NULL";
 }

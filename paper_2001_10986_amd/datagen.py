@@ -86,6 +86,24 @@ def config3_pair(seed0=3000):
     return mu, nu, dict(s=4, n_levels=5, stages=eps_schedule(1024, 5))
 
 
+def config4_pairs(n_pairs=64, sizes=(64, 128, 256, 512)):
+    """Uneven batch: n_pairs independent pairs, side drawn uniformly from `sizes`,
+    4-16 blobs per image (floor 1e-3*max); sides and blob counts come from
+    default_rng(4000), image k (2 per pair) from seed 4001 + k.  Each pair runs
+    its own multi-scale schedule from a 64x64 coarsest level to (1/N)^2.
+    Returns a list of (mu, nu, cfg)."""
+    rng = np.random.default_rng(4000)
+    out = []
+    for k in range(n_pairs):
+        N = int(rng.choice(sizes))
+        nb = int(rng.integers(4, 17))
+        nlev = int(np.log2(N // 64)) + 1 if N >= 64 else 1
+        mu = blob_image(N, N, nb, 4001 + 2 * k)
+        nu = blob_image(N, N, nb, 4002 + 2 * k)
+        out.append((mu, nu, dict(s=4, n_levels=nlev, stages=eps_schedule(N, nlev))))
+    return out
+
+
 def small_pair(N, n_blobs=4, seed=7, n_levels=1):
     mu = blob_image(N, N, n_blobs, seed)
     nu = blob_image(N, N, n_blobs, seed + 1)

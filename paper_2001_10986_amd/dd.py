@@ -22,7 +22,12 @@ EXPORTED = ["dd_options_default", "dd_init", "dd_half_iterate", "dd_set_eps", "d
             "dd_mlp_create", "dd_mlp_free", "dd_mlp_last_error", "dd_mlp_shape",
             "dd_mlp_set_params", "dd_mlp_get_params", "dd_mlp_forward", "dd_mlp_forward_bf16",
             "dd_mlp_loss_grad", "dd_mlp_train_step", "dd_mlp_get_stream", "dd_set_warm_start",
-            "dd_collect_cells", "dd_warm_start_count"]
+            "dd_collect_cells", "dd_warm_start_count", "dd_batch_create",
+            "dd_batch_half_iterate", "dd_batch_run_schedule", "dd_batch_schedule_step",
+            "dd_batch_info", "dd_batch_free",
+            "dd_batch_last_error"]
+
+DD_BATCH_GRAPH = 1
 
 
 class Stage(C.Structure):
@@ -120,7 +125,18 @@ def _load():
     lib.dd_collect_cells.argtypes = [C.c_void_p] + [C.c_void_p] * 4 + [C.c_int, P(C.c_int)]
     lib.dd_mlp_get_stream.argtypes = [C.c_void_p]
     lib.dd_mlp_get_stream.restype = C.c_void_p
-    for name in ("dd_set_warm_start", "dd_collect_cells"):
+    lib.dd_batch_create.argtypes = [P(C.c_void_p), C.c_int, C.c_int, P(C.c_void_p)]
+    lib.dd_batch_half_iterate.argtypes = [C.c_void_p, C.c_int, P(IterStats)]
+    lib.dd_batch_run_schedule.argtypes = [C.c_void_p, P(RunStats)]
+    lib.dd_batch_schedule_step.argtypes = [C.c_void_p, P(IterStats), P(C.c_int)]
+    lib.dd_batch_info.argtypes = [C.c_void_p, P(C.c_int), P(C.c_longlong), P(C.c_int)]
+    lib.dd_batch_free.argtypes = [C.c_void_p]
+    lib.dd_batch_free.restype = None
+    lib.dd_batch_last_error.argtypes = [C.c_void_p]
+    lib.dd_batch_last_error.restype = C.c_char_p
+    for name in ("dd_set_warm_start", "dd_collect_cells", "dd_batch_create",
+                 "dd_batch_half_iterate", "dd_batch_run_schedule", "dd_batch_schedule_step",
+                 "dd_batch_info"):
         getattr(lib, name).restype = C.c_int
     for name in ("dd_init", "dd_half_iterate", "dd_set_eps", "dd_refine", "dd_run_schedule",
                  "dd_cost", "dd_export_plan", "dd_import_state", "dd_cell_results",
@@ -309,3 +325,58 @@ class Problem:
         for b in range(info["n_basic"]):
             out[b, e["col"][rp[b]:rp[b + 1]]] = e["val"][rp[b]:rp[b + 1]]
         return out
+
+
+class Batch:
+    """Problems whose sweeps run together (a dd_batch).  The Problems must
+    share a stream and outlive the batch; while it exists their own
+    half_iterate/run_schedule are refused."""
+
+    def __init__(self, problems, graph=False):
+        self.problems = list(problems)
+        n = len(self.problems)
+        arr = (C.c_void_p * n)(*[p._h for p in self.problems])
+        h = C.c_void_p()
+        rc = lib.dd_batch_create(arr, n, DD_BATCH_GRAPH if graph else 0, C.byref(h))
+        if rc != 0:
+            raise DDError(f"dd_batch_create: invalid batch ({rc})")
+        self._h = h
+
+    def _chk(self, rc, what):
+        if rc < 0:
+            raise DDError(f"{what}: {lib.dd_batch_last_error(self._h).decode()} ({rc})")
+        return rc
+
+    def close(self):
+        if getattr(self, "_h", None) and lib is not None:
+            lib.dd_batch_free(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def half_iterate(self, partition):
+        n = len(self.problems)
+        st = (IterStats * n)()
+        rc = self._chk(lib.dd_batch_half_iterate(self._h, partition, st), "dd_batch_half_iterate")
+        return [dict(x.as_dict(), status=rc) for x in st]
+
+    def run_schedule(self):
+        n = len(self.problems)
+        st = (RunStats * n)()
+        rc = self._chk(lib.dd_batch_run_schedule(self._h, st), "dd_batch_run_schedule")
+        return [dict(x.as_dict(), status=rc) for x in st]
+
+    def schedule_step(self):
+        """One lockstep sweep of the problems' schedules: (problems that ran, stats)."""
+        n = len(self.problems)
+        st = (IterStats * n)()
+        na = C.c_int()
+        rc = self._chk(lib.dd_batch_schedule_step(self._h, st, C.byref(na)),
+                       "dd_batch_schedule_step")
+        return na.value, [dict(x.as_dict(), status=rc) for x in st]
+
+    def info(self):
+        a, b, c = C.c_int(), C.c_longlong(), C.c_int()
+        self._chk(lib.dd_batch_info(self._h, C.byref(a), C.byref(b), C.byref(c)), "dd_batch_info")
+        return {"n_problems": a.value, "n_sweeps": b.value, "n_captures": c.value}
