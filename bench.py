@@ -54,6 +54,13 @@ def main():
                     help="256x256 training pairs for the warm-start network (0 skips the "
                          "learned leg)")
     ap.add_argument("--learned-steps", type=int, default=2000, help="Adam steps of the network")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default launch sizes instead of tuning them on the warm-up run")
+    ap.add_argument("--batch-pairs", type=int, default=0,
+                    help="also time the uneven batch: this many pairs of 64..512 px, all "
+                         "schedules in lockstep through one batch (0 skips it)")
+    ap.add_argument("--batch-seq", action="store_true",
+                    help="with --batch-pairs, also time the same pairs one after another")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (calibrates the HBM "
                          "byte counters of a profiler) and exit")
@@ -94,15 +101,28 @@ def main():
     nu_d = torch.from_numpy(nu).cuda()
     torch.cuda.synchronize()
 
+    launch = None  # (solver, Newton) workgroups per compute unit; None: defaults
+
     def step():
         g = dd.Problem(mu_d, nu_d, cfg["stages"], s=cfg["s"], n_levels=cfg["n_levels"],
                        timing=True)
+        if launch is not None:
+            g.set_launch(*launch)
         rs = g.run_schedule()
         c = g.cost()
         return g, rs, c
 
-    for _ in range(args.warmup):
+    tune = None
+    for w in range(args.warmup):
         g, rs, c = step()
+        if w == 0 and not args.no_autotune:
+            # the autotuner times one more finest-level sweep under every
+            # candidate launch size (same state each time; results do not
+            # depend on it) and the timed runs use the fastest
+            best, tried = g.autotune(0, reps=2)
+            launch = (best["solver_per_cu"], best["newton_per_cu"])
+            tune = {"chosen": best, "tried": tried,
+                    "on": "one more finest-level sweep of partition A after the warm-up run"}
         g.close()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -208,6 +228,8 @@ def main():
 
         def lstep():
             gl = dd.Problem(mu_d, nu_d, cfg["stages"], s=cfg["s"], n_levels=cfg["n_levels"])
+            if launch is not None:
+                gl.set_launch(*launch)
             gl.set_warm_start(net, warmstart.POLICY, warmstart.MIN_RMS)
             rsl = gl.run_schedule()
             return gl, rsl, gl.cost()
@@ -243,6 +265,60 @@ def main():
                       "data_s": t_gen, "train_s": t_train},
         }
 
+    # uneven batch: many small pairs, each with its own multi-scale schedule,
+    # run in lockstep through one batch (shared launches, graph replays)
+    batch = None
+    if args.batch_pairs > 0:
+        pairs = datagen.config4_pairs(args.batch_pairs)
+        devp = [(torch.from_numpy(m).cuda(), torch.from_numpy(v).cuda(), cf) for m, v, cf in pairs]
+        torch.cuda.synchronize()
+
+        def mk():
+            ps = [dd.Problem(m, v, cf["stages"], s=cf["s"], n_levels=cf["n_levels"])
+                  for m, v, cf in devp]
+            if launch is not None:
+                for q in ps:
+                    q.set_launch(*launch)
+            return ps
+
+        ps = mk()
+        bt = dd.Batch(ps, graph=True)
+        if launch is not None:
+            bt.set_launch(*launch)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rsb = bt.run_schedule()
+        torch.cuda.synchronize()
+        t_b = time.perf_counter() - t0
+        info = bt.info()
+        bt.close()
+        costs = [q.cost() for q in ps]
+        nsol = sum(r["n_cell_solves"] for r in rsb)
+        sizes = {}
+        for m, _, _ in pairs:
+            sizes[str(m.shape[0])] = sizes.get(str(m.shape[0]), 0) + 1
+        batch = {"workload": f"{args.batch_pairs} pairs, sides {sizes}, 4-16 blobs, each its own "
+                             "schedule 64 px -> (1/N)^2, lockstep",
+                 "time_s": t_b, "cell_solves": nsol, "solves_per_s": nsol / t_b,
+                 "sweeps": info["n_sweeps"], "graph_captures": info["n_captures"],
+                 "tol_met": all(q["err_x"] <= 1e-5 and q["err_y"] <= 1e-5 for q in costs),
+                 "max_err_x": max(q["err_x"] for q in costs),
+                 "cells_failed": sum(r["n_failed"] for r in rsb),
+                 "cells_newton": sum(r["n_newton"] for r in rsb)}
+        for q in ps:
+            q.close()
+        if args.batch_seq:
+            ps = mk()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for q in ps:
+                q.run_schedule()
+            torch.cuda.synchronize()
+            batch["sequential_time_s"] = time.perf_counter() - t0
+            batch["speedup_vs_sequential"] = batch["sequential_time_s"] / t_b
+            for q in ps:
+                q.close()
+
     out = {
         "metric": "time-to-tol (L1 marg<=1e-5) 1024^2 W2, learned vs plain; cell-Sinkhorn solves/s",
         "value": value,
@@ -271,6 +347,8 @@ def main():
         "sinkhorn_loops": rs["loops_total"],
         "kernel_ms_per_step": kernel_ms,
         "learned_warm_start": learned,
+        "autotune": tune,
+        "batch": batch,
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity_sample": parity,

@@ -269,6 +269,33 @@ dd_status dd_batch_schedule_step(dd_batch* batch, dd_iter_stats* stats, int* n_a
 dd_status dd_batch_info(const dd_batch* batch, int* n_problems, long long* n_sweeps,
                         int* n_captures);
 
+/* ---- Launch configuration and autotuning ------------------------------
+ * Every solver launch of a sweep loops over a work queue, so its number of
+ * workgroups changes the speed, never the result.  A configuration is the
+ * number of workgroups per compute unit of each solver launch (1..64,
+ * default 8) and of each Newton launch (1..16, default 2). */
+typedef struct {
+  int solver_per_cu;
+  int newton_per_cu;
+  double ms; /* GPU time of the sweep (best of the repetitions) */
+} dd_tune_point;
+
+dd_status dd_set_launch(dd_ctx* ctx, int solver_per_cu, int newton_per_cu);
+dd_status dd_batch_set_launch(dd_batch* batch, int solver_per_cu, int newton_per_cu);
+
+/* Autotuner: runs the next sweep of `partition` under each candidate
+ * configuration (solver 2/4/8/16 x Newton 1/2/4 per compute unit), reps
+ * times each, from the same state (a device snapshot of the basic-cell rows
+ * and the partition's potentials, restored before every run and at the end,
+ * so the state is unchanged on return), and keeps the fastest for later
+ * sweeps.  best: the chosen point; tried (nullable): up to max_tried
+ * points in the order run, *n_tried (nullable) their number.  The snapshot
+ * needs device memory of the size of the entry buffer. */
+dd_status dd_autotune(dd_ctx* ctx, int partition, int reps, dd_tune_point* best,
+                      dd_tune_point* tried, int max_tried, int* n_tried);
+dd_status dd_batch_autotune(dd_batch* batch, int partition, int reps, dd_tune_point* best,
+                            dd_tune_point* tried, int max_tried, int* n_tried);
+
 /* Release the batch (not its contexts, which return to their own sweeps). */
 void dd_batch_free(dd_batch* batch);
 

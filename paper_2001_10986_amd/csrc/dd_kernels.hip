@@ -1674,8 +1674,10 @@ DEVI double row16_max(double v) {
 
 // Conditional plan of support point yi for the 4 pixels xs + 16k of this
 // thread (16 threads per support point, lanes xs = tid & 15 of a 16-lane
-// group): pk[k] = p_x(y), returns m + log s (= -G(y)).
-DEVI double cond_plan(const BigShared& sh, int r, int c, int xs, double lam, double pk[4]) {
+// group): pk[k] = p_x(y), returns m + log s (= -G(y)).  exact: FP64
+// exponentials (for the Newton system), else FP32 (plain iterations).
+DEVI double cond_plan(const BigShared& sh, int r, int c, int xs, double lam, double pk[4],
+                      bool exact) {
   double e[4];
   double m = -INFINITY;
 #pragma unroll
@@ -1689,9 +1691,11 @@ DEVI double cond_plan(const BigShared& sh, int r, int c, int xs, double lam, dou
   double v[4], s = 0;
 #pragma unroll
   for (int k = 0; k < 4; k++) {
-    // FP64: the plans of far-apart pixels underflow FP32, and the Newton
-    // system needs exactly those weak couplings
-    v[k] = e[k] == -INFINITY ? 0.0 : exp(e[k] - m);
+    // the plans of far-apart pixels underflow FP32, and the Newton system
+    // needs exactly those weak couplings
+    v[k] = e[k] == -INFINITY ? 0.0
+           : exact          ? exp(e[k] - m)
+                            : (double)fast_exp2((float)((e[k] - m) * kLog2e));
     s += v[k];
   }
   s = row16_sum(s);
@@ -1878,7 +1882,7 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(const HalfParams* __r
             if (yi < U) {  // uniform within each 16-lane group
               int r, c;
               split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
-              const double lse = cond_plan(sh, r, c, xs, lam, pk);
+              const double lse = cond_plan(sh, r, c, xs, lam, pk, build_w);
               const double nu = p.uni_nu[ub + yi];
 #pragma unroll
               for (int k = 0; k < 4; k++) racc[k] += nu * pk[k];
@@ -1991,7 +1995,7 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(const HalfParams* __r
                     int r, c;
                     split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
                     double pk[4];
-                    cond_plan(sh, r, c, xs, lam, pk);
+                    cond_plan(sh, r, c, xs, lam, pk, true);
                     double a[4], cy = 0;
 #pragma unroll
                     for (int k = 0; k < 4; k++) {

@@ -54,7 +54,8 @@ struct Runner {
   hipEvent_t kev[ddk::kNEvents] = {};
   bool timing = false;
   int n_cu = 64;
-  int grid_cap = 2048;
+  int solver_per_cu = 8;           // workgroups per solver launch, per compute unit
+  int newton_per_cu = 2;           // workgroups per Newton launch, per compute unit
   int n_cap = 0;                   // problems the parameter and statistics arrays hold
   HalfParams* dP = nullptr;        // per-problem parameters (device)
   HalfParams* hP = nullptr;        // their pinned host staging
@@ -121,10 +122,7 @@ static hipError_t runner_init(Runner& r, hipStream_t main, bool timing) {
   if ((e = hipGetDevice(&dev)) != hipSuccess) return e;
   if ((e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, dev)) != hipSuccess)
     return e;
-  if (n_cu > 0) {
-    r.n_cu = n_cu;
-    r.grid_cap = 8 * n_cu;
-  }
+  if (n_cu > 0) r.n_cu = n_cu;
   if ((e = dmalloc(&r.bin_count, ddk::kNBins)) != hipSuccess) return e;
   if ((e = dmalloc(&r.queue, ddk::kNBins + ddk::kNDeferGroups)) != hipSuccess) return e;
   return dmalloc(&r.defer_count, ddk::kNDeferGroups);
@@ -203,16 +201,17 @@ static ddk::SweepSched runner_sched(const Runner& r, int n_prob) {
 }
 
 // Workgroups per solver launch: every workgroup loops over its bin's queue,
-// so a launch needs no more workgroups than the GPU holds at once (8 per
-// compute unit) or than its bin has cells.  (Sharing the wave slots out in
-// proportion to each bin's work in the previous sweep was measured slower.)
+// so a launch needs no more workgroups than the GPU holds at once or than its
+// bin has cells; the counts per compute unit are set by dd_set_launch or
+// picked by dd_autotune (default 8 per solver launch, 2 per Newton launch).
 // The union kernel runs a row of workgroups per problem.
 static ddk::SweepGrid plan_grid(const Runner& r, int total_cells, int max_cells, int n_prob) {
   ddk::SweepGrid gr{};
-  const int g = std::max(1, std::min(total_cells, r.grid_cap));
+  const int cap = r.solver_per_cu * r.n_cu;
+  const int g = std::max(1, std::min(total_cells, cap));
   for (int b = 0; b < ddk::kNBins; b++) gr.bin[b] = g;
-  gr.newton = std::max(1, std::min(total_cells, 2 * r.n_cu));
-  gr.other = std::max(1, std::min(max_cells, std::max(64, r.grid_cap / std::max(n_prob, 1))));
+  gr.newton = std::max(1, std::min(total_cells, r.newton_per_cu * r.n_cu));
+  gr.other = std::max(1, std::min(max_cells, std::max(64, 8 * r.n_cu / std::max(n_prob, 1))));
   return gr;
 }
 
@@ -1233,11 +1232,11 @@ namespace {
 
 // What a captured sweep depends on besides the parameter array's contents.
 struct GraphKey {
-  int n_prob = 0, total = 0, max_cells = 0, cap = 0, stream_wgs = 0;
+  int n_prob = 0, total = 0, max_cells = 0, cap = 0, stream_wgs = 0, solver_pc = 0, newton_pc = 0;
   const void* ptr[7] = {};
   bool operator==(const GraphKey& o) const {
     if (n_prob != o.n_prob || total != o.total || max_cells != o.max_cells || cap != o.cap ||
-        stream_wgs != o.stream_wgs)
+        stream_wgs != o.stream_wgs || solver_pc != o.solver_pc || newton_pc != o.newton_pc)
       return false;
     for (int i = 0; i < 7; i++)
       if (ptr[i] != o.ptr[i]) return false;
@@ -1343,6 +1342,8 @@ static dd_status batch_sweep(dd_batch* b, const int* parts, dd_iter_stats* out) 
     key.max_cells = mx;
     key.cap = r.cap;
     key.stream_wgs = r.stream_wgs;
+    key.solver_pc = r.solver_per_cu;
+    key.newton_pc = r.newton_per_cu;
     const void* ptrs[7] = {r.dP, r.dstats, r.bin_list, r.defer_list, r.stream_tile, r.stream_S,
                            r.stream_nu};
     for (int i = 0; i < 7; i++) key.ptr[i] = ptrs[i];
@@ -1568,4 +1569,198 @@ extern "C" void dd_batch_free(dd_batch* b) {
 
 extern "C" const char* dd_batch_last_error(const dd_batch* b) {
   return b ? b->err.c_str() : "batch is NULL";
+}
+
+// ------------------------------------------------------------ launch tuning
+
+namespace {
+
+// Device copy of the state a sweep of one partition changes (the basic-cell
+// rows and that partition's potentials), so that the sweep can be run again
+// from the same state.
+struct Snapshot {
+  int64_t* row_off = nullptr;
+  int* row_len = nullptr;
+  int* col = nullptr;
+  double* val = nullptr;
+  double* alpha = nullptr;
+  int64_t capE = 0, npx = 0, nnz = 0;
+  int nb = 0, part = 0, last_part = -1;
+  dd_iter_stats last{};
+  bool prev_valid = false;
+  int warm_fresh[2] = {1, 1};
+  int n_warm_sweeps = 0;
+};
+
+const int kTuneSolver[] = {2, 4, 8, 16};
+const int kTuneNewton[] = {1, 2, 4};
+
+}  // namespace
+
+static void snap_free(Snapshot& s) {
+  (void)hipFree(s.row_off);
+  (void)hipFree(s.row_len);
+  (void)hipFree(s.col);
+  (void)hipFree(s.val);
+  (void)hipFree(s.alpha);
+  s = Snapshot();
+}
+
+static dd_status snap_take(dd_ctx* c, int part, Snapshot& s) {
+  const Level& l = c->L[c->lev];
+  s.nb = c->nb;
+  s.capE = c->capE;
+  s.npx = (int64_t)l.H * l.W;
+  s.nnz = c->nnz;
+  s.part = part;
+  s.last_part = c->last_part;
+  s.last = c->last;
+  s.prev_valid = c->prev_valid;
+  s.warm_fresh[0] = c->warm_fresh[0];
+  s.warm_fresh[1] = c->warm_fresh[1];
+  s.n_warm_sweeps = c->n_warm_sweeps;
+  HIPCHK(c, dmalloc(&s.row_off, s.nb));
+  HIPCHK(c, dmalloc(&s.row_len, s.nb));
+  HIPCHK(c, dmalloc(&s.col, s.capE));
+  HIPCHK(c, dmalloc(&s.val, s.capE));
+  HIPCHK(c, dmalloc(&s.alpha, s.npx));
+  const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+  HIPCHK(c, hipMemcpyAsync(s.row_off, c->row_off, sizeof(int64_t) * s.nb, k, c->st));
+  HIPCHK(c, hipMemcpyAsync(s.row_len, c->row_len, sizeof(int) * s.nb, k, c->st));
+  HIPCHK(c, hipMemcpyAsync(s.col, c->col, sizeof(int) * s.capE, k, c->st));
+  HIPCHK(c, hipMemcpyAsync(s.val, c->val, sizeof(double) * s.capE, k, c->st));
+  HIPCHK(c, hipMemcpyAsync(s.alpha, c->alpha[part], sizeof(double) * s.npx, k, c->st));
+  return DD_OK;
+}
+
+// The entry buffer may have grown since the snapshot (never shrunk), so the
+// rows, which point below s.capE, stay valid.
+static dd_status snap_restore(dd_ctx* c, const Snapshot& s) {
+  if (c->capE < s.capE || c->nb != s.nb) return fail(c, DD_ESTATE, "state changed shape");
+  const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+  HIPCHK(c, hipMemcpyAsync(c->row_off, s.row_off, sizeof(int64_t) * s.nb, k, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->row_len, s.row_len, sizeof(int) * s.nb, k, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->col, s.col, sizeof(int) * s.capE, k, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->val, s.val, sizeof(double) * s.capE, k, c->st));
+  HIPCHK(c, hipMemcpyAsync(c->alpha[s.part], s.alpha, sizeof(double) * s.npx, k, c->st));
+  HIPCHK(c, hipStreamSynchronize(c->st));
+  c->nnz = s.nnz;
+  c->last_part = s.last_part;
+  c->last = s.last;
+  c->prev_valid = s.prev_valid;
+  c->warm_fresh[0] = s.warm_fresh[0];
+  c->warm_fresh[1] = s.warm_fresh[1];
+  c->n_warm_sweeps = s.n_warm_sweeps;
+  return DD_OK;
+}
+
+static bool valid_launch(int solver_per_cu, int newton_per_cu) {
+  return solver_per_cu >= 1 && solver_per_cu <= 64 && newton_per_cu >= 1 && newton_per_cu <= 16;
+}
+
+extern "C" dd_status dd_set_launch(dd_ctx* c, int solver_per_cu, int newton_per_cu) {
+  if (!c) return DD_EINVAL;
+  if (!valid_launch(solver_per_cu, newton_per_cu)) return fail(c, DD_EINVAL, "launch sizes out of range");
+  c->run.solver_per_cu = solver_per_cu;
+  c->run.newton_per_cu = newton_per_cu;
+  return DD_OK;
+}
+
+extern "C" dd_status dd_batch_set_launch(dd_batch* b, int solver_per_cu, int newton_per_cu) {
+  if (!b) return DD_EINVAL;
+  if (!valid_launch(solver_per_cu, newton_per_cu)) return bfail(b, DD_EINVAL, "launch sizes out of range");
+  b->run.solver_per_cu = solver_per_cu;
+  b->run.newton_per_cu = newton_per_cu;
+  return DD_OK;
+}
+
+// Time every candidate launch configuration on the same sweep (state restored
+// before each run and at the end), keep the fastest.  sweep(): runs the sweep
+// and returns its status and GPU time.
+template <typename Sweep, typename Restore>
+static dd_status tune_loop(Runner& r, int reps, Sweep sweep, Restore restore, dd_tune_point* best,
+                           dd_tune_point* tried, int max_tried, int* n_tried) {
+  dd_tune_point b{};
+  b.ms = INFINITY;
+  int nt = 0;
+  for (int sp : kTuneSolver)
+    for (int np : kTuneNewton) {
+      r.solver_per_cu = sp;
+      r.newton_per_cu = np;
+      double mn = INFINITY;
+      for (int k = 0; k < reps; k++) {
+        double ms = 0;
+        dd_status s = restore();
+        if (s < 0) return s;
+        s = sweep(&ms);
+        if (s < 0) return s;
+        mn = std::min(mn, ms);
+      }
+      dd_tune_point t{sp, np, mn};
+      if (tried && nt < max_tried) tried[nt] = t;
+      nt++;
+      if (mn < b.ms) b = t;
+    }
+  const dd_status s = restore();
+  if (s < 0) return s;
+  r.solver_per_cu = b.solver_per_cu;
+  r.newton_per_cu = b.newton_per_cu;
+  if (best) *best = b;
+  if (n_tried) *n_tried = nt;
+  return DD_OK;
+}
+
+extern "C" dd_status dd_autotune(dd_ctx* c, int part, int reps, dd_tune_point* best,
+                                 dd_tune_point* tried, int max_tried, int* n_tried) {
+  if (!c) return DD_EINVAL;
+  if (part != 0 && part != 1) return fail(c, DD_EINVAL, "partition must be 0 or 1");
+  if (reps < 1 || max_tried < 0) return fail(c, DD_EINVAL, "reps must be >= 1");
+  if (c->in_batch) return fail(c, DD_ESTATE, "the context belongs to a batch");
+  Snapshot snap;
+  dd_status s = snap_take(c, part, snap);
+  if (s == DD_OK) {
+    auto sweep = [&](double* ms) {
+      dd_iter_stats it;
+      const dd_status st = dd_half_iterate(c, part, &it);
+      *ms = it.ms;
+      return st;
+    };
+    auto restore = [&]() { return snap_restore(c, snap); };
+    s = tune_loop(c->run, reps, sweep, restore, best, tried, max_tried, n_tried);
+  }
+  snap_free(snap);
+  return s;
+}
+
+extern "C" dd_status dd_batch_autotune(dd_batch* b, int part, int reps, dd_tune_point* best,
+                                       dd_tune_point* tried, int max_tried, int* n_tried) {
+  if (!b) return DD_EINVAL;
+  if (part != 0 && part != 1) return bfail(b, DD_EINVAL, "partition must be 0 or 1");
+  if (reps < 1 || max_tried < 0) return bfail(b, DD_EINVAL, "reps must be >= 1");
+  const int n = (int)b->cs.size();
+  std::vector<Snapshot> snaps(n);
+  dd_status s = DD_OK;
+  for (int i = 0; i < n && s == DD_OK; i++) {
+    s = snap_take(b->cs[i], part, snaps[i]);
+    if (s) s = bfail(b, s, "problem %d: %s", i, b->cs[i]->err.c_str());
+  }
+  if (s == DD_OK) {
+    std::vector<int> parts(n, part);
+    std::vector<dd_iter_stats> it(n);
+    auto sweep = [&](double* ms) {
+      const dd_status st = batch_sweep(b, parts.data(), it.data());
+      *ms = it[0].ms;
+      return st;
+    };
+    auto restore = [&]() {
+      for (int i = 0; i < n; i++) {
+        const dd_status st = snap_restore(b->cs[i], snaps[i]);
+        if (st < 0) return bfail(b, st, "problem %d: %s", i, b->cs[i]->err.c_str());
+      }
+      return DD_OK;
+    };
+    s = tune_loop(b->run, reps, sweep, restore, best, tried, max_tried, n_tried);
+  }
+  for (auto& sn : snaps) snap_free(sn);
+  return s;
 }

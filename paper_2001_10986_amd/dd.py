@@ -24,7 +24,8 @@ EXPORTED = ["dd_options_default", "dd_init", "dd_half_iterate", "dd_set_eps", "d
             "dd_mlp_loss_grad", "dd_mlp_train_step", "dd_mlp_get_stream", "dd_set_warm_start",
             "dd_collect_cells", "dd_warm_start_count", "dd_batch_create",
             "dd_batch_half_iterate", "dd_batch_run_schedule", "dd_batch_schedule_step",
-            "dd_batch_info", "dd_batch_free",
+            "dd_batch_info", "dd_batch_free", "dd_set_launch", "dd_batch_set_launch",
+            "dd_autotune", "dd_batch_autotune",
             "dd_batch_last_error"]
 
 DD_BATCH_GRAPH = 1
@@ -70,6 +71,13 @@ class RunStats(C.Structure):
     def as_dict(self):
         return {k: (list(getattr(self, k)) if k in ("ms_kernel", "launches_bin", "evals_bin")
                     else getattr(self, k)) for k, _ in self._fields_}
+
+
+class TunePoint(C.Structure):
+    _fields_ = [("solver_per_cu", C.c_int), ("newton_per_cu", C.c_int), ("ms", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
 
 
 class CostReport(C.Structure):
@@ -129,6 +137,11 @@ def _load():
     lib.dd_batch_half_iterate.argtypes = [C.c_void_p, C.c_int, P(IterStats)]
     lib.dd_batch_run_schedule.argtypes = [C.c_void_p, P(RunStats)]
     lib.dd_batch_schedule_step.argtypes = [C.c_void_p, P(IterStats), P(C.c_int)]
+    lib.dd_set_launch.argtypes = [C.c_void_p, C.c_int, C.c_int]
+    lib.dd_batch_set_launch.argtypes = [C.c_void_p, C.c_int, C.c_int]
+    for name in ("dd_autotune", "dd_batch_autotune"):
+        getattr(lib, name).argtypes = [C.c_void_p, C.c_int, C.c_int, P(TunePoint), P(TunePoint),
+                                       C.c_int, P(C.c_int)]
     lib.dd_batch_info.argtypes = [C.c_void_p, P(C.c_int), P(C.c_longlong), P(C.c_int)]
     lib.dd_batch_free.argtypes = [C.c_void_p]
     lib.dd_batch_free.restype = None
@@ -136,7 +149,8 @@ def _load():
     lib.dd_batch_last_error.restype = C.c_char_p
     for name in ("dd_set_warm_start", "dd_collect_cells", "dd_batch_create",
                  "dd_batch_half_iterate", "dd_batch_run_schedule", "dd_batch_schedule_step",
-                 "dd_batch_info"):
+                 "dd_batch_info", "dd_set_launch", "dd_batch_set_launch", "dd_autotune",
+                 "dd_batch_autotune"):
         getattr(lib, name).restype = C.c_int
     for name in ("dd_init", "dd_half_iterate", "dd_set_eps", "dd_refine", "dd_run_schedule",
                  "dd_cost", "dd_export_plan", "dd_import_state", "dd_cell_results",
@@ -154,6 +168,14 @@ class DDError(RuntimeError):
 
 def _p(a):
     return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _autotune(fn, h, partition, reps, chk):
+    best = TunePoint()
+    tried = (TunePoint * 32)()
+    n = C.c_int()
+    chk(fn(h, partition, reps, C.byref(best), tried, 32, C.byref(n)), fn.__name__)
+    return best.as_dict(), [tried[i].as_dict() for i in range(min(n.value, 32))]
 
 
 class Problem:
@@ -290,6 +312,14 @@ class Problem:
                                       _p(status)), "dd_cell_results")
         return {"cost": cost, "obj": obj, "err_x": err, "loops": loops, "status": status}
 
+    def set_launch(self, solver_per_cu, newton_per_cu):
+        self._chk(lib.dd_set_launch(self._h, solver_per_cu, newton_per_cu), "dd_set_launch")
+
+    def autotune(self, partition, reps=1):
+        """Time the candidate launch configurations on the next sweep of `partition`
+        (state unchanged on return); keeps the fastest.  Returns (best, tried)."""
+        return _autotune(lib.dd_autotune, self._h, partition, reps, self._chk)
+
     def set_warm_start(self, net, policy=1, min_rms=0.0):
         """Attach a warm-start network (paper_2001_10986_amd.mlp.MLP; None detaches).
         policy 1: first sweep of each partition after init/refine/eps change; 2: every
@@ -366,6 +396,13 @@ class Batch:
         st = (RunStats * n)()
         rc = self._chk(lib.dd_batch_run_schedule(self._h, st), "dd_batch_run_schedule")
         return [dict(x.as_dict(), status=rc) for x in st]
+
+    def set_launch(self, solver_per_cu, newton_per_cu):
+        self._chk(lib.dd_batch_set_launch(self._h, solver_per_cu, newton_per_cu),
+                  "dd_batch_set_launch")
+
+    def autotune(self, partition, reps=1):
+        return _autotune(lib.dd_batch_autotune, self._h, partition, reps, self._chk)
 
     def schedule_step(self):
         """One lockstep sweep of the problems' schedules: (problems that ran, stats)."""

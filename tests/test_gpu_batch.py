@@ -144,3 +144,50 @@ def test_batch_rules(dd):
     b.half_iterate(0)
     b.close()
     g.half_iterate(1)  # back to its own sweeps
+
+
+def test_autotune_leaves_state_and_results_unchanged(dd):
+    # the number of workgroups per launch changes the speed only: after the
+    # tuner (which runs the next sweep 12 times from a snapshot) the state is
+    # the one before, and the following sweeps match an untuned problem bit
+    # for bit
+    mu, nu = datagen.small_pair(64, 4, seed=71)
+    st = [(0, 4.0 / 64 ** 2, 4)]
+    g = dd.Problem(mu, nu, st, s=4, n_levels=1)
+    h = dd.Problem(mu, nu, st, s=4, n_levels=1)
+    g.half_iterate(0)
+    h.half_iterate(0)
+    before = g.export()
+    best, tried = g.autotune(1, reps=1)
+    after = g.export()
+    for k in ("row_ptr", "col", "val", "alpha_a", "alpha_b"):
+        assert np.array_equal(before[k], after[k]), k
+    assert len(tried) == 12
+    assert (best["solver_per_cu"], best["newton_per_cu"]) in \
+        [(t["solver_per_cu"], t["newton_per_cu"]) for t in tried]
+    assert best["ms"] == min(t["ms"] for t in tried)
+    for ell in (1, 0, 1):
+        a, b = g.half_iterate(ell), h.half_iterate(ell)
+        assert a["loops_total"] == b["loops_total"]
+    _states_equal(g, h)
+    with pytest.raises(dd.DDError):
+        g.set_launch(0, 1)
+
+
+def test_batch_autotune_then_sweeps_equal_single(dd):
+    cases = _cases()
+    single = _mixed_problems(dd, cases)
+    batched = _mixed_problems(dd, cases)
+    b = dd.Batch(batched, graph=True)
+    b.half_iterate(0)
+    for g in single:
+        g.half_iterate(0)
+    best, tried = b.autotune(1, reps=1)
+    assert len(tried) == 12
+    for ell in (1, 0):
+        b.half_iterate(ell)
+        for g in single:
+            g.half_iterate(ell)
+    for g, h in zip(single, batched):
+        _states_equal(g, h)
+    b.close()
