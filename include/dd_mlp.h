@@ -54,13 +54,15 @@ void* dd_mlp_get_stream(const dd_mlp* net);
 
 /* ---- use with a domain-decomposition context (include/dd.h) ----
  *
- * Cell features (768 per cell, the network's input): 64 mu_J / |mu_J| on the
- * cell's 8x8 pixel block; 256 nu_J / |nu_J| on a 24x24 pixel window around
- * the block moved by the cell's integer shift d_J = round(mean_nu - mean_mu);
- * log(h^2/eps); the nu_J mass outside the window; d_J / 8; and the potential
+ * Cell features (768 per cell, the network's input): [0,64) 64 mu_J/|mu_J|
+ * on the cell's 8x8 pixel block; [64,640) 256 nu_J/|nu_J| on a 24x24 pixel
+ * window around the block moved by the cell's integer shift
+ * d_J = round(mean_nu - mean_mu); [640] log(h^2/eps); [641] the nu_J mass
+ * outside the window (fraction); [642,644) d_J / 8; [644,708) the potential
  * the solve would start from (the previous sweep's), in units of eps, with
  * the linear part 2 (h^2/eps) (x - x_c).d_J of the shift added, centred over
- * the pixels of positive mass and divided by 16 h^2/eps.  Output (64): the
+ * the pixels of positive mass and divided by 16 h^2/eps; [708,768) zero.
+ * Output (64): the
  * change of that centred potential which the solve makes, in the same units;
  * a zero output gives back the plain warm start.  Only cells whose Y-support
  * has at most 512 points are eligible; the others keep the plain start.
