@@ -42,6 +42,12 @@ def kernel_traffic(name, config):
     return TRAFFIC_BYTES_PER_LAUNCH[name]
 
 
+def progress(msg):
+    """One line on stderr as each leg of the benchmark ends (the JSON result
+    stays the only line on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -141,6 +147,8 @@ def main():
     value = solves / (ms_per_step / 1000)
     tol_met = bool(c["err_x"] <= 1e-5 and c["err_y"] <= 1e-5 and rs["n_failed"] == 0)
 
+    progress(f"timed schedules: {ms_per_step:.1f} ms each")
+
     # roofline of the dominant solver kernel, from the events recorded around it
     tot_ms = [sum(r["ms_kernel"][k] for r, _ in runs) for k in range(dd.N_KERNELS)]
     solver = max(range(3, 3 + dd.N_BINS), key=lambda k: tot_ms[k])
@@ -207,11 +215,14 @@ def main():
     # method (256x256 training pairs, untimed), then time the same schedule
     # with the network's start on the first sweeps after each refinement /
     # eps change (cells whose predicted change is large enough)
+    if cpu is not None:
+        progress(f"oracle leg: {cpu['value']:.0f} solves/s")
     learned = None
     if args.learned_pairs > 0 and args.config == 3:
         from paper_2001_10986_amd import mlp, warmstart
         t = time.perf_counter()
         X, T, M = warmstart.generate(args.learned_pairs, 2_000_000)
+        progress(f"learned leg: {X.shape[0]} training samples")
         n = X.shape[0]
         nv = max(n // 20, 1)
         perm = torch.randperm(n, device=X.device, generator=torch.Generator(device=X.device).manual_seed(0))
@@ -221,6 +232,7 @@ def main():
         val0 = warmstart.mean_loss(net, Xv, Tv, Mv)
         t_gen = time.perf_counter() - t
         warmstart.train(net, Xt, Tt, Mt, args.learned_steps)
+        progress("learned leg: network trained")
         val1 = warmstart.mean_loss(net, Xv, Tv, Mv)
         torch.cuda.synchronize()
         t_train = time.perf_counter() - t - t_gen
@@ -287,13 +299,24 @@ def main():
             bt.set_launch(*launch)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        rsb = bt.run_schedule()
+        nsol = nfail = nnewt = step_no = 0
+        while True:  # dd_batch_run_schedule, one lockstep sweep at a time
+            na, st = bt.schedule_step()
+            if na == 0:
+                break
+            step_no += 1
+            nsol += sum(x["n_cells"] for x in st)
+            nfail += sum(x["n_failed"] for x in st)
+            nnewt += sum(x["n_newton"] for x in st)
+            if step_no % 6 == 0:
+                progress(f"batch: sweep {step_no}, {na} problems active, "
+                         f"{time.perf_counter() - t0:.1f} s")
         torch.cuda.synchronize()
         t_b = time.perf_counter() - t0
         info = bt.info()
         bt.close()
         costs = [q.cost() for q in ps]
-        nsol = sum(r["n_cell_solves"] for r in rsb)
+        progress(f"batch: {t_b:.1f} s")
         sizes = {}
         for m, _, _ in pairs:
             sizes[str(m.shape[0])] = sizes.get(str(m.shape[0]), 0) + 1
@@ -303,16 +326,16 @@ def main():
                  "sweeps": info["n_sweeps"], "graph_captures": info["n_captures"],
                  "tol_met": all(q["err_x"] <= 1e-5 and q["err_y"] <= 1e-5 for q in costs),
                  "max_err_x": max(q["err_x"] for q in costs),
-                 "cells_failed": sum(r["n_failed"] for r in rsb),
-                 "cells_newton": sum(r["n_newton"] for r in rsb)}
+                 "cells_failed": nfail, "cells_newton": nnewt}
         for q in ps:
             q.close()
         if args.batch_seq:
             ps = mk()
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-            for q in ps:
+            for i, q in enumerate(ps):
                 q.run_schedule()
+                progress(f"sequential: pair {i} done, {time.perf_counter() - t0:.1f} s")
             torch.cuda.synchronize()
             batch["sequential_time_s"] = time.perf_counter() - t0
             batch["speedup_vs_sequential"] = batch["sequential_time_s"] / t_b

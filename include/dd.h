@@ -69,6 +69,9 @@ typedef struct {
   int n_half_iters;
 } dd_stage;
 
+#define DD_PREC_SPLIT 0
+#define DD_PREC_FP64 1
+
 typedef struct {
   double err_tol;          /* Sinkhorn stop: L1 X-marginal error <= err_tol*|mu_J| (Sec. 6.2); default 1e-5 */
   double trunc_threshold;  /* truncation threshold of the basic marginals (Sec. 6.1 (ii)); default 1e-15 */
@@ -79,6 +82,10 @@ typedef struct {
   int newton_after;        /* >0: a cell not converged after this many loops continues with
                               damped Newton steps on its X potential (same stopping test, same
                               fixed point); 0: never; default 256 */
+  int precision;           /* DD_PREC_SPLIT (default): FP32 exponentials in the Sinkhorn bulk,
+                              FP64 potentials, sums and bookkeeping; DD_PREC_FP64: every cell on
+                              the log-domain solver with FP64 exponentials (the arithmetic of the
+                              FP64 oracle, for parity runs; slower) */
   int inputs_on_device;    /* 1: mu, nu passed to dd_init are device pointers; default 0 */
   int timing;              /* 1: record HIP events around every kernel of a sweep; default 0 */
   void* stream;            /* hipStream_t for all work of the context; default NULL */

@@ -27,6 +27,7 @@ struct HalfParams {
   double err_tol, trunc;
   int max_iter, safeguard, accel;
   int newton_after;            // >0: hand a cell to Newton steps after this many loops
+  int fp64;                    // 1: every cell on the log-domain solver, FP64 exponentials
   const double* mu;            // level mu, H*W
   const double* nu;            // level nu, H*W
   double* alpha;               // potentials f of partition `part`, H*W (in/out)

@@ -163,6 +163,11 @@ __global__ __launch_bounds__(1024) void k_scan_T(const HalfParams* __restrict__ 
 // solver (bin 5).
 DEVI int defer_group(int bin) { return bin <= 2 ? 0 : bin - 2; }
 
+// Size bin of a cell (the FP64 instantiation puts every cell on the
+// log-domain solver).
+DEVI int bin_of(int U);
+DEVI int cell_bin(const HalfParams& p, int U);
+
 DEVI int bin_of(int U) {
   if (U <= 64) return 0;
   if (U <= 128) return 1;
@@ -172,6 +177,8 @@ DEVI int bin_of(int U) {
   if (U <= kStreamMaxU) return 5;
   return 6;
 }
+
+DEVI int cell_bin(const HalfParams& p, int U) { return p.fp64 ? kNBins - 1 : bin_of(U); }
 
 // cell_ooff = exclusive scan of |J| * U_J; stable lists of cells per size bin
 __global__ __launch_bounds__(1024) void k_scan_out(const HalfParams* __restrict__ P) {
@@ -191,7 +198,7 @@ __global__ __launch_bounds__(1024) void k_scan_out(const HalfParams* __restrict_
       int nq = (q.x >= 0) + (q.y >= 0) + (q.z >= 0) + (q.w >= 0);
       int U = p.cell_U[i];
       t = (long long)nq * U;
-      b = bin_of(U);
+      b = cell_bin(p, U);
     }
     long long tot;
     long long ex = block_excl_scan(t, sh, &tot);
@@ -1672,6 +1679,17 @@ DEVI double row16_max(double v) {
   return v;
 }
 
+// e^x in FP64 or through the FP32 exponential (x <= 0 in every use)
+DEVI double ex(double x, bool fp64) {
+  return fp64 ? exp(x) : (double)fast_exp2((float)(x * kLog2e));
+}
+
+// e^b - 1 - b in FP64 (series for small |b|, no cancellation)
+DEVI double phi1d(double b) {
+  if (fabs(b) < 1e-3) return b * b * (0.5 + b * (1.0 / 6 + b * (1.0 / 24 + b / 120)));
+  return expm1(b) - b;
+}
+
 // Conditional plan of support point yi for the 4 pixels xs + 16k of this
 // thread (16 threads per support point, lanes xs = tid & 15 of a 16-lane
 // group): pk[k] = p_x(y), returns m + log s (= -G(y)).  exact: FP64
@@ -1724,6 +1742,7 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(const HalfParams* __r
     const HalfParams& p = P[item >> kItemShift];
     const int cell = item & kItemCellMask;
     const double invW = 1.0 / p.W;
+    const bool fp64 = p.fp64 != 0;
     const CellGeo g = load_geo(p, cell);
     const int U = p.cell_U[cell];
     const int64_t ub = p.cell_toff[cell];
@@ -1794,7 +1813,7 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(const HalfParams* __r
           for (int k = 0; k < 64; k++) {
             const int dr = r - sh.xr[k], dc = c - sh.xc[k];
             const double e = sh.Fmu[k] - lam * (double)(dr * dr + dc * dc) - m;
-            s += (double)fast_exp2((float)(e * kLog2e));
+            s += ex(e, fp64);
           }
           const double nu = p.uni_nu[ub + yi];
           G[yi] = -(m + log(s)) + (nu > 0 ? log(nu) : -INFINITY);  // G(y) + log nu_J(y)
@@ -1811,10 +1830,10 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(const HalfParams* __r
             const double e = G[yi] - lam * (double)(dr * dr + dc * dc);
             if (e == -INFINITY) continue;
             if (e > m) {
-              s = s * (double)fast_exp2((float)((m - e) * kLog2e)) + 1.0;
+              s = s * ex(m - e, fp64) + 1.0;
               m = e;
             } else {
-              s += (double)fast_exp2((float)((e - m) * kLog2e));
+              s += ex(e - m, fp64);
             }
           }
           sh.u.lse.pm[wave][x] = m;
@@ -1882,7 +1901,7 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(const HalfParams* __r
             if (yi < U) {  // uniform within each 16-lane group
               int r, c;
               split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
-              const double lse = cond_plan(sh, r, c, xs, lam, pk, build_w);
+              const double lse = cond_plan(sh, r, c, xs, lam, pk, build_w || fp64);
               const double nu = p.uni_nu[ub + yi];
 #pragma unroll
               for (int k = 0; k < 4; k++) racc[k] += nu * pk[k];
@@ -2006,7 +2025,9 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(const HalfParams* __r
                     double sp = 0;
 #pragma unroll
                     for (int k = 0; k < 4; k++)
-                      sp += pk[k] > 0 ? pk[k] * (double)phi1f((float)(a[k] - cy)) : 0.0;
+                      sp += pk[k] > 0 ? pk[k] * (fp64 ? phi1d(a[k] - cy)
+                                                      : (double)phi1f((float)(a[k] - cy)))
+                                      : 0.0;
                     sp = row16_sum(sp);
                     if (xs == 0) loc -= p.uni_nu[ub + yi] * log1p(sp);
                   }
@@ -2073,7 +2094,7 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(const HalfParams* __r
           const int dr = r - sh.xr[k], dc = c - sh.xc[k];
           const int d2 = dr * dr + dc * dc;
           const double e = sh.Fmu[k] - lam * (double)d2 - m;
-          const double v = (double)fast_exp2((float)(e * kLog2e));
+          const double v = ex(e, fp64);
           const int qa = ((k >> 5) << 1) | ((k & 7) >> 2);
           sq[0] += qa == 0 ? v : 0.0;
           sq[1] += qa == 1 ? v : 0.0;
@@ -2359,7 +2380,7 @@ __global__ __launch_bounds__(1024) void k_stats(const HalfParams* __restrict__ P
     cb[k] = 0;
   }
   for (int i = threadIdx.x; i < p.n_cells; i += 1024) {
-    const int b = bin_of(p.cell_U[i]);
+    const int b = cell_bin(p, p.cell_U[i]);
 #pragma unroll
     for (int k = 0; k < kNBins; k++) {
       eb[k] += b == k ? p.r_evals[i] : 0;

@@ -436,6 +436,7 @@ extern "C" void dd_options_default(dd_options* o) {
   o->safeguard = 1;
   o->accel = 1;
   o->newton_after = 256;
+  o->precision = DD_PREC_SPLIT;
   o->inputs_on_device = 0;
   o->timing = 0;
   o->stream = nullptr;
@@ -557,7 +558,8 @@ extern "C" dd_status dd_init(const double* mu, const double* nu, int H, int W, i
   else
     dd_options_default(&c->opt);
   if (!(c->opt.err_tol > 0) || !(c->opt.trunc_threshold >= 0) || c->opt.max_sinkhorn_iter < 1 ||
-      c->opt.newton_after < 0) {
+      c->opt.newton_after < 0 ||
+      (c->opt.precision != DD_PREC_SPLIT && c->opt.precision != DD_PREC_FP64)) {
     delete c;
     return fail(nullptr, DD_EINVAL, "invalid options");
   }
@@ -659,6 +661,7 @@ static HalfParams make_params(dd_ctx* c, int part) {
   p.safeguard = c->opt.safeguard;
   p.accel = c->opt.accel;
   p.newton_after = c->opt.newton_after;
+  p.fp64 = c->opt.precision == DD_PREC_FP64;
   p.mu = l.mu;
   p.nu = l.nu;
   p.alpha = c->alpha[part];

@@ -29,6 +29,7 @@ EXPORTED = ["dd_options_default", "dd_init", "dd_half_iterate", "dd_set_eps", "d
             "dd_batch_last_error"]
 
 DD_BATCH_GRAPH = 1
+DD_PREC_SPLIT, DD_PREC_FP64 = 0, 1
 
 
 class Stage(C.Structure):
@@ -38,7 +39,8 @@ class Stage(C.Structure):
 class Options(C.Structure):
     _fields_ = [("err_tol", C.c_double), ("trunc_threshold", C.c_double),
                 ("max_sinkhorn_iter", C.c_int), ("safeguard", C.c_int), ("accel", C.c_int),
-                ("newton_after", C.c_int), ("inputs_on_device", C.c_int), ("timing", C.c_int), ("stream", C.c_void_p)]
+                ("newton_after", C.c_int), ("precision", C.c_int), ("inputs_on_device", C.c_int),
+                ("timing", C.c_int), ("stream", C.c_void_p)]
 
 
 N_KERNELS, N_BINS = 12, 7
@@ -187,7 +189,7 @@ class Problem:
 
     def __init__(self, mu, nu, schedule, s=4, n_levels=1, err_tol=1e-5, trunc=1e-15,
                  max_iter=50000, safeguard=1, stream=None, timing=False, accel=1,
-                 newton_after=256):
+                 newton_after=256, precision=DD_PREC_SPLIT):
         opt = Options()
         lib.dd_options_default(C.byref(opt))
         opt.err_tol, opt.trunc_threshold = err_tol, trunc
@@ -195,6 +197,7 @@ class Problem:
         opt.timing = 1 if timing else 0
         opt.accel = int(accel)
         opt.newton_after = int(newton_after)
+        opt.precision = int(precision)
         on_dev = hasattr(mu, "data_ptr") and getattr(mu, "is_cuda", False)
         if on_dev:
             import torch
