@@ -107,13 +107,13 @@ def main():
     nu_d = torch.from_numpy(nu).cuda()
     torch.cuda.synchronize()
 
-    launch = None  # (solver, Newton) workgroups per compute unit; None: defaults
+    launch = None  # launch sizes chosen by the autotuner; None: defaults
 
     def step():
         g = dd.Problem(mu_d, nu_d, cfg["stages"], s=cfg["s"], n_levels=cfg["n_levels"],
                        timing=True)
         if launch is not None:
-            g.set_launch(*launch)
+            g.set_launch(**launch)
         rs = g.run_schedule()
         c = g.cost()
         return g, rs, c
@@ -126,7 +126,7 @@ def main():
             # candidate launch size (same state each time; results do not
             # depend on it) and the timed runs use the fastest
             best, tried = g.autotune(0, reps=2)
-            launch = (best["solver_per_cu"], best["newton_per_cu"])
+            launch = best
             tune = {"chosen": best, "tried": tried,
                     "on": "one more finest-level sweep of partition A after the warm-up run"}
         g.close()
@@ -241,7 +241,7 @@ def main():
         def lstep():
             gl = dd.Problem(mu_d, nu_d, cfg["stages"], s=cfg["s"], n_levels=cfg["n_levels"])
             if launch is not None:
-                gl.set_launch(*launch)
+                gl.set_launch(**launch)
             gl.set_warm_start(net, warmstart.POLICY, warmstart.MIN_RMS)
             rsl = gl.run_schedule()
             return gl, rsl, gl.cost()
@@ -290,13 +290,13 @@ def main():
                   for m, v, cf in devp]
             if launch is not None:
                 for q in ps:
-                    q.set_launch(*launch)
+                    q.set_launch(**launch)
             return ps
 
         ps = mk()
         bt = dd.Batch(ps, graph=True)
         if launch is not None:
-            bt.set_launch(*launch)
+            bt.set_launch(**launch)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         nsol = nfail = nnewt = step_no = 0

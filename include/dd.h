@@ -114,6 +114,8 @@ typedef struct {
   double err_x;            /* sum over cells of the L1 X-marginal error */
   double ms;               /* device time of the half-iteration (ms) */
   double ms_kernel[DD_N_KERNELS];   /* per-kernel device time (ms) when timing is on, else 0 */
+  double ms_start[DD_N_KERNELS];    /* timing on: start and end of each kernel after the start */
+  double ms_end[DD_N_KERNELS];      /* of the sweep (ms; the Newton launches: first start, last end) */
   int cells_bin[DD_N_BINS];         /* cells per solver bin */
   int64_t evals_bin[DD_N_BINS];     /* entry_evals per solver bin */
 } dd_iter_stats;
@@ -282,17 +284,27 @@ dd_status dd_batch_info(const dd_batch* batch, int* n_problems, long long* n_swe
  * number of workgroups per compute unit of each solver launch (1..64,
  * default 8) and of each Newton launch (1..16, default 2). */
 typedef struct {
-  int solver_per_cu;
-  int newton_per_cu;
-  double ms; /* GPU time of the sweep (best of the repetitions) */
+  int solver_per_cu; /* workgroups per solver launch and compute unit, 1..64 (default 8) */
+  int newton_per_cu; /* workgroups per Newton launch and compute unit, 1..16 (default 2) */
+  int stream_wgs;    /* the streamed solver's workgroups at most, 0..4096 (each re-reads
+                        its cell's tile of up to 2 MiB every loop, so fewer of them keep
+                        more tiles in the last-level cache); 0 = two per compute unit */
+  int cells_per_wg;  /* register solvers: cells a workgroup takes before it exits (then
+                        the launch has enough workgroups for every cell, and launches on
+                        the other streams get compute units as they finish); 0 = loop
+                        until the queue is empty (default) */
+  double ms;         /* autotuner: GPU time of the sweep (best of the repetitions) */
 } dd_tune_point;
 
-dd_status dd_set_launch(dd_ctx* ctx, int solver_per_cu, int newton_per_cu);
-dd_status dd_batch_set_launch(dd_batch* batch, int solver_per_cu, int newton_per_cu);
+dd_status dd_set_launch(dd_ctx* ctx, const dd_tune_point* cfg);
+dd_status dd_batch_set_launch(dd_batch* batch, const dd_tune_point* cfg);
+dd_status dd_get_launch(const dd_ctx* ctx, dd_tune_point* cfg);
 
-/* Autotuner: runs the next sweep of `partition` under each candidate
- * configuration (solver 2/4/8/16 x Newton 1/2/4 per compute unit), reps
- * times each, from the same state (a device snapshot of the basic-cell rows
+/* Autotuner: runs the next sweep of `partition` under candidate
+ * configurations, reps times each, one axis at a time with the others at the
+ * best so far: cells_per_wg 0/1/2/4, stream_wgs 32/64/128/256/0, Newton
+ * 1/2/4 and (persistent workgroups only) solver 2/4/8/16 per compute unit
+ * (at most 16 distinct points), from the same state (a device snapshot of the basic-cell rows
  * and the partition's potentials, restored before every run and at the end,
  * so the state is unchanged on return), and keeps the fastest for later
  * sweeps.  best: the chosen point; tried (nullable): up to max_tried

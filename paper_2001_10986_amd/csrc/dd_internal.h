@@ -77,6 +77,7 @@ struct SweepSched {
   float* stream_S;             // streamed solver: S(y), kStreamMaxU per workgroup
   float* stream_nu;            // streamed solver: nu_J(y) in FP32, kStreamMaxU per workgroup
   int stream_wgs;              // workgroups the streamed-solver buffers are sized for
+  int wg_cells;                // register solvers: cells per workgroup (0: until the queue is empty)
 };
 
 struct IterStatsDev {

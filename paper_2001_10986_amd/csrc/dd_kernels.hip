@@ -747,9 +747,14 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
   const int count = s.bin_count[bin];
   float* rd = sh.red[wave];
   float* uw = sh.uw[wave];
+  int taken = 0;
   for (;;) {
     // next item of this bin (a work queue, so that slow cells do not hold up
-    // the cells behind them)
+    // the cells behind them); with wg_cells > 0 a workgroup takes at most that
+    // many cells and exits, so that launches on other streams get compute
+    // units as this one's workgroups finish
+    if (s.wg_cells > 0 && taken == s.wg_cells) break;
+    taken++;
     if (tid == 0) sh.next = atomicAdd(&s.queue[bin], 1);
     __syncthreads();
     const int ci = sh.next;

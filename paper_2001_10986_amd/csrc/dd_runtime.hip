@@ -56,6 +56,8 @@ struct Runner {
   int n_cu = 64;
   int solver_per_cu = 8;           // workgroups per solver launch, per compute unit
   int newton_per_cu = 2;           // workgroups per Newton launch, per compute unit
+  int stream_max = 0;              // workgroups of the streamed solver at most (0: 2 per CU)
+  int wg_cells = 0;                // register solvers: cells per workgroup (0: persistent)
   int n_cap = 0;                   // problems the parameter and statistics arrays hold
   HalfParams* dP = nullptr;        // per-problem parameters (device)
   HalfParams* hP = nullptr;        // their pinned host staging
@@ -165,9 +167,11 @@ static hipError_t runner_reserve(Runner& r, int n_prob, int items) {
 // workgroups loop over the bin's queue, so fewer of them than cells is still
 // correct; size for the bin's cells in the previous sweep plus a margin (64
 // before any sweep), at most two per compute unit.
+static int stream_limit(const Runner& r) { return r.stream_max > 0 ? r.stream_max : 2 * r.n_cu; }
+
 static hipError_t runner_stream(Runner& r, int n_cells) {
   const int prev = r.stream_prev >= 0 ? r.stream_prev + 16 : 64;
-  const int want = std::min(std::min(n_cells, 2 * r.n_cu), prev);
+  const int want = std::min(std::min(n_cells, stream_limit(r)), prev);
   if (want <= r.stream_wgs) return hipSuccess;
   hipFree(r.stream_tile);
   hipFree(r.stream_S);
@@ -197,6 +201,7 @@ static ddk::SweepSched runner_sched(const Runner& r, int n_prob) {
   sc.stream_S = r.stream_S;
   sc.stream_nu = r.stream_nu;
   sc.stream_wgs = r.stream_wgs;
+  sc.wg_cells = r.wg_cells;
   return sc;
 }
 
@@ -210,6 +215,13 @@ static ddk::SweepGrid plan_grid(const Runner& r, int total_cells, int max_cells,
   const int cap = r.solver_per_cu * r.n_cu;
   const int g = std::max(1, std::min(total_cells, cap));
   for (int b = 0; b < ddk::kNBins; b++) gr.bin[b] = g;
+  // one-shot register-solver workgroups: enough of them for every cell
+  if (r.wg_cells > 0)
+    for (int b = 0; b < ddk::kNRegBins; b++)
+      gr.bin[b] = std::max(1, (total_cells + r.wg_cells - 1) / r.wg_cells);
+  // the streamed solver's tiles (up to 2 MiB each) are re-read every loop:
+  // fewer workgroups keep more of them in the last-level cache
+  gr.bin[ddk::kNBins - 2] = std::min(g, stream_limit(r));
   gr.newton = std::max(1, std::min(total_cells, r.newton_per_cu * r.n_cu));
   gr.other = std::max(1, std::min(max_cells, std::max(64, 8 * r.n_cu / std::max(n_prob, 1))));
   return gr;
@@ -803,19 +815,30 @@ static dd_status sweep_begin(dd_ctx* c, int part, bool keep_prev, HalfParams* p)
   return DD_OK;
 }
 
-// Per-kernel times of the last sweep of a runner (timing mode).
-static void runner_kernel_ms(const Runner& r, double* ms_kernel) {
-  for (int k = 0; k < DD_N_KERNELS; k++) {
+// Per-kernel times of the last sweep of a runner (timing mode): durations
+// and start/end after the sweep's start event; ms_kernel[3 * DD_N_KERNELS].
+static void runner_kernel_ms(const Runner& r, double* mk) {
+  double* dur = mk;
+  double* t0 = mk + DD_N_KERNELS;
+  double* t1 = mk + 2 * DD_N_KERNELS;
+  auto span = [&](int slot, double* d, double* a, double* b) {
+    float s = 0, e = 0;
+    (void)hipEventElapsedTime(&s, r.ev0, r.kev[2 * slot]);
+    (void)hipEventElapsedTime(&e, r.ev0, r.kev[2 * slot + 1]);
     float t = 0;
-    hipEventElapsedTime(&t, r.kev[2 * k], r.kev[2 * k + 1]);
-    ms_kernel[k] = t;
+    (void)hipEventElapsedTime(&t, r.kev[2 * slot], r.kev[2 * slot + 1]);
+    *d += t;
+    *a = std::min(*a, (double)s);
+    *b = std::max(*b, (double)e);
+  };
+  for (int k = 0; k < DD_N_KERNELS; k++) {
+    dur[k] = 0;
+    t0[k] = INFINITY;
+    t1[k] = -INFINITY;
+    span(k, &dur[k], &t0[k], &t1[k]);
     if (k == 10)  // the Newton launches on the auxiliary streams
-      for (int i = 0; i < ddk::kNDeferGroups - 1; i++) {
-        float t2 = 0;
-        hipEventElapsedTime(&t2, r.kev[2 * (ddk::kNKernels + i)],
-                            r.kev[2 * (ddk::kNKernels + i) + 1]);
-        ms_kernel[k] += t2;
-      }
+      for (int i = 0; i < ddk::kNDeferGroups - 1; i++)
+        span(ddk::kNKernels + i, &dur[k], &t0[k], &t1[k]);
   }
 }
 
@@ -842,7 +865,11 @@ static dd_status sweep_finish(dd_ctx* c, int part, const IterStatsDev& d, float 
     r.evals_bin[k] = d.evals_bin[k];
   }
   if (ms_kernel)
-    for (int k = 0; k < DD_N_KERNELS; k++) r.ms_kernel[k] = ms_kernel[k];
+    for (int k = 0; k < DD_N_KERNELS; k++) {
+      r.ms_kernel[k] = ms_kernel[k];
+      r.ms_start[k] = ms_kernel[DD_N_KERNELS + k];
+      r.ms_end[k] = ms_kernel[2 * DD_N_KERNELS + k];
+    }
   c->nnz = d.nnz;
   c->last = r;
   c->last_part = part;
@@ -884,7 +911,7 @@ extern "C" dd_status dd_half_iterate(dd_ctx* c, int part, dd_iter_stats* out) {
   HIPCHK(c, hipStreamSynchronize(c->st));
   float ms = 0;
   hipEventElapsedTime(&ms, r.ev0, r.ev1);
-  double mk[DD_N_KERNELS];
+  double mk[3 * DD_N_KERNELS];
   if (kev) runner_kernel_ms(r, mk);
   r.stream_prev = r.hstats[0].cells_bin[ddk::kNBins - 2];
   return sweep_finish(c, part, r.hstats[0], ms, kev ? mk : nullptr, out);
@@ -1235,11 +1262,13 @@ namespace {
 
 // What a captured sweep depends on besides the parameter array's contents.
 struct GraphKey {
-  int n_prob = 0, total = 0, max_cells = 0, cap = 0, stream_wgs = 0, solver_pc = 0, newton_pc = 0;
+  int n_prob = 0, total = 0, max_cells = 0, cap = 0, stream_wgs = 0, solver_pc = 0, newton_pc = 0,
+      stream_max = 0, wg_cells = 0;
   const void* ptr[7] = {};
   bool operator==(const GraphKey& o) const {
     if (n_prob != o.n_prob || total != o.total || max_cells != o.max_cells || cap != o.cap ||
-        stream_wgs != o.stream_wgs || solver_pc != o.solver_pc || newton_pc != o.newton_pc)
+        stream_wgs != o.stream_wgs || solver_pc != o.solver_pc || newton_pc != o.newton_pc ||
+        stream_max != o.stream_max || wg_cells != o.wg_cells)
       return false;
     for (int i = 0; i < 7; i++)
       if (ptr[i] != o.ptr[i]) return false;
@@ -1347,6 +1376,8 @@ static dd_status batch_sweep(dd_batch* b, const int* parts, dd_iter_stats* out) 
     key.stream_wgs = r.stream_wgs;
     key.solver_pc = r.solver_per_cu;
     key.newton_pc = r.newton_per_cu;
+    key.stream_max = stream_limit(r);
+    key.wg_cells = r.wg_cells;
     const void* ptrs[7] = {r.dP, r.dstats, r.bin_list, r.defer_list, r.stream_tile, r.stream_S,
                            r.stream_nu};
     for (int i = 0; i < 7; i++) key.ptr[i] = ptrs[i];
@@ -1397,7 +1428,7 @@ static dd_status batch_sweep(dd_batch* b, const int* parts, dd_iter_stats* out) 
   BHIPCHK(b, hipStreamSynchronize(r.main));
   float ms = 0;
   (void)hipEventElapsedTime(&ms, r.ev0, r.ev1);
-  double mk[DD_N_KERNELS];
+  double mk[3 * DD_N_KERNELS];
   if (kev) runner_kernel_ms(r, mk);
   int sp = 0;
   dd_status worst = DD_OK;
@@ -1597,6 +1628,8 @@ struct Snapshot {
 
 const int kTuneSolver[] = {2, 4, 8, 16};
 const int kTuneNewton[] = {1, 2, 4};
+const int kTuneStream[] = {32, 64, 128, 256, 0};  // 0: two per compute unit
+const int kTuneCells[] = {0, 1, 2, 4};             // 0: persistent workgroups
 
 }  // namespace
 
@@ -1657,57 +1690,107 @@ static dd_status snap_restore(dd_ctx* c, const Snapshot& s) {
   return DD_OK;
 }
 
-static bool valid_launch(int solver_per_cu, int newton_per_cu) {
-  return solver_per_cu >= 1 && solver_per_cu <= 64 && newton_per_cu >= 1 && newton_per_cu <= 16;
+static bool valid_launch(const dd_tune_point* t) {
+  return t && t->solver_per_cu >= 1 && t->solver_per_cu <= 64 && t->newton_per_cu >= 1 &&
+         t->newton_per_cu <= 16 && t->stream_wgs >= 0 && t->stream_wgs <= 4096 &&
+         t->cells_per_wg >= 0 && t->cells_per_wg <= 1 << 20;
 }
 
-extern "C" dd_status dd_set_launch(dd_ctx* c, int solver_per_cu, int newton_per_cu) {
+static void apply_launch(Runner& r, const dd_tune_point& t) {
+  r.solver_per_cu = t.solver_per_cu;
+  r.newton_per_cu = t.newton_per_cu;
+  r.stream_max = t.stream_wgs;
+  r.wg_cells = t.cells_per_wg;
+}
+
+static dd_tune_point launch_of(const Runner& r) {
+  return dd_tune_point{r.solver_per_cu, r.newton_per_cu, r.stream_max, r.wg_cells, 0.0};
+}
+
+extern "C" dd_status dd_set_launch(dd_ctx* c, const dd_tune_point* cfg) {
   if (!c) return DD_EINVAL;
-  if (!valid_launch(solver_per_cu, newton_per_cu)) return fail(c, DD_EINVAL, "launch sizes out of range");
-  c->run.solver_per_cu = solver_per_cu;
-  c->run.newton_per_cu = newton_per_cu;
+  if (!valid_launch(cfg)) return fail(c, DD_EINVAL, "launch sizes out of range");
+  apply_launch(c->run, *cfg);
   return DD_OK;
 }
 
-extern "C" dd_status dd_batch_set_launch(dd_batch* b, int solver_per_cu, int newton_per_cu) {
+extern "C" dd_status dd_batch_set_launch(dd_batch* b, const dd_tune_point* cfg) {
   if (!b) return DD_EINVAL;
-  if (!valid_launch(solver_per_cu, newton_per_cu)) return bfail(b, DD_EINVAL, "launch sizes out of range");
-  b->run.solver_per_cu = solver_per_cu;
-  b->run.newton_per_cu = newton_per_cu;
+  if (!valid_launch(cfg)) return bfail(b, DD_EINVAL, "launch sizes out of range");
+  apply_launch(b->run, *cfg);
   return DD_OK;
 }
 
-// Time every candidate launch configuration on the same sweep (state restored
-// before each run and at the end), keep the fastest.  sweep(): runs the sweep
-// and returns its status and GPU time.
+extern "C" dd_status dd_get_launch(const dd_ctx* c, dd_tune_point* out) {
+  if (!c || !out) return DD_EINVAL;
+  *out = launch_of(c->run);
+  return DD_OK;
+}
+
+// Time candidate launch configurations on the same sweep (state restored
+// before each run and at the end) and keep the fastest, one axis at a time
+// with the others at the best so far: register-solver cells per workgroup,
+// the streamed solver's workgroups, Newton and (for persistent workgroups)
+// solver workgroups per compute unit.  sweep() runs the sweep and returns its
+// status and GPU time.  Every configuration gives the same results.
 template <typename Sweep, typename Restore>
 static dd_status tune_loop(Runner& r, int reps, Sweep sweep, Restore restore, dd_tune_point* best,
                            dd_tune_point* tried, int max_tried, int* n_tried) {
-  dd_tune_point b{};
-  b.ms = INFINITY;
   int nt = 0;
-  for (int sp : kTuneSolver)
-    for (int np : kTuneNewton) {
-      r.solver_per_cu = sp;
-      r.newton_per_cu = np;
-      double mn = INFINITY;
-      for (int k = 0; k < reps; k++) {
-        double ms = 0;
-        dd_status s = restore();
-        if (s < 0) return s;
-        s = sweep(&ms);
-        if (s < 0) return s;
-        mn = std::min(mn, ms);
+  std::vector<dd_tune_point> seen;
+  auto same = [](const dd_tune_point& a, const dd_tune_point& b) {
+    return a.solver_per_cu == b.solver_per_cu && a.newton_per_cu == b.newton_per_cu &&
+           a.stream_wgs == b.stream_wgs && a.cells_per_wg == b.cells_per_wg;
+  };
+  dd_tune_point b = launch_of(r);
+  b.ms = INFINITY;
+  auto run = [&](dd_tune_point c) -> dd_status {
+    for (const auto& q : seen)
+      if (same(q, c)) {
+        if (q.ms < b.ms) b = q;
+        return DD_OK;
       }
-      dd_tune_point t{sp, np, mn};
-      if (tried && nt < max_tried) tried[nt] = t;
-      nt++;
-      if (mn < b.ms) b = t;
+    apply_launch(r, c);
+    double mn = INFINITY;
+    for (int k = 0; k < reps; k++) {
+      double ms = 0;
+      dd_status s = restore();
+      if (s < 0) return s;
+      s = sweep(&ms);
+      if (s < 0) return s;
+      mn = std::min(mn, ms);
     }
-  const dd_status s = restore();
-  if (s < 0) return s;
-  r.solver_per_cu = b.solver_per_cu;
-  r.newton_per_cu = b.newton_per_cu;
+    c.ms = mn;
+    seen.push_back(c);
+    if (tried && nt < max_tried) tried[nt] = c;
+    nt++;
+    if (c.ms < b.ms) b = c;
+    return DD_OK;
+  };
+  dd_status s;
+  for (int v : kTuneCells) {
+    dd_tune_point c = b;
+    c.cells_per_wg = v;
+    if ((s = run(c)) < 0) return s;
+  }
+  for (int v : kTuneStream) {
+    dd_tune_point c = b;
+    c.stream_wgs = v;
+    if ((s = run(c)) < 0) return s;
+  }
+  for (int v : kTuneNewton) {
+    dd_tune_point c = b;
+    c.newton_per_cu = v;
+    if ((s = run(c)) < 0) return s;
+  }
+  if (b.cells_per_wg == 0)
+    for (int v : kTuneSolver) {
+      dd_tune_point c = b;
+      c.solver_per_cu = v;
+      if ((s = run(c)) < 0) return s;
+    }
+  if ((s = restore()) < 0) return s;
+  apply_launch(r, b);
   if (best) *best = b;
   if (n_tried) *n_tried = nt;
   return DD_OK;

@@ -25,7 +25,7 @@ EXPORTED = ["dd_options_default", "dd_init", "dd_half_iterate", "dd_set_eps", "d
             "dd_collect_cells", "dd_warm_start_count", "dd_batch_create",
             "dd_batch_half_iterate", "dd_batch_run_schedule", "dd_batch_schedule_step",
             "dd_batch_info", "dd_batch_free", "dd_set_launch", "dd_batch_set_launch",
-            "dd_autotune", "dd_batch_autotune",
+            "dd_autotune", "dd_batch_autotune", "dd_get_launch",
             "dd_batch_last_error"]
 
 DD_BATCH_GRAPH = 1
@@ -54,11 +54,13 @@ class IterStats(C.Structure):
                 ("n_failed", C.c_int), ("n_safeguard", C.c_int), ("n_newton", C.c_int),
                 ("nnz", C.c_int64), ("entry_evals", C.c_int64), ("cost", C.c_double),
                 ("obj", C.c_double), ("err_x", C.c_double), ("ms", C.c_double),
-                ("ms_kernel", C.c_double * N_KERNELS), ("cells_bin", C.c_int * N_BINS),
+                ("ms_kernel", C.c_double * N_KERNELS), ("ms_start", C.c_double * N_KERNELS),
+                ("ms_end", C.c_double * N_KERNELS), ("cells_bin", C.c_int * N_BINS),
                 ("evals_bin", C.c_int64 * N_BINS)]
 
     def as_dict(self):
-        return {k: (list(getattr(self, k)) if k in ("ms_kernel", "cells_bin", "evals_bin")
+        return {k: (list(getattr(self, k)) if k in ("ms_kernel", "ms_start", "ms_end", "cells_bin",
+                                                     "evals_bin")
                     else getattr(self, k)) for k, _ in self._fields_}
 
 
@@ -76,7 +78,8 @@ class RunStats(C.Structure):
 
 
 class TunePoint(C.Structure):
-    _fields_ = [("solver_per_cu", C.c_int), ("newton_per_cu", C.c_int), ("ms", C.c_double)]
+    _fields_ = [("solver_per_cu", C.c_int), ("newton_per_cu", C.c_int), ("stream_wgs", C.c_int),
+                ("cells_per_wg", C.c_int), ("ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -139,8 +142,10 @@ def _load():
     lib.dd_batch_half_iterate.argtypes = [C.c_void_p, C.c_int, P(IterStats)]
     lib.dd_batch_run_schedule.argtypes = [C.c_void_p, P(RunStats)]
     lib.dd_batch_schedule_step.argtypes = [C.c_void_p, P(IterStats), P(C.c_int)]
-    lib.dd_set_launch.argtypes = [C.c_void_p, C.c_int, C.c_int]
-    lib.dd_batch_set_launch.argtypes = [C.c_void_p, C.c_int, C.c_int]
+    lib.dd_set_launch.argtypes = [C.c_void_p, P(TunePoint)]
+    lib.dd_batch_set_launch.argtypes = [C.c_void_p, P(TunePoint)]
+    lib.dd_get_launch.argtypes = [C.c_void_p, P(TunePoint)]
+    lib.dd_get_launch.restype = C.c_int
     for name in ("dd_autotune", "dd_batch_autotune"):
         getattr(lib, name).argtypes = [C.c_void_p, C.c_int, C.c_int, P(TunePoint), P(TunePoint),
                                        C.c_int, P(C.c_int)]
@@ -315,8 +320,14 @@ class Problem:
                                       _p(status)), "dd_cell_results")
         return {"cost": cost, "obj": obj, "err_x": err, "loops": loops, "status": status}
 
-    def set_launch(self, solver_per_cu, newton_per_cu):
-        self._chk(lib.dd_set_launch(self._h, solver_per_cu, newton_per_cu), "dd_set_launch")
+    def set_launch(self, solver_per_cu=8, newton_per_cu=2, stream_wgs=0, cells_per_wg=0, **_):
+        t = TunePoint(solver_per_cu, newton_per_cu, stream_wgs, cells_per_wg, 0.0)
+        self._chk(lib.dd_set_launch(self._h, C.byref(t)), "dd_set_launch")
+
+    def get_launch(self):
+        t = TunePoint()
+        self._chk(lib.dd_get_launch(self._h, C.byref(t)), "dd_get_launch")
+        return t.as_dict()
 
     def autotune(self, partition, reps=1):
         """Time the candidate launch configurations on the next sweep of `partition`
@@ -400,9 +411,9 @@ class Batch:
         rc = self._chk(lib.dd_batch_run_schedule(self._h, st), "dd_batch_run_schedule")
         return [dict(x.as_dict(), status=rc) for x in st]
 
-    def set_launch(self, solver_per_cu, newton_per_cu):
-        self._chk(lib.dd_batch_set_launch(self._h, solver_per_cu, newton_per_cu),
-                  "dd_batch_set_launch")
+    def set_launch(self, solver_per_cu=8, newton_per_cu=2, stream_wgs=0, cells_per_wg=0, **_):
+        t = TunePoint(solver_per_cu, newton_per_cu, stream_wgs, cells_per_wg, 0.0)
+        self._chk(lib.dd_batch_set_launch(self._h, C.byref(t)), "dd_batch_set_launch")
 
     def autotune(self, partition, reps=1):
         return _autotune(lib.dd_batch_autotune, self._h, partition, reps, self._chk)
