@@ -22,6 +22,7 @@ namespace ddk {
 
 static constexpr double kLog2e = 1.4426950408889634;
 static constexpr double kLn2 = 0.6931471805599453;
+static constexpr float kLn2f = 0.6931471805599453f;
 
 // ------------------------------------------------------------ primitives
 
@@ -82,6 +83,16 @@ DEVI double wave_sum_dpp(double v) {
   const int lo = __builtin_amdgcn_readlane((int)(q & 0xffffffffll), 63);
   const int hi = __builtin_amdgcn_readlane((int)(q >> 32), 63);
   return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+
+DEVI float wave_sum_dpp_f(float v) {
+  v += __builtin_bit_cast(float, dpp_mov0<0xb1>(__builtin_bit_cast(int, v)));
+  v += __builtin_bit_cast(float, dpp_mov0<0x4e>(__builtin_bit_cast(int, v)));
+  v += __builtin_bit_cast(float, dpp_mov0<0x124>(__builtin_bit_cast(int, v)));
+  v += __builtin_bit_cast(float, dpp_mov0<0x128>(__builtin_bit_cast(int, v)));
+  v += __builtin_bit_cast(float, dpp_mov0<0x142>(__builtin_bit_cast(int, v)));
+  v += __builtin_bit_cast(float, dpp_mov0<0x143>(__builtin_bit_cast(int, v)));
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
 
 template <typename T>
@@ -709,7 +720,11 @@ DEVI XUpdate x_update(float r, double mu, float u, float* lup, float* unew_out, 
                       int it, int max_iter, int accel, ChebState& cheb, int lane) {
   XUpdate o;
   o.r = r;
-  const double e = wave_sum_dpp(mu > 0 ? fabs((double)u * (double)r - mu) : 0.0);
+  // |u r - mu| per pixel (one rounding through the FMA) summed in FP32: 64
+  // positive terms, relative error < 4e-6 of the sum, far below what the
+  // stopping test resolves
+  const float muf = (float)mu;
+  const double e = (double)wave_sum_dpp_f(mu > 0 ? fabsf(fmaf(u, r, -muf)) : 0.f);
   o.err = e;
   o.go_on = !(e <= tol) && it < max_iter && (e == e);
   double a0 = 0, b0 = 1, d0 = 0;
@@ -719,8 +734,7 @@ DEVI XUpdate x_update(float r, double mu, float u, float* lup, float* unew_out, 
   o.a = readlane0_d(a0);
   o.b = readlane0_d(b0);
   o.d = readlane0_d(d0);
-  const float muf = (float)mu;
-  const float un = mu > 0 ? muf / r : 0.f;
+  const float un = mu > 0 ? muf * __builtin_amdgcn_rcpf(r) : 0.f;
   const float lu = mu > 0 ? fast_log2(u) : 0.f;
   float unew = un;
   if (o.acc && mu > 0) unew = fast_exp2((float)(o.a * lu + o.b * fast_log2(un) + o.d * *lup));
@@ -880,7 +894,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
           transpose_y(rd, xg, yg, Sp, &a, &b);
           const float s = a + b;
           const int yi = ybase + xg;
-          sh.w[yi] = s > 0.f ? sh.nuf[yi] / s : 0.f;
+          sh.w[yi] = s > 0.f ? sh.nuf[yi] * __builtin_amdgcn_rcpf(s) : 0.f;
         }
         wave_sync();
         // ---- X-marginal: r(x) = sum_y P w
@@ -938,7 +952,9 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
               if (yi < U && wy > 0.f && nf > 0.f) {
                 const int rc = sh.yrc[yi];
                 const int dr = (rc >> 16) - xr, dc = (rc & 0xffff) - (g.C0 + j);
-                const double e = -(mbuf[yi] + log((double)(nf / wy))) + log((double)nf) -
+                // G(y) + log nu_J(y) = log w(y) - m(y): the FP32 logarithm of w
+                // is enough for the next absorbed potential (the loops go on)
+                const double e = (double)(fast_log2(wy) * kLn2f) - mbuf[yi] -
                                  lam * (double)(dr * dr + dc * dc);
                 mm = e > mm ? e : mm;
               }
@@ -971,7 +987,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
               if (yi < U && wy > 0.f && nf > 0.f) {
                 const int rc = sh.yrc[yi];
                 const int dr = (rc >> 16) - xr, dc = (rc & 0xffff) - (g.C0 + j);
-                const double e = -(mbuf[yi] + log((double)(nf / wy))) + log((double)nf) -
+                const double e = (double)(fast_log2(wy) * kLn2f) - mbuf[yi] -
                                  lam * (double)(dr * dr + dc * dc) - mm;
                 s += (double)fast_exp2((float)(e * kLog2e));
               }
@@ -1302,7 +1318,7 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
           transpose_y(rd, xg, yg, Sp, &a, &b);
           const int yi = sl * kSlab + yoff + xg;
           const float S = a + b;
-          const float w = (yi < U && S > 0.f) ? nug[yi] / S : 0.f;
+          const float w = (yi < U && S > 0.f) ? nug[yi] * __builtin_amdgcn_rcpf(S) : 0.f;
           Sg[yi] = S;
           sh.wl[wave][yg * 8 + xg] = w;
           wave_sync();
