@@ -22,11 +22,13 @@ PEAK_FP32_FMA_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12  # 78.6: non-packed FP32 
 # 2.0 and WRITE by 1.0, the factors a plain 256 MiB device copy gives); the
 # summary is kept under profiles/.  Valid only for the kernel source the
 # counters were taken on, identified by its hash.
-TRAFFIC_KERNEL_SHA256 = "5397b0b26b18938b5116e0bf7d0a1510455c8666d0ad5929cb91f486730af311"
+TRAFFIC_KERNEL_SHA256 = "602e237a8e389860313e4c6ef918f1f9b223f5d7b65412ae0faf43096bc0c217"
 TRAFFIC_BYTES_PER_LAUNCH = {
-    "solve_reg_16w": (2.0 * 73093 + 228981) * 1024,
-    "solve_reg_8w": (2.0 * 8482 + 15291) * 1024,
-    "solve_stream": (2.0 * 2328310 + 245373) * 1024,
+    "solve_stream": (2.0 * 2329361 + 245521) * 1024,
+    "solve_reg_16w": (2.0 * 87599 + 279245) * 1024,
+    "solve_reg_8w": (2.0 * 7877 + 15270) * 1024,
+    "solve_reg_4w": (2.0 * 2866 + 5007) * 1024,
+    "solve_reg_2w": (2.0 * 934 + 1386) * 1024,
 }
 
 
