@@ -1,7 +1,10 @@
-"""The C-ABI library loads and exports every function declared in include/dd.h (CPU only)."""
+"""The C-ABI library loads and exports every function declared in include/*.h, and the
+host-side recipes (schedules, generators, bench traffic guard) hold (CPU only)."""
 import ctypes
 import os
 import re
+
+import numpy as np
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -56,3 +59,39 @@ def test_generator_is_deterministic():
     assert a.dtype.name == "float64" and abs(a.sum() - 1) < 1e-14
     assert (a == b).all() and (a > 0).all()
     assert not (a == datagen.blob_image(32, 32, 4, 1001)).all()
+
+
+def test_uneven_batch_recipe():
+    from paper_2001_10986_amd import datagen
+    pairs = datagen.config4_pairs(8)
+    assert len(pairs) == 8
+    for mu, nu, cfg in pairs:
+        N = mu.shape[0]
+        assert mu.shape == nu.shape == (N, N) and N in (64, 128, 256, 512)
+        assert abs(mu.sum() - 1) < 1e-12 and abs(nu.sum() - 1) < 1e-12
+        # coarsest level 64 px, finest eps (1/N)^2
+        assert cfg["n_levels"] == int(np.log2(N // 64)) + 1
+        assert N >> (cfg["n_levels"] - 1) == 64
+        assert cfg["stages"][-1][0] == cfg["n_levels"] - 1
+        assert abs(cfg["stages"][-1][1] - 1.0 / N ** 2) < 1e-15
+    # the same recipe every time
+    again = datagen.config4_pairs(8)
+    assert all((a[0] == b[0]).all() for a, b in zip(pairs, again))
+
+
+def test_bench_traffic_only_for_the_profiled_kernel_build(tmp_path):
+    import importlib.util
+    spec = importlib.util.spec_from_file_location(
+        "bench", os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                              "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    # other workloads and unprofiled kernels report no traffic
+    assert bench.kernel_traffic("solve_reg_16w", 2) is None
+    assert bench.kernel_traffic("union", 3) is None
+    # a source that does not match the profiled hash reports none either
+    bench.ROOT = str(tmp_path)
+    src = tmp_path / "paper_2001_10986_amd" / "csrc"
+    src.mkdir(parents=True)
+    (src / "dd_kernels.hip").write_text("// changed\n")
+    assert bench.kernel_traffic("solve_reg_16w", 3) is None

@@ -184,8 +184,9 @@ def test_newton_fallback_matches_oracle(dd, ddo, N, K):
     # Newton steps after K loops: N=32 hands register-solver cells to the Newton
     # kernel, N=64 (U = 4096) runs them inside the log-domain big-cell solver.
     # Both sides stop on the same test at the same fixed point, but their
-    # Newton iterates differ (FP32 weights on the GPU), so the bar is the
-    # stopping tolerance rather than loop-for-loop agreement.
+    # Newton iterates differ (the GPU hands over the iterate of its FP32
+    # scaling loops), so the bar is the stopping tolerance rather than
+    # loop-for-loop agreement.
     mu, nu = datagen.small_pair(N, 3, seed=6)
     eps = 4.0 / N ** 2
     g = dd.Problem(mu, nu, [(0, eps, 4)], s=4, n_levels=1, newton_after=K)
