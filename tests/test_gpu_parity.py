@@ -270,3 +270,45 @@ def test_fp64_instantiation_matches_oracle_closely(dd, ddo):
     assert worst <= 1e-9
     cg, co = g.cost(), o.cost()
     assert abs(cg["cost"] - co["cost"]) <= 1e-10 * co["cost"]
+
+
+@pytest.mark.parametrize("shape,n_levels", [((32, 64), 1), ((64, 32), 2)])
+def test_rectangular_images_match_oracle(dd, ddo, shape, n_levels):
+    # H != W: the pixel spacing is 1/max(H, W) on both sides, B-cells clip at
+    # the longer border, refinement doubles both sides
+    H, W = shape
+    mu = datagen.blob_image(H, W, 4, 81)
+    nu = datagen.blob_image(H, W, 4, 82)
+    stages = [(0, 2.0 ** -8, 4)] + ([(1, 2.0 ** -10, 4)] if n_levels == 2 else [])
+    g = dd.Problem(mu, nu, stages, s=4, n_levels=n_levels)
+    g.run_schedule()
+    o = ddo.Oracle(mu, nu, s=4, n_levels=n_levels, eps=stages[0][1])
+    o.run_schedule(stages)
+    cg, co = g.cost(), o.cost()
+    assert cg["level"] == co["level"] == n_levels - 1
+    assert abs(cg["cost"] - co["cost"]) <= 1e-5 * co["cost"]
+    assert cg["err_x"] <= 1e-5 and cg["err_y"] <= 1e-5
+    bg, bo = g.basic_marginals(), o.basic_marginals()
+    assert bg.shape == bo.shape
+    assert np.abs(bg - bo).max() < 2e-5 * bg.sum(axis=1).max()
+
+
+def test_identical_marginals(dd, ddo):
+    # mu = nu, from the product coupling: the decomposition moves the mass
+    # back to where it sits, the objective falls on every sweep and both sides
+    # agree along the way
+    N = 32
+    mu = datagen.blob_image(N, N, 4, 91)
+    eps = 4.0 / N ** 2
+    g = dd.Problem(mu, mu, [(0, eps, 12)], s=4, n_levels=1)
+    o = ddo.Oracle(mu, mu, s=4, n_levels=1, eps=eps)
+    prev = None
+    for ell in range(12):
+        sg = g.half_iterate(ell % 2)
+        so = o.half_iterate(ell % 2)
+        assert abs(sg["cost"] - so["cost"]) <= 1e-5 * so["cost"]
+        if prev is not None:
+            assert sg["obj"] <= prev + 1e-12
+        prev = sg["obj"]
+    cg = g.cost()
+    assert cg["err_x"] <= 1e-5 and cg["err_y"] <= 1e-5
