@@ -170,9 +170,11 @@ __global__ __launch_bounds__(1024) void k_scan_T(const HalfParams* __restrict__ 
 
 // Cells handed to Newton steps are collected per group of solver launches
 // that share a stream, so that each group's Newton launch can follow its
-// producers on that stream: bins 0-2 (main stream), 3, 4, and the streamed
-// solver (bin 5).
-DEVI int defer_group(int bin) { return bin <= 2 ? 0 : bin - 2; }
+// producers on that stream: bin 2 (main stream), bins 0 and 3, bins 1 and 4,
+// and the streamed solver (bin 5).
+DEVI int defer_group(int bin) {
+  return bin == 2 ? 0 : bin == 0 || bin == 3 ? 1 : bin == 1 || bin == 4 ? 2 : 3;
+}
 
 // Size bin of a cell (the FP64 instantiation puts every cell on the
 // log-domain solver).
@@ -1713,10 +1715,13 @@ DEVI double phi1d(double b) {
 
 // Conditional plan of support point yi for the 4 pixels xs + 16k of this
 // thread (16 threads per support point, lanes xs = tid & 15 of a 16-lane
-// group): pk[k] = p_x(y), returns m + log s (= -G(y)).  exact: FP64
-// exponentials (for the Newton system), else FP32 (plain iterations).
+// group): pk[k] = p_x(y), returns m + log s (= -G(y)).  prec 0: FP32
+// exponentials (plain iterations); 1: FP64 exponentials (the Newton system);
+// 2: FP64 exponentials and logarithm (FP64 instantiation).  s lies in
+// [1, 64] (the largest term is e^0), so the FP32 logarithm is accurate to
+// ~1e-7 absolute.
 DEVI double cond_plan(const BigShared& sh, int r, int c, int xs, double lam, double pk[4],
-                      bool exact) {
+                      int prec) {
   double e[4];
   double m = -INFINITY;
 #pragma unroll
@@ -1733,7 +1738,7 @@ DEVI double cond_plan(const BigShared& sh, int r, int c, int xs, double lam, dou
     // the plans of far-apart pixels underflow FP32, and the Newton system
     // needs exactly those weak couplings
     v[k] = e[k] == -INFINITY ? 0.0
-           : exact          ? exp(e[k] - m)
+           : prec > 0       ? exp(e[k] - m)
                             : (double)fast_exp2((float)((e[k] - m) * kLog2e));
     s += v[k];
   }
@@ -1741,7 +1746,7 @@ DEVI double cond_plan(const BigShared& sh, int r, int c, int xs, double lam, dou
   const double inv = 1.0 / s;
 #pragma unroll
   for (int k = 0; k < 4; k++) pk[k] = v[k] * inv;
-  return m + log(s);
+  return m + (prec == 2 ? log(s) : (double)fast_log2((float)s) * kLn2);
 }
 
 __global__ __launch_bounds__(kBigThreads) void k_solve_big(const HalfParams* __restrict__ P,
@@ -1922,7 +1927,7 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(const HalfParams* __r
             if (yi < U) {  // uniform within each 16-lane group
               int r, c;
               split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
-              const double lse = cond_plan(sh, r, c, xs, lam, pk, build_w || fp64);
+              const double lse = cond_plan(sh, r, c, xs, lam, pk, fp64 ? 2 : build_w ? 1 : 0);
               const double nu = p.uni_nu[ub + yi];
 #pragma unroll
               for (int k = 0; k < 4; k++) racc[k] += nu * pk[k];
@@ -2035,7 +2040,7 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(const HalfParams* __r
                     int r, c;
                     split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
                     double pk[4];
-                    cond_plan(sh, r, c, xs, lam, pk, true);
+                    cond_plan(sh, r, c, xs, lam, pk, fp64 ? 2 : 1);
                     double a[4], cy = 0;
 #pragma unroll
                     for (int k = 0; k < 4; k++) {
@@ -2506,12 +2511,21 @@ void launch_sweep_solve(const HalfParams* P, const SweepSched& s, const SweepStr
   pre(kNKernels + 0, ss.aux[0]);
   hipLaunchKernelGGL(k_solve_big, dim3(gr.newton), dim3(kBigThreads), 0, ss.aux[0], P, s, 1 + 3);
   post(kNKernels + 0, ss.aux[0]);
+  // the small-cell bins go first on their streams: launched behind the
+  // persistent workgroups of the large bins they would wait for free compute
+  // units until those drain
+  pre(4, ss.aux[1]);
+  hipLaunchKernelGGL(k_solve_reg<2>, dim3(gr.bin[1]), dim3(128), 0, ss.aux[1], P, s, 1);
+  post(4, ss.aux[1]);
   pre(7, ss.aux[1]);
   hipLaunchKernelGGL(k_solve_reg<16>, dim3(gr.bin[4]), dim3(1024), 0, ss.aux[1], P, s, 4);
   post(7, ss.aux[1]);
   pre(kNKernels + 1, ss.aux[1]);
   hipLaunchKernelGGL(k_solve_big, dim3(gr.newton), dim3(kBigThreads), 0, ss.aux[1], P, s, 1 + 2);
   post(kNKernels + 1, ss.aux[1]);
+  pre(3, ss.aux[2]);
+  hipLaunchKernelGGL(k_solve_reg<1>, dim3(gr.bin[0]), dim3(64), 0, ss.aux[2], P, s, 0);
+  post(3, ss.aux[2]);
   pre(6, ss.aux[2]);
   hipLaunchKernelGGL(k_solve_reg<8>, dim3(gr.bin[3]), dim3(512), 0, ss.aux[2], P, s, 3);
   post(6, ss.aux[2]);
@@ -2521,12 +2535,6 @@ void launch_sweep_solve(const HalfParams* P, const SweepSched& s, const SweepStr
   pre(5, st);
   hipLaunchKernelGGL(k_solve_reg<4>, dim3(gr.bin[2]), dim3(256), 0, st, P, s, 2);
   post(5, st);
-  pre(4, st);
-  hipLaunchKernelGGL(k_solve_reg<2>, dim3(gr.bin[1]), dim3(128), 0, st, P, s, 1);
-  post(4, st);
-  pre(3, st);
-  hipLaunchKernelGGL(k_solve_reg<1>, dim3(gr.bin[0]), dim3(64), 0, st, P, s, 0);
-  post(3, st);
   pre(10, st);
   hipLaunchKernelGGL(k_solve_big, dim3(gr.newton), dim3(kBigThreads), 0, st, P, s, 1 + 0);
   post(10, st);
