@@ -312,3 +312,21 @@ def test_identical_marginals(dd, ddo):
         prev = sg["obj"]
     cg = g.cost()
     assert cg["err_x"] <= 1e-5 and cg["err_y"] <= 1e-5
+
+
+def test_split_precision_matches_fp64_instantiation_at_256(dd):
+    # the 256x256 workload (3 levels, eps 1 -> (1/256)^2): the split precision
+    # (FP32 exponentials) against the FP64 instantiation of the same iteration
+    mu, nu, cfg = datagen.config2_pair()
+    res = {}
+    for prec in (dd.DD_PREC_SPLIT, dd.DD_PREC_FP64):
+        g = dd.Problem(mu, nu, cfg["stages"], s=4, n_levels=cfg["n_levels"], precision=prec)
+        rs = g.run_schedule()
+        res[prec] = (g.cost(), rs, g.basic_marginals())
+        g.close()
+    (c32, r32, b32), (c64, r64, b64) = res[dd.DD_PREC_SPLIT], res[dd.DD_PREC_FP64]
+    print("256^2 split", c32["cost"], r32["loops_total"], "fp64", c64["cost"], r64["loops_total"])
+    for c, r in ((c32, r32), (c64, r64)):
+        assert r["n_failed"] == 0 and c["err_x"] <= 1e-5 and c["err_y"] <= 1e-5
+    assert abs(c32["cost"] - c64["cost"]) <= 1e-5 * c64["cost"]
+    assert np.abs(b32 - b64).sum() <= 1e-4
