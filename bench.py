@@ -16,6 +16,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP32_FMA_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12  # 78.6: non-packed FP32 FMA issue rate
+PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 
 # HBM bytes per launch of the solver kernels on the 1024x1024 schedule, from
 # rocprofv3 FETCH_SIZE and WRITE_SIZE runs (KiB per dispatch, FETCH scaled by
@@ -164,6 +165,16 @@ def main():
             "traffic_unit": "HBM bytes per launch", "launches": launches,
             "avg_launch_ms": tot_ms[solver] / max(launches, 1),
             "flops_per_launch": flops / max(launches, 1)}
+    # the streamed solver keeps its cell's kernel tile in memory and reads it
+    # in both passes of every loop: as a memory-bound kernel its algorithmic
+    # traffic is 2 passes x 4 B per kernel entry, i.e. 2 bytes per counted flop
+    roof_mem = None
+    if dd.KERNEL_NAMES[solver] == "solve_stream" and tot_ms[solver] > 0:
+        gbs = 2.0 * flops / (tot_ms[solver] / 1000) / 1e9
+        roof_mem = {"kernel": "solve_stream", "bound": "hbm", "achieved": gbs,
+                    "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
+                    "bytes_per_launch": 2.0 * flops / max(launches, 1),
+                    "note": "tile reads of both passes per loop (8 B per kernel entry)"}
     kernel_ms = {dd.KERNEL_NAMES[k]: tot_ms[k] / args.steps for k in range(dd.N_KERNELS)}
 
     # CPU baseline: the FP64 oracle on a sample of cells of one more sweep
@@ -374,6 +385,7 @@ def main():
         "autotune": tune,
         "batch": batch,
         "roofline": roof,
+        "roofline_memory_view": roof_mem,
         "cpu_baseline": cpu,
         "parity_sample": parity,
     }

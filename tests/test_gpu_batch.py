@@ -197,3 +197,25 @@ def test_batch_autotune_then_sweeps_equal_single(dd):
     for g, h in zip(single, batched):
         _states_equal(g, h)
     b.close()
+
+
+def test_batch_mixes_precisions(dd):
+    # a split-precision and an FP64 problem in one batch: each keeps its own
+    # solver path (the FP64 one's cells all go to the log-domain solver)
+    mu, nu = datagen.small_pair(32, 3, seed=95)
+    st = [(0, 4.0 / 32 ** 2, 4)]
+    single = [dd.Problem(mu, nu, st, s=4, n_levels=1, precision=p)
+              for p in (dd.DD_PREC_SPLIT, dd.DD_PREC_FP64)]
+    batched = [dd.Problem(mu, nu, st, s=4, n_levels=1, precision=p)
+               for p in (dd.DD_PREC_SPLIT, dd.DD_PREC_FP64)]
+    b = dd.Batch(batched)
+    for ell in range(4):
+        sb = b.half_iterate(ell % 2)
+        for i, g in enumerate(single):
+            ss = g.half_iterate(ell % 2)
+            assert sb[i]["cells_bin"] == ss["cells_bin"]
+            assert sb[i]["loops_total"] == ss["loops_total"]
+        assert sb[1]["cells_bin"][dd.N_BINS - 1] == sb[1]["n_cells"]
+    for g, h in zip(single, batched):
+        _states_equal(g, h)
+    b.close()
