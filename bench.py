@@ -282,7 +282,7 @@ def main():
             "loops_vs_plain": rsl["loops_total"] / rs["loops_total"],
             "cells_newton": rsl["n_newton"],
             "sweeps_with_network": wsw, "cells_warm_started": wsc,
-            "policy": f"first sweep of each partition after refine/eps change, "
+            "policy": f"first sweep of each partition after init or refinement, "
                       f"cells with predicted-change RMS >= {warmstart.MIN_RMS}",
             "train": {"pairs": args.learned_pairs, "samples": n, "steps": args.learned_steps,
                       "val_loss_before": val0, "val_loss_after": val1,

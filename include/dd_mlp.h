@@ -70,7 +70,8 @@ void* dd_mlp_get_stream(const dd_mlp* net);
  * dd_set_warm_start: attach a network (n_in 768, n_out 64) or detach it
  * (net NULL).  policy 1: predict the start of every eligible cell on the
  * first sweep of each partition after dd_init, dd_refine or an eps change;
- * policy 2: on every sweep; 0: never.  On such a sweep the prediction replaces
+ * policy 2: on every sweep; policy 3: on the first sweep of each partition
+ * after dd_init or dd_refine only; 0: never.  On such a sweep the prediction replaces
  * the start of a cell only if the RMS of its predicted change (output units,
  * over the pixels of positive mass) is at least min_rms.  The network must
  * outlive its use.  The cell solves still run to the stopping tolerance of

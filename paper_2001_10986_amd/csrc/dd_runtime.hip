@@ -278,6 +278,7 @@ struct dd_ctx {
   float warm_min_rms = 0.f;
   int* warm_count = nullptr;        // cells warm-started, summed over sweeps (device)
   int warm_fresh[2] = {1, 1};     // no sweep of this partition since init/refine/eps change
+  int warm_level[2] = {1, 1};     // no sweep of this partition since init/refine
   unsigned short* warm_X = nullptr;
   float* warm_Y = nullptr;
   int warm_rows = 0;
@@ -741,7 +742,7 @@ static dd_status warm_start(dd_ctx* c, const HalfParams& p) {
 }
 
 extern "C" dd_status dd_set_warm_start(dd_ctx* c, dd_mlp* net, int policy, float min_rms) {
-  if (!c || policy < 0 || policy > 2 || !(min_rms >= 0)) return DD_EINVAL;
+  if (!c || policy < 0 || policy > 3 || !(min_rms >= 0)) return DD_EINVAL;
   if (net) {
     int n_in = 0, n_out = 0;
     dd_mlp_shape(net, &n_in, &n_out, nullptr, nullptr);
@@ -753,6 +754,7 @@ extern "C" dd_status dd_set_warm_start(dd_ctx* c, dd_mlp* net, int policy, float
   c->warm_policy = net ? policy : 0;
   c->warm_min_rms = min_rms;
   c->warm_fresh[0] = c->warm_fresh[1] = 1;
+  c->warm_level[0] = c->warm_level[1] = 1;
   return DD_OK;
 }
 
@@ -895,13 +897,15 @@ extern "C" dd_status dd_half_iterate(dd_ctx* c, int part, dd_iter_stats* out) {
   HIPCHK(c, hipEventRecord(r.ev0, c->st));
   ddk::launch_sweep_prep(r.dP, sc, r.ss, gr, kev);
   const bool warm = c->warm_net && c->warm_policy > 0 &&
-                    (c->warm_policy == 2 || c->warm_fresh[part]);
+                    (c->warm_policy == 2 || (c->warm_policy == 1 && c->warm_fresh[part]) ||
+                     (c->warm_policy == 3 && c->warm_level[part]));
   if (warm) {
     dd_status ws = warm_start(c, p);
     if (ws) return ws;
     c->n_warm_sweeps++;
   }
   c->warm_fresh[part] = 0;
+  c->warm_level[part] = 0;
   ddk::launch_sweep_solve(r.dP, sc, r.ss, gr, kev);
   HIPCHK(c, hipGetLastError());
   ddk::launch_stats(r.dP, 1, r.dstats, c->st, kev ? kev + 2 * (DD_N_KERNELS - 1) : nullptr);
@@ -1078,6 +1082,7 @@ extern "C" dd_status dd_refine(dd_ctx* c) {
   c->nb = nbf;
   c->last_part = -1;
   c->warm_fresh[0] = c->warm_fresh[1] = 1;
+  c->warm_level[0] = c->warm_level[1] = 1;
   return upload_cells(c);
 }
 
@@ -1623,6 +1628,7 @@ struct Snapshot {
   dd_iter_stats last{};
   bool prev_valid = false;
   int warm_fresh[2] = {1, 1};
+  int warm_level[2] = {1, 1};
   int n_warm_sweeps = 0;
 };
 
@@ -1654,6 +1660,8 @@ static dd_status snap_take(dd_ctx* c, int part, Snapshot& s) {
   s.prev_valid = c->prev_valid;
   s.warm_fresh[0] = c->warm_fresh[0];
   s.warm_fresh[1] = c->warm_fresh[1];
+  s.warm_level[0] = c->warm_level[0];
+  s.warm_level[1] = c->warm_level[1];
   s.n_warm_sweeps = c->n_warm_sweeps;
   HIPCHK(c, dmalloc(&s.row_off, s.nb));
   HIPCHK(c, dmalloc(&s.row_len, s.nb));
@@ -1686,6 +1694,8 @@ static dd_status snap_restore(dd_ctx* c, const Snapshot& s) {
   c->prev_valid = s.prev_valid;
   c->warm_fresh[0] = s.warm_fresh[0];
   c->warm_fresh[1] = s.warm_fresh[1];
+  c->warm_level[0] = s.warm_level[0];
+  c->warm_level[1] = s.warm_level[1];
   c->n_warm_sweeps = s.n_warm_sweeps;
   return DD_OK;
 }
