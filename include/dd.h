@@ -81,7 +81,7 @@ typedef struct {
                               stopping test, same fixed point), 0: plain Sinkhorn; default 1 */
   int newton_after;        /* >0: a cell not converged after this many loops continues with
                               damped Newton steps on its X potential (same stopping test, same
-                              fixed point); 0: never; default 256 */
+                              fixed point); 0: never; default 384 */
   int precision;           /* DD_PREC_SPLIT (default): FP32 exponentials in the Sinkhorn bulk,
                               FP64 potentials, sums and bookkeeping; DD_PREC_FP64: every cell on
                               the log-domain solver with FP64 exponentials (the arithmetic of the

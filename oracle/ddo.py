@@ -82,7 +82,7 @@ class Oracle:
     """One problem instance of the oracle; mirrors the C-ABI of the GPU library."""
 
     def __init__(self, mu, nu, s=4, n_levels=1, eps=1.0, err_tol=1e-5, trunc=1e-15,
-                 max_iter=50000, n_threads=0, safeguard=1, accel=1, newton_after=256):
+                 max_iter=50000, n_threads=0, safeguard=1, accel=1, newton_after=384):
         mu = np.ascontiguousarray(mu, dtype=np.float64)
         nu = np.ascontiguousarray(nu, dtype=np.float64)
         assert mu.shape == nu.shape and mu.ndim == 2

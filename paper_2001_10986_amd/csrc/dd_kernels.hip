@@ -1631,20 +1631,24 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
 // Y potential eliminated by the exact Y-iteration).  Gradient mu - r, minus
 // the Hessian is the Laplacian of W(x,x') = sum_y nu_J p_x(y) p_x'(y) with
 // p_x(y) the conditional plan.  Each iteration: one Y-iteration (the loop and
-// its stopping test), W in FP32, the grounded Laplacian system solved by
+// its stopping test), W in FP64, the grounded Laplacian system solved by
 // subtraction-free (GTH) elimination, the step capped to max|d| <= 8, then a
 // backtracking Armijo search on the increase of Phi evaluated as
 //   <g, a> - sum_y nu_J log(sum_x p_x (e^(a - c_y))),  c_y = sum_x p_x a,
 // (two non-negative sums) and, if no trial passes, a plain X-iteration.
+// Waves per workgroup: 8 for the log-domain solver of the largest bin, 16 for
+// the Newton launches (one tail cell then holds a compute unit alone, and
+// twice the waves hide more of the FP64 latency).
 constexpr int kBigWaves = 8;
-constexpr int kBigThreads = kBigWaves * 64;
-constexpr int kNChunk = kBigThreads / 16;  // support points per Newton chunk (16 threads each)
+constexpr int kNewtonWaves = 16;
 constexpr int kNewtonMaxSteps = 100;
 constexpr double kNewtonStepCap = 8.0;
 constexpr int kNewtonTrials = 10;
 constexpr double kNewtonArmijo = 1e-4;
 
+template <int NW>
 struct BigShared {
+  static constexpr int kNChunk = NW * 4;  // support points per Newton chunk (16 threads each)
   double F[64], Fmu[64], mu[64], Fh[64], F0orig[64], Fp[64];
   double r[64], b[64], dl[64], piv[64];
   ChebState cheb;
@@ -1653,10 +1657,10 @@ struct BigShared {
   int xr[64], xc[64];
   union {
     struct {
-      double pm[kBigWaves][64], ps[kBigWaves][64];
+      double pm[NW][64], ps[NW][64];
     } lse;                       // Sinkhorn X-marginal partials
     double q[64][kNChunk + 1];   // Newton: p_x(y) sqrt(nu_J(y)) of one chunk of support points
-    double racc[kBigWaves][64];  // Newton: X-marginal partials per wave
+    double racc[NW][64];         // Newton: X-marginal partials per wave
   } u;
   double Wm[64][65];             // Newton: weights W(x,x'), eliminated in place
   double err, slope;
@@ -1720,7 +1724,8 @@ DEVI double phi1d(double b) {
 // 2: FP64 exponentials and logarithm (FP64 instantiation).  s lies in
 // [1, 64] (the largest term is e^0), so the FP32 logarithm is accurate to
 // ~1e-7 absolute.
-DEVI double cond_plan(const BigShared& sh, int r, int c, int xs, double lam, double pk[4],
+template <class SH>
+DEVI double cond_plan(const SH& sh, int r, int c, int xs, double lam, double pk[4],
                       int prec) {
   double e[4];
   double m = -INFINITY;
@@ -1749,9 +1754,12 @@ DEVI double cond_plan(const BigShared& sh, int r, int c, int xs, double lam, dou
   return m + (prec == 2 ? log(s) : (double)fast_log2((float)s) * kLn2);
 }
 
-__global__ __launch_bounds__(kBigThreads) void k_solve_big(const HalfParams* __restrict__ P,
-                                                           SweepSched s, int mode) {
-  __shared__ BigShared sh;
+template <int NW>
+__global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restrict__ P,
+                                                       SweepSched s, int mode) {
+  constexpr int kBigThreads = NW * 64, kNChunk = BigShared<NW>::kNChunk;
+  constexpr int kTiles = 16 / NW;  // 16x16 tiles of W per wave
+  __shared__ BigShared<NW> sh;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int yl = tid >> 4, xs = tid & 15;  // Newton layout: kNChunk support points x 16 threads
   const bool deferred = mode >= 1;
@@ -1849,7 +1857,7 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(const HalfParams* __r
         {
           const int x = lane;
           double m = -INFINITY, s = 0;
-          for (int yi = wave; yi < U; yi += kBigWaves) {
+          for (int yi = wave; yi < U; yi += NW) {
             int r, c;
             split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
             const int dr = r - sh.xr[x], dc = c - sh.xc[x];
@@ -1868,9 +1876,9 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(const HalfParams* __r
         __syncthreads();
         if (wave == 0) {
           double m = -INFINITY;
-          for (int w = 0; w < kBigWaves; w++) m = sh.u.lse.pm[w][lane] > m ? sh.u.lse.pm[w][lane] : m;
+          for (int w = 0; w < NW; w++) m = sh.u.lse.pm[w][lane] > m ? sh.u.lse.pm[w][lane] : m;
           double s = 0;
-          for (int w = 0; w < kBigWaves; w++)
+          for (int w = 0; w < NW; w++)
             if (sh.u.lse.ps[w][lane] > 0) s += sh.u.lse.ps[w][lane] * exp(sh.u.lse.pm[w][lane] - m);
           const double Fh = -(m + log(s));
           sh.Fh[lane] = Fh;
@@ -1912,14 +1920,14 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(const HalfParams* __r
           const bool build_w = nst < kNewtonMaxSteps && n_act > 1;
           // ---- Y-iteration with conditional plans, X-marginal r, weights W
           double racc[4] = {0, 0, 0, 0};
-          // W = Q Q^T by FP64 matrix cores: wave w owns the 16x16 tiles
-          // (w>>1, 2(w&1)) and (w>>1, 2(w&1)+1).  The couplings of far-apart
+          // W = Q Q^T by FP64 matrix cores, 16x16 tiles.  The couplings of far-apart
           // pixels are tiny and the Newton step follows the smallest
           // eigenvalues of the Laplacian, so W is formed and eliminated in FP64.
-          doublex4 wacc0 = {}, wacc1 = {};
-          const int wr = 16 * (wave >> 1) + (lane & 15);       // row of Q for operand A
-          const int wc = 16 * (2 * (wave & 1)) + (lane & 15);  // row of Q for operand B
-          const int wk = lane >> 4;                            // k within a step of 4
+          // wave w owns the tiles t = kTiles w + j: rows 16 (t >> 2), columns 16 (t & 3)
+          doublex4 wacc[kTiles] = {};
+          const int wr = 16 * ((kTiles * wave) >> 2) + (lane & 15);  // row of Q for operand A
+          const int wc = 16 * ((kTiles * wave) & 3) + (lane & 15);   // row of Q for operand B
+          const int wk = lane >> 4;                                  // k within a step of 4
           for (int y0 = 0; y0 < U; y0 += kNChunk) {
             const int yi = y0 + yl;
             double pk[4] = {0, 0, 0, 0};
@@ -1941,9 +1949,10 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(const HalfParams* __r
 #pragma unroll
               for (int k0 = 0; k0 < kNChunk; k0 += 4) {
                 const double a = sh.u.q[wr][k0 + wk];
-                wacc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sh.u.q[wc][k0 + wk], wacc0, 0, 0, 0);
-                wacc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sh.u.q[wc + 16][k0 + wk], wacc1, 0,
-                                                             0, 0);
+#pragma unroll
+                for (int j = 0; j < kTiles; j++)
+                  wacc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, sh.u.q[wc + 16 * j][k0 + wk],
+                                                                 wacc[j], 0, 0, 0);
               }
               __syncthreads();
             }
@@ -1959,15 +1968,14 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(const HalfParams* __r
           if (build_w)
 #pragma unroll
             for (int v = 0; v < 4; v++) {  // D(i,j): i = 4v + lane/16, j = lane%16
-              const int i = 16 * (wave >> 1) + 4 * v + (lane >> 4);
-              const int j = 32 * (wave & 1) + (lane & 15);
-              sh.Wm[i][j] = wacc0[v];
-              sh.Wm[i][j + 16] = wacc1[v];
+              const int i = wr - (lane & 15) + 4 * v + (lane >> 4);
+#pragma unroll
+              for (int j = 0; j < kTiles; j++) sh.Wm[i][wc + 16 * j] = wacc[j][v];
             }
           __syncthreads();
           if (wave == 0) {
             double r = 0;
-            for (int w = 0; w < kBigWaves; w++) r += sh.u.racc[w][lane];
+            for (int w = 0; w < NW; w++) r += sh.u.racc[w][lane];
             const double mu = sh.mu[lane];
             if (!(mu > 0)) r = 0;
             sh.r[lane] = r;
@@ -2004,7 +2012,7 @@ __global__ __launch_bounds__(kBigThreads) void k_solve_big(const HalfParams* __r
               if (dk > 0) {
                 const double inv = 1.0 / dk;
                 if (wave == 0 && lane > k) sh.b[lane] += sh.Wm[lane][k] * inv * sh.b[k];
-                for (int i = k + 1 + wave; i < 64; i += kBigWaves) {
+                for (int i = k + 1 + wave; i < 64; i += NW) {
                   const double c = sh.Wm[i][k] * inv;
                   if (lane > k && lane != i && c != 0) sh.Wm[i][lane] += c * sh.Wm[k][lane];
                 }
@@ -2506,10 +2514,10 @@ void launch_sweep_solve(const HalfParams* P, const SweepSched& s, const SweepStr
   if (gs > 0) hipLaunchKernelGGL(k_solve_stream, dim3(gs), dim3(kSlab), 0, ss.aux[0], P, s);
   post(8, ss.aux[0]);
   pre(9, ss.aux[0]);
-  hipLaunchKernelGGL(k_solve_big, dim3(gr.bin[6]), dim3(kBigThreads), 0, ss.aux[0], P, s, 0);
+  hipLaunchKernelGGL(k_solve_big<kBigWaves>, dim3(gr.bin[6]), dim3(kBigWaves * 64), 0, ss.aux[0], P, s, 0);
   post(9, ss.aux[0]);
   pre(kNKernels + 0, ss.aux[0]);
-  hipLaunchKernelGGL(k_solve_big, dim3(gr.newton), dim3(kBigThreads), 0, ss.aux[0], P, s, 1 + 3);
+  hipLaunchKernelGGL(k_solve_big<kNewtonWaves>, dim3(gr.newton), dim3(kNewtonWaves * 64), 0, ss.aux[0], P, s, 1 + 3);
   post(kNKernels + 0, ss.aux[0]);
   // the small-cell bins go first on their streams: launched behind the
   // persistent workgroups of the large bins they would wait for free compute
@@ -2521,7 +2529,7 @@ void launch_sweep_solve(const HalfParams* P, const SweepSched& s, const SweepStr
   hipLaunchKernelGGL(k_solve_reg<16>, dim3(gr.bin[4]), dim3(1024), 0, ss.aux[1], P, s, 4);
   post(7, ss.aux[1]);
   pre(kNKernels + 1, ss.aux[1]);
-  hipLaunchKernelGGL(k_solve_big, dim3(gr.newton), dim3(kBigThreads), 0, ss.aux[1], P, s, 1 + 2);
+  hipLaunchKernelGGL(k_solve_big<kNewtonWaves>, dim3(gr.newton), dim3(kNewtonWaves * 64), 0, ss.aux[1], P, s, 1 + 2);
   post(kNKernels + 1, ss.aux[1]);
   pre(3, ss.aux[2]);
   hipLaunchKernelGGL(k_solve_reg<1>, dim3(gr.bin[0]), dim3(64), 0, ss.aux[2], P, s, 0);
@@ -2530,13 +2538,13 @@ void launch_sweep_solve(const HalfParams* P, const SweepSched& s, const SweepStr
   hipLaunchKernelGGL(k_solve_reg<8>, dim3(gr.bin[3]), dim3(512), 0, ss.aux[2], P, s, 3);
   post(6, ss.aux[2]);
   pre(kNKernels + 2, ss.aux[2]);
-  hipLaunchKernelGGL(k_solve_big, dim3(gr.newton), dim3(kBigThreads), 0, ss.aux[2], P, s, 1 + 1);
+  hipLaunchKernelGGL(k_solve_big<kNewtonWaves>, dim3(gr.newton), dim3(kNewtonWaves * 64), 0, ss.aux[2], P, s, 1 + 1);
   post(kNKernels + 2, ss.aux[2]);
   pre(5, st);
   hipLaunchKernelGGL(k_solve_reg<4>, dim3(gr.bin[2]), dim3(256), 0, st, P, s, 2);
   post(5, st);
   pre(10, st);
-  hipLaunchKernelGGL(k_solve_big, dim3(gr.newton), dim3(kBigThreads), 0, st, P, s, 1 + 0);
+  hipLaunchKernelGGL(k_solve_big<kNewtonWaves>, dim3(gr.newton), dim3(kNewtonWaves * 64), 0, st, P, s, 1 + 0);
   post(10, st);
   // join
   for (int i = 0; i < 3; i++) {
@@ -2548,7 +2556,8 @@ void launch_sweep_solve(const HalfParams* P, const SweepSched& s, const SweepStr
 size_t sweep_max_static_lds() {
   const void* ks[] = {(const void*)k_union, (const void*)k_solve_reg<1>, (const void*)k_solve_reg<2>,
                       (const void*)k_solve_reg<4>, (const void*)k_solve_reg<8>,
-                      (const void*)k_solve_reg<16>, (const void*)k_solve_big};
+                      (const void*)k_solve_reg<16>, (const void*)k_solve_big<kBigWaves>,
+                      (const void*)k_solve_big<kNewtonWaves>};
   size_t mx = 0;
   for (const void* k : ks) {
     hipFuncAttributes a;

@@ -448,7 +448,7 @@ extern "C" void dd_options_default(dd_options* o) {
   o->max_sinkhorn_iter = 50000;
   o->safeguard = 1;
   o->accel = 1;
-  o->newton_after = 256;
+  o->newton_after = 384;
   o->precision = DD_PREC_SPLIT;
   o->inputs_on_device = 0;
   o->timing = 0;

@@ -194,7 +194,7 @@ class Problem:
 
     def __init__(self, mu, nu, schedule, s=4, n_levels=1, err_tol=1e-5, trunc=1e-15,
                  max_iter=50000, safeguard=1, stream=None, timing=False, accel=1,
-                 newton_after=256, precision=DD_PREC_SPLIT):
+                 newton_after=384, precision=DD_PREC_SPLIT):
         opt = Options()
         lib.dd_options_default(C.byref(opt))
         opt.err_tol, opt.trunc_threshold = err_tol, trunc
