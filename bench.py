@@ -23,12 +23,12 @@ PEAK_HBM_GBS = 8000.0  # MI355X HBM3E
 # 2.0 and WRITE by 1.0, the factors a plain 256 MiB device copy gives); the
 # summary is kept under profiles/.  Valid only for the kernel source the
 # counters were taken on, identified by its hash.
-TRAFFIC_KERNEL_SHA256 = "f8120dacf7c14e0e30c2b4fe06542fc732e6dc79d5b197c46852462ab5dccfb8"
+TRAFFIC_KERNEL_SHA256 = "9870f63ebf4542a5e34a8307061538d427fadaabee8debc440416f1180c674f3"
 TRAFFIC_BYTES_PER_LAUNCH = {
-    "solve_stream": (2.0 * 2321928 + 245481) * 1024,
-    "solve_reg_16w": (2.0 * 87530 + 280287) * 1024,
-    "solve_reg_8w": (2.0 * 7867 + 15270) * 1024,
-    "solve_reg_4w": (2.0 * 2881 + 5007) * 1024,
+    "solve_stream": (2.0 * 2332477 + 246443) * 1024,
+    "solve_reg_16w": (2.0 * 86479 + 279778) * 1024,
+    "solve_reg_8w": (2.0 * 7872 + 15283) * 1024,
+    "solve_reg_4w": (2.0 * 2902 + 5008) * 1024,
 }
 
 

@@ -179,17 +179,19 @@ def test_device_inputs_match_host_inputs(dd):
     assert np.array_equal(e1["val"], e2["val"]) and np.array_equal(e1["alpha_a"], e2["alpha_a"])
 
 
-@pytest.mark.parametrize("N,K", [(32, 4), (64, 2)])
-def test_newton_fallback_matches_oracle(dd, ddo, N, K):
-    # Newton steps after K loops: N=32 hands register-solver cells to the Newton
-    # kernel, N=64 (U = 4096) runs them inside the log-domain big-cell solver.
-    # Both sides stop on the same test at the same fixed point, but their
-    # Newton iterates differ (the GPU hands over the iterate of its FP32
-    # scaling loops), so the bar is the stopping tolerance rather than
-    # loop-for-loop agreement.
+@pytest.mark.parametrize("N,K,fp64", [(32, 4, False), (64, 2, False), (32, 4, True)])
+def test_newton_fallback_matches_oracle(dd, ddo, N, K, fp64):
+    # Newton steps after K loops: N=32 hands register-solver cells to the
+    # 16-wave Newton launch, N=64 (U = 4096) hands streamed-solver cells to it,
+    # and the FP64 instantiation runs them in place inside the 8-wave
+    # log-domain solver.  Both sides stop on the same test at the same fixed
+    # point, but their Newton iterates differ (the GPU hands over the iterate
+    # of its FP32 scaling loops), so the bar is the stopping tolerance rather
+    # than loop-for-loop agreement.
     mu, nu = datagen.small_pair(N, 3, seed=6)
     eps = 4.0 / N ** 2
-    g = dd.Problem(mu, nu, [(0, eps, 4)], s=4, n_levels=1, newton_after=K)
+    g = dd.Problem(mu, nu, [(0, eps, 4)], s=4, n_levels=1, newton_after=K,
+                   precision=dd.DD_PREC_FP64 if fp64 else dd.DD_PREC_SPLIT)
     o = ddo.Oracle(mu, nu, s=4, n_levels=1, eps=eps, newton_after=K)
     info = g.level_info()
     for ell in range(4 if N < 64 else 2):
