@@ -332,3 +332,51 @@ def test_split_precision_matches_fp64_instantiation_at_256(dd):
         assert r["n_failed"] == 0 and c["err_x"] <= 1e-5 and c["err_y"] <= 1e-5
     assert abs(c32["cost"] - c64["cost"]) <= 1e-5 * c64["cost"]
     assert np.abs(b32 - b64).sum() <= 1e-4
+
+
+def test_full_size_schedule_and_sampled_cells_match_oracle(dd, ddo):
+    # The 1024x1024 blob pair through its whole schedule (5 levels, 62
+    # half-iterations) in the launch configuration the tuned benchmark runs:
+    # properties that hold at any size on the whole result, then one more
+    # finest-level sweep of partition A compared cell by cell with the oracle,
+    # from the same state, on a random sample of 1024 cells.
+    import os
+    mu, nu, cfg = datagen.config3_pair()
+    H, W = mu.shape
+    s = cfg["s"]
+    g = dd.Problem(mu, nu, cfg["stages"], s=s, n_levels=cfg["n_levels"])
+    g.set_launch(solver_per_cu=8, newton_per_cu=1, stream_wgs=64, cells_per_wg=0)
+    rs = g.run_schedule()
+    c = g.cost()
+    assert rs["n_half_iters"] == 62 and rs["n_failed"] == 0
+    assert c["err_x"] <= 1e-5 and c["err_y"] <= 1e-5
+    e = _valid_state(g)
+    info = g.level_info()
+    nb = info["n_basic"]
+    assert info["H"] == H and info["W"] == W and nb == (H // s) * (W // s)
+    # basic-cell rows carry the mu mass of their block (balancing is exact;
+    # truncation only removes mass, all of it counted in the drift)
+    rows = np.repeat(np.arange(nb), np.diff(e["row_ptr"]))
+    rm = np.bincount(rows, weights=e["val"], minlength=nb)
+    blk = mu.reshape(H // s, s, W // s, s).sum(axis=(1, 3)).ravel()
+    assert np.abs(rm - blk).sum() <= 2 * c["mass_drift"] + 1e-12
+    # the Y-marginal recomputed from the exported entries meets the tolerance
+    colm = np.bincount(e["col"], weights=e["val"], minlength=H * W)
+    assert np.abs(colm - nu.ravel()).sum() <= 1e-5
+    o = ddo.Oracle(mu, nu, s=s, n_levels=cfg["n_levels"], eps=cfg["stages"][0][1],
+                   n_threads=min(16, os.cpu_count() or 1))
+    o.import_state(e["level"], e["eps"], e["row_ptr"], e["col"], e["val"], e["alpha_a"],
+                   e["alpha_b"])
+    n_cells = o.level_info()["n_cells_a"]
+    mask = np.zeros(n_cells, dtype=np.uint8)
+    mask[np.random.default_rng(1).permutation(n_cells)[:1024]] = 1
+    o.half_iterate(0, mask)
+    sg = g.half_iterate(0)
+    assert sg["n_failed"] == 0
+    rg, ro = g.cell_results(), o.cell_results(0)
+    m = mask.astype(bool)
+    assert np.all(np.abs(rg["cost"][m] - ro["cost"][m]) <= 2e-5 * np.abs(ro["cost"][m]) + 1e-18)
+    lg, lo = int(rg["loops"][m].sum()), int(ro["loops"][m].sum())
+    print("full size: cells", int(m.sum()), "loops gpu", lg, "oracle", lo, flush=True)
+    assert abs(lg - lo) <= 0.02 * lo + 16
+    g.close()
