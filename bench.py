@@ -165,16 +165,17 @@ def main():
             "traffic_unit": "HBM bytes per launch", "launches": launches,
             "avg_launch_ms": tot_ms[solver] / max(launches, 1),
             "flops_per_launch": flops / max(launches, 1)}
-    # the streamed solver keeps its cell's kernel tile in memory and reads it
-    # in both passes of every loop: as a memory-bound kernel its algorithmic
-    # traffic is 2 passes x 4 B per kernel entry, i.e. 2 bytes per counted flop
+    # the streamed solver keeps its cell's kernel tile (FP32) in memory and
+    # reads it once per loop, each entry serving both half-steps from
+    # registers: as a memory-bound kernel its algorithmic traffic is 4 B per
+    # kernel entry per loop, i.e. 1 byte per counted flop
     roof_mem = None
     if dd.KERNEL_NAMES[solver] == "solve_stream" and tot_ms[solver] > 0:
-        gbs = 2.0 * flops / (tot_ms[solver] / 1000) / 1e9
+        gbs = flops / (tot_ms[solver] / 1000) / 1e9
         roof_mem = {"kernel": "solve_stream", "bound": "hbm", "achieved": gbs,
                     "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": gbs / PEAK_HBM_GBS,
-                    "bytes_per_launch": 2.0 * flops / max(launches, 1),
-                    "note": "tile reads of both passes per loop (8 B per kernel entry)"}
+                    "bytes_per_launch": flops / max(launches, 1),
+                    "note": "one FP32 tile read per loop (4 B per kernel entry)"}
     kernel_ms = {dd.KERNEL_NAMES[k]: tot_ms[k] / args.steps for k in range(dd.N_KERNELS)}
 
     # CPU baseline: the FP64 oracle on a sample of cells of one more sweep
