@@ -44,6 +44,17 @@ def kernel_traffic(name, config):
     return TRAFFIC_BYTES_PER_LAUNCH[name]
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def progress(msg):
     """One line on stderr as each leg of the benchmark ends (the JSON result
     stays the only line on stdout)."""
@@ -213,6 +224,22 @@ def main():
                "kind": "oracle",
                "sample": f"{n} of {n_cells} partition-A cells of one more finest-level sweep "
                          f"of the same 1024x1024 solve, state taken from the GPU run"}
+        # the same oracle on one thread, on the first cells of the same sample
+        o1 = ddo.Oracle(mu, nu, s=cfg["s"], n_levels=cfg["n_levels"], eps=cfg["stages"][0][1],
+                        n_threads=1)
+        o1.import_state(e["level"], e["eps"], e["row_ptr"], e["col"], e["val"], e["alpha_a"],
+                        e["alpha_b"])
+        n1 = min(n, 256)
+        mask1 = np.zeros(n_cells, dtype=np.uint8)
+        mask1[order[:n1]] = 1
+        t = time.perf_counter()
+        o1.half_iterate(0, mask1)
+        dt1 = time.perf_counter() - t
+        o1.close()
+        cpu["single_thread"] = {"value": n1 / dt1, "cores": 1,
+                                "sample": f"the first {n1} cells of the same sample"}
+        cpu["nproc"] = os.cpu_count()
+        cpu["cpu_model"] = cpu_model()
         # the same sweep on the GPU, compared cell by cell on the sample
         g.half_iterate(0)
         rg = g.cell_results()
