@@ -32,10 +32,11 @@ TRAFFIC_BYTES_PER_LAUNCH = {
 }
 
 
-def kernel_traffic(name, config):
-    """Measured HBM bytes per launch, or None if not measured for this build."""
+def kernel_traffic(name, standard):
+    """Measured HBM bytes per launch on the 1024x1024 schedule, or None if not
+    measured for this build or for another workload."""
     import hashlib
-    if config != 3 or name not in TRAFFIC_BYTES_PER_LAUNCH:
+    if not standard or name not in TRAFFIC_BYTES_PER_LAUNCH:
         return None
     src = os.path.join(ROOT, "paper_2001_10986_amd", "csrc", "dd_kernels.hip")
     with open(src, "rb") as f:
@@ -67,6 +68,11 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", type=int, default=3, choices=[1, 2, 3])
+    ap.add_argument("--size", type=int, default=1024, choices=[256, 512, 1024, 2048],
+                    help="config 3: image side (2048 is the paper's largest)")
+    ap.add_argument("--final-eps-factor", type=float, default=1.0,
+                    help="config 3: final eps in units of the squared finest pixel spacing "
+                         "(the paper ends at 0.25)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the oracle leg (0 disables it)")
     ap.add_argument("--learned-pairs", type=int, default=24,
@@ -107,13 +113,19 @@ def main():
 
     torch.cuda.set_device(0)
     if args.config == 3:
-        mu, nu, cfg = datagen.config3_pair()
-        workload = ("1024x1024 Gaussian-blob image pair (16 blobs + U[0,0.1]*max noise), "
-                    "5 levels 64->1024, eps 1 -> (1/1024)^2, Err 1e-5, trunc 1e-15, s=4")
+        N, fe = args.size, args.final_eps_factor
+        mu, nu, cfg = datagen.config3_pair(N=N, final_factor=fe)
+        fin = f"(1/{N})^2" if fe == 1.0 else f"{fe:g}*(1/{N})^2"
+        workload = (f"{N}x{N} Gaussian-blob image pair (16 blobs + U[0,0.1]*max noise), "
+                    f"{cfg['n_levels']} levels 64->{N}, eps 1 -> {fin}, Err 1e-5, "
+                    "trunc 1e-15, s=4")
+        standard = N == 1024 and fe == 1.0
     elif args.config == 2:
+        standard = False
         mu, nu, cfg = datagen.config2_pair()
         workload = "256x256 Gaussian-blob image pair (8 blobs), 3 levels, eps 1 -> (1/256)^2"
     else:
+        standard = False
         mu, nu, cfg = datagen.config1_pair()
         workload = "32x32 Gaussian-blob pair (4 blobs), one level, eps 4/32^2, 40 half-iterations"
     mu_d = torch.from_numpy(mu).cuda()
@@ -172,7 +184,7 @@ def main():
     achieved = flops / (tot_ms[solver] / 1000) / 1e12 if tot_ms[solver] > 0 else 0.0
     roof = {"kernel": dd.KERNEL_NAMES[solver], "bound": "alu", "achieved": achieved,
             "peak": PEAK_FP32_FMA_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_FMA_TFLOPS,
-            "traffic": kernel_traffic(dd.KERNEL_NAMES[solver], args.config),
+            "traffic": kernel_traffic(dd.KERNEL_NAMES[solver], standard),
             "traffic_unit": "HBM bytes per launch", "launches": launches,
             "avg_launch_ms": tot_ms[solver] / max(launches, 1),
             "flops_per_launch": flops / max(launches, 1)}
@@ -223,7 +235,7 @@ def main():
         cpu = {"value": n / dt, "unit": "cell-Sinkhorn solves/s", "cores": cores,
                "kind": "oracle",
                "sample": f"{n} of {n_cells} partition-A cells of one more finest-level sweep "
-                         f"of the same 1024x1024 solve, state taken from the GPU run"}
+                         f"of the same {mu.shape[0]}x{mu.shape[1]} solve, state taken from the GPU run"}
         # the same oracle on one thread, on the first cells of the same sample
         o1 = ddo.Oracle(mu, nu, s=cfg["s"], n_levels=cfg["n_levels"], eps=cfg["stages"][0][1],
                         n_threads=1)

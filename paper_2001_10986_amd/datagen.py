@@ -79,11 +79,18 @@ def config2_pair(i=0, j=1):
     return mu, nu, dict(s=4, n_levels=3, stages=eps_schedule(256, 3))
 
 
-def config3_pair(seed0=3000):
-    """1024x1024 pair, 16 blobs + U[0,0.1]*max noise; 5 levels 64->1024, eps 1 -> (1/1024)^2."""
-    mu = blob_image(1024, 1024, 16, seed0, noise=0.1)
-    nu = blob_image(1024, 1024, 16, seed0 + 1, noise=0.1)
-    return mu, nu, dict(s=4, n_levels=5, stages=eps_schedule(1024, 5))
+def config3_pair(seed0=3000, N=1024, final_factor=1.0):
+    """NxN pair (default 1024), 16 blobs + U[0,0.1]*max noise; levels 64->N,
+    eps 1 -> final_factor*(1/N)^2.  N = 2048 with final_factor = 0.25 is the
+    paper's largest image size (summary table of the quantitative evaluation)
+    and its final eps of a quarter pixel spacing squared (Sec. 7.1)."""
+    if N < 64 or N & (N - 1):
+        raise ValueError("N must be a power of two >= 64")
+    nlev = int(np.log2(N // 64)) + 1
+    mu = blob_image(N, N, 16, seed0, noise=0.1)
+    nu = blob_image(N, N, 16, seed0 + 1, noise=0.1)
+    return mu, nu, dict(s=4, n_levels=nlev,
+                        stages=eps_schedule(N, nlev, final_eps=final_factor / N ** 2))
 
 
 def config4_pairs(n_pairs=64, sizes=(64, 128, 256, 512)):

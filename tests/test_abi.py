@@ -87,11 +87,11 @@ def test_bench_traffic_only_for_the_profiled_kernel_build(tmp_path):
     bench = importlib.util.module_from_spec(spec)
     spec.loader.exec_module(bench)
     # other workloads and unprofiled kernels report no traffic
-    assert bench.kernel_traffic("solve_reg_16w", 2) is None
-    assert bench.kernel_traffic("union", 3) is None
+    assert bench.kernel_traffic("solve_reg_16w", False) is None
+    assert bench.kernel_traffic("union", True) is None
     # a source that does not match the profiled hash reports none either
     bench.ROOT = str(tmp_path)
     src = tmp_path / "paper_2001_10986_amd" / "csrc"
     src.mkdir(parents=True)
     (src / "dd_kernels.hip").write_text("// changed\n")
-    assert bench.kernel_traffic("solve_reg_16w", 3) is None
+    assert bench.kernel_traffic("solve_reg_16w", True) is None
