@@ -73,6 +73,10 @@ def main():
     ap.add_argument("--final-eps-factor", type=float, default=1.0,
                     help="config 3: final eps in units of the squared finest pixel spacing "
                          "(the paper ends at 0.25)")
+    ap.add_argument("--newton-after", type=int, default=384,
+                    help="Sinkhorn loops before a slow cell switches to Newton steps (0: never)")
+    ap.add_argument("--max-iter", type=int, default=50000,
+                    help="Sinkhorn loop cap of a cell solve before the eps safeguard")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="budget of the oracle leg (0 disables it)")
     ap.add_argument("--learned-pairs", type=int, default=24,
@@ -136,6 +140,7 @@ def main():
 
     def step():
         g = dd.Problem(mu_d, nu_d, cfg["stages"], s=cfg["s"], n_levels=cfg["n_levels"],
+                       newton_after=args.newton_after, max_iter=args.max_iter,
                        timing=True)
         if launch is not None:
             g.set_launch(**launch)
@@ -210,6 +215,7 @@ def main():
         e = g.export()
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         o = ddo.Oracle(mu, nu, s=cfg["s"], n_levels=cfg["n_levels"], eps=cfg["stages"][0][1],
+                       newton_after=args.newton_after, max_iter=args.max_iter,
                        n_threads=cores)
         o.import_state(e["level"], e["eps"], e["row_ptr"], e["col"], e["val"], e["alpha_a"],
                        e["alpha_b"])
@@ -238,6 +244,7 @@ def main():
                          f"of the same {mu.shape[0]}x{mu.shape[1]} solve, state taken from the GPU run"}
         # the same oracle on one thread, on the first cells of the same sample
         o1 = ddo.Oracle(mu, nu, s=cfg["s"], n_levels=cfg["n_levels"], eps=cfg["stages"][0][1],
+                        newton_after=args.newton_after, max_iter=args.max_iter,
                         n_threads=1)
         o1.import_state(e["level"], e["eps"], e["row_ptr"], e["col"], e["val"], e["alpha_a"],
                         e["alpha_b"])
@@ -291,7 +298,8 @@ def main():
         del X, T, M, Xt, Tt, Mt
 
         def lstep():
-            gl = dd.Problem(mu_d, nu_d, cfg["stages"], s=cfg["s"], n_levels=cfg["n_levels"])
+            gl = dd.Problem(mu_d, nu_d, cfg["stages"], s=cfg["s"], n_levels=cfg["n_levels"],
+                            newton_after=args.newton_after, max_iter=args.max_iter)
             if launch is not None:
                 gl.set_launch(**launch)
             gl.set_warm_start(net, warmstart.POLICY, warmstart.MIN_RMS)
@@ -408,6 +416,7 @@ def main():
         "dtype": "f32 bulk / f64 bookkeeping",
         "data": "synthetic",
         "config": {"workload": workload, "half_iterations": rs["n_half_iters"],
+                   "newton_after": args.newton_after, "max_iter": args.max_iter,
                    "cell_solves": solves, "warm_start": "plain (previous potentials)"},
         "time_to_tol_s": ms_per_step / 1000,
         "tol_met": tol_met,
