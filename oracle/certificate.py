@@ -1,0 +1,134 @@
+"""FP64 primal-dual certificate of a domain-decomposition iterate (test
+infrastructure only: tests, the smoke check and the bench's CPU leg use it;
+the product path never does).
+
+Follows Sec. 6 "Estimating the primal-dual gap" and the relative PD gap of
+Sec. 7 (eq. RelPDGap), with the dual objective J of eq.
+EntropicOTDualObjective:
+
+    J(u, v) = int log u dmu + int log v dnu - int u (x) v dK + |K|,
+    K = exp(-c/eps) mu (x) nu.
+
+Potentials are carried in the additive form alpha = eps log u, beta = eps log v.
+
+Steps, in the paper's order:
+
+1. Edge weights of the A-cell graph.  Two A-cells J1, J2 are joined through
+   every B-cell J_B that meets both; the oriented weight is
+   q(J1, J2) = mean_{J1 n J_B} (u_A / u_B) dmu * mean_{J2 n J_B} (u_B / u_A) dmu.
+2. Discrete Helmholtz step: V on the A-cells minimising the squared misfit
+   between the graph gradient of V and log q over all oriented edges.
+   READING: the misfit is taken as V(J2) - V(J1) - log q(J1, J2), the
+   orientation under which the path product of the q's (the construction
+   the least-squares step replaces) glues consistent potentials; the printed
+   form has the two vertices the other way round, which would glue with
+   exp(-V).  V is fixed to mean zero (the minimiser is unique up to a
+   constant on a connected graph).
+3. Glued X-scaling u_hat = exp(V_J) u_{A,J} on each A-cell J.
+4. READING for the Y-side: instead of gluing the truncated v_J, v_hat is the
+   exact Y-iteration of u_hat (the maximiser of J over v for fixed u_hat,
+   Remark "Sinkhorn algorithm"), so J(u_hat, v_hat) >= J(u_hat, any glued v).
+   After it, int u_hat (x) v_hat dK = |nu| = 1.
+5. Relative PD gap (KL(pi|K) - J) / (KL(pi|K) - |K|); the primal score
+   KL(pi|K) - |K| of the DD plan is the sum of the composite-cell objectives
+   (Sec. 6: summed over the cells of the last half-iteration).
+
+Parity pinned by: weak and strong duality against the dense entropic optimum,
+exact recovery of a planted gradient by the Helmholtz step, and the gap of a
+converged DD iterate tending to zero (tests/test_certificate.py).
+"""
+import numpy as np
+from scipy.special import logsumexp
+
+
+def dual_objective(alpha, beta, C, mu, nu, eps):
+    """J(u, v) - |K| of eq. EntropicOTDualObjective written out densely
+    (u = exp(alpha/eps), v = exp(beta/eps), K = exp(-c/eps) mu nu)."""
+    alpha = np.asarray(alpha, dtype=np.float64)
+    beta = np.asarray(beta, dtype=np.float64)
+    mass = np.sum(np.exp((alpha[:, None] + beta[None, :] - C) / eps) * np.outer(mu, nu))
+    return float(np.dot(alpha, mu) / eps + np.dot(beta, nu) / eps - mass)
+
+
+def primal_score(plan, C, mu, nu, eps):
+    """KL(pi|K) - |K| = sum pi log(pi/K) - |pi| (Definition "Kullback-Leibler divergence")."""
+    P = np.asarray(plan, dtype=np.float64)
+    K = np.exp(-C / eps) * np.outer(mu, nu)
+    pos = P > 0
+    return float(np.sum(P[pos] * np.log(P[pos] / K[pos])) - P.sum())
+
+
+def graph_edges(alpha_a, alpha_b, mu, eps, basic, cells_a, cells_b):
+    """Oriented edges (J1, J2, log q(J1, J2)) of the A-cell graph (step 1).
+
+    basic: pixel index arrays of the basic cells; cells_a / cells_b: lists of
+    basic-cell ids of the composite cells.  The means are mu-weighted averages
+    over J1 n J_B and J2 n J_B, evaluated with a max shift for range."""
+    a_of_basic = {}
+    for J, cell in enumerate(cells_a):
+        for i in cell:
+            a_of_basic[i] = J
+    edges = []
+    for cell_b in cells_b:
+        pix_by_a = {}
+        for i in cell_b:
+            pix_by_a.setdefault(a_of_basic[i], []).append(basic[i])
+        parts = {J: np.concatenate(p) for J, p in pix_by_a.items()}
+        lmean_ab, lmean_ba = {}, {}
+        for J, xs in parts.items():
+            w = np.log(mu[xs]) - np.log(mu[xs].sum())
+            d = (alpha_a[xs] - alpha_b[xs]) / eps
+            lmean_ab[J] = logsumexp(d + w)
+            lmean_ba[J] = logsumexp(-d + w)
+        for J1 in parts:
+            for J2 in parts:
+                if J1 != J2:
+                    edges.append((J1, J2, lmean_ab[J1] + lmean_ba[J2]))
+    return edges
+
+
+def helmholtz(edges, n_cells):
+    """Mean-zero V minimising sum_e (V(J2) - V(J1) - log q_e)^2 (step 2)."""
+    if not edges:
+        return np.zeros(n_cells)
+    D = np.zeros((len(edges), n_cells))
+    w = np.empty(len(edges))
+    for e, (J1, J2, lq) in enumerate(edges):
+        D[e, J2] += 1.0
+        D[e, J1] -= 1.0
+        w[e] = lq
+    V = np.linalg.lstsq(D, w, rcond=None)[0]
+    return V - V.mean()
+
+
+def y_iteration(alpha, C, mu, eps, chunk=2048):
+    """beta(y) = -eps log sum_x exp((alpha(x) - c(x,y))/eps) mu(x) (step 4)."""
+    lmu = np.log(mu)
+    out = np.empty(C.shape[1])
+    for j0 in range(0, C.shape[1], chunk):
+        Cj = C[:, j0:j0 + chunk]
+        out[j0:j0 + chunk] = -eps * logsumexp((alpha[:, None] - Cj) / eps + lmu[:, None], axis=0)
+    return out
+
+
+def certificate(alpha_a, alpha_b, obj, C, mu, nu, eps, basic, cells_a, cells_b):
+    """Glued dual candidate and relative PD gap of a DD iterate (steps 1-5).
+
+    alpha_a, alpha_b: the stored X-potentials of the two partitions (per pixel,
+    any constant per composite cell); obj: eps * (KL(pi|K) - |K|) of the
+    primal iterate.  Returns a dict with V, the glued alpha_hat, beta_hat,
+    J - |K| and the relative gap."""
+    alpha_a = np.asarray(alpha_a, dtype=np.float64).ravel()
+    alpha_b = np.asarray(alpha_b, dtype=np.float64).ravel()
+    edges = graph_edges(alpha_a, alpha_b, mu, eps, basic, cells_a, cells_b)
+    V = helmholtz(edges, len(cells_a))
+    alpha_hat = alpha_a.copy()
+    for J, cell in enumerate(cells_a):
+        for i in cell:
+            alpha_hat[basic[i]] += eps * V[J]
+    beta_hat = y_iteration(alpha_hat, C, mu, eps)
+    dual = float(np.dot(alpha_hat, mu) / eps + np.dot(beta_hat, nu) / eps - nu.sum())
+    primal = obj / eps
+    return {"V": V, "alpha_hat": alpha_hat, "beta_hat": beta_hat, "dual": dual,
+            "primal": primal, "gap": primal - dual, "rel_gap": (primal - dual) / primal,
+            "n_edges": len(edges)}
