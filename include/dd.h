@@ -213,6 +213,40 @@ dd_status dd_export_plan(dd_ctx* ctx, dd_plan_view* view);
  * view->level; rows sorted, no duplicates); for resume and tests. */
 dd_status dd_import_state(dd_ctx* ctx, const dd_plan_view* view);
 
+/* Primal-dual certificate of the current iterate (Sec. 6, "Estimating the
+ * primal-dual gap"; relative gap of eq. RelPDGap in Sec. 7).
+ *  - primal = KL(pi|K) - |K| of the last half-iteration's cell plans
+ *    (the sum of their cell objectives divided by eps), K = exp(-c/eps) mu nu;
+ *  - the X-potentials of the two partitions are glued on the A-cell graph:
+ *    every pair of A-cells meeting one B-cell gives an edge in each
+ *    orientation with weight log q (mu-weighted means of u_A/u_B and u_B/u_A
+ *    over the two overlaps), V minimises sum (V(J2) - V(J1) - log q)^2 with
+ *    mean zero, alpha_hat = alpha_A + eps V on each A-cell;
+ *  - beta_hat is the exact Y-iteration of alpha_hat, summed over the stored
+ *    support of the plan (entries below the truncation threshold are left
+ *    out, as in the sweeps); then int u_hat v_hat dK = |nu| and
+ *    dual = J - |K| = (<alpha_hat, mu> + <beta_hat, nu>)/eps - |nu|;
+ *  - gap = primal - dual, rel_gap = gap / primal.
+ * alpha_hat and beta_hat: optional host buffers of H*W doubles (NULL to
+ * skip); beta_hat is NaN where no stored entry reaches a pixel (counted in
+ * n_uncovered; the dual is then not a valid bound).  Synchronises the
+ * context's stream.  DD_ESTATE if no half-iteration ran on this level.
+ * Allocates and frees device scratch (4 H*W doubles). */
+typedef struct {
+  double primal;
+  double dual;
+  double gap;
+  double rel_gap;
+  double sum_nu;
+  int64_t n_uncovered;
+  int n_edges;
+  int level;
+  double eps;
+} dd_cert_report;
+
+dd_status dd_certificate(dd_ctx* ctx, dd_cert_report* report, double* alpha_hat,
+                         double* beta_hat);
+
 /* Per-cell results of the last half-iteration (arrays of that partition's
  * cell count, cells numbered row-major; nullable): transport cost, objective,
  * X-marginal error, Sinkhorn loops, status (1 cap, 2 non-finite, 4 safeguard). */

@@ -101,22 +101,34 @@ def helmholtz(edges, n_cells):
     return V - V.mean()
 
 
-def y_iteration(alpha, C, mu, eps, chunk=2048):
-    """beta(y) = -eps log sum_x exp((alpha(x) - c(x,y))/eps) mu(x) (step 4)."""
+def y_iteration(alpha, C, mu, eps, chunk=2048, support=None):
+    """beta(y) = -eps log sum_x exp((alpha(x) - c(x,y))/eps) mu(x) (step 4);
+    with a boolean support matrix the sum runs over its True entries only
+    (the stored support of a truncated plan)."""
     lmu = np.log(mu)
     out = np.empty(C.shape[1])
     for j0 in range(0, C.shape[1], chunk):
-        Cj = C[:, j0:j0 + chunk]
-        out[j0:j0 + chunk] = -eps * logsumexp((alpha[:, None] - Cj) / eps + lmu[:, None], axis=0)
+        t = (alpha[:, None] - C[:, j0:j0 + chunk]) / eps + lmu[:, None]
+        if support is not None:
+            t = np.where(support[:, j0:j0 + chunk], t, -np.inf)
+        out[j0:j0 + chunk] = -eps * logsumexp(t, axis=0)
     return out
 
 
-def certificate(alpha_a, alpha_b, obj, C, mu, nu, eps, basic, cells_a, cells_b):
+def plan_support(row_ptr, col, basic, n_px):
+    """Boolean (x, y) mask of the pairs a basic-cell CSR stores: X_i x supp(nu_i)."""
+    S = np.zeros((n_px, n_px), dtype=bool)
+    for i, xs in enumerate(basic):
+        S[np.ix_(xs, col[row_ptr[i]:row_ptr[i + 1]])] = True
+    return S
+
+
+def certificate(alpha_a, alpha_b, obj, C, mu, nu, eps, basic, cells_a, cells_b, support=None):
     """Glued dual candidate and relative PD gap of a DD iterate (steps 1-5).
 
     alpha_a, alpha_b: the stored X-potentials of the two partitions (per pixel,
     any constant per composite cell); obj: eps * (KL(pi|K) - |K|) of the
-    primal iterate.  Returns a dict with V, the glued alpha_hat, beta_hat,
+    primal iterate; support: optional mask restricting the Y-iteration.  Returns a dict with V, the glued alpha_hat, beta_hat,
     J - |K| and the relative gap."""
     alpha_a = np.asarray(alpha_a, dtype=np.float64).ravel()
     alpha_b = np.asarray(alpha_b, dtype=np.float64).ravel()
@@ -126,7 +138,7 @@ def certificate(alpha_a, alpha_b, obj, C, mu, nu, eps, basic, cells_a, cells_b):
     for J, cell in enumerate(cells_a):
         for i in cell:
             alpha_hat[basic[i]] += eps * V[J]
-    beta_hat = y_iteration(alpha_hat, C, mu, eps)
+    beta_hat = y_iteration(alpha_hat, C, mu, eps, support=support)
     dual = float(np.dot(alpha_hat, mu) / eps + np.dot(beta_hat, nu) / eps - nu.sum())
     primal = obj / eps
     return {"V": V, "alpha_hat": alpha_hat, "beta_hat": beta_hat, "dual": dual,

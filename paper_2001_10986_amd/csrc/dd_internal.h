@@ -169,4 +169,13 @@ void launch_glue_ratios(const RefineParams& r, double* out, hipStream_t st);
 void launch_interp(const double* fglued_c, int Hc, int Wc, double* fa, double* fb, int Hf,
                    int Wf, hipStream_t st);
 
+// Primal-dual certificate: beta_hat(y) = exact Y-iteration of alpha_hat over
+// the stored support (-eps log sum_x exp((alpha_hat(x) - c(x,y))/eps) mu(x)),
+// sums[0..3] = (sum alpha_hat mu, sum beta_hat nu, sum nu, uncovered pixels).
+// scratch holds 2*H*W doubles; beta_hat H*W; sums 4.
+void launch_cert_y(const int64_t* row_off, const int* row_len, const int* col,
+                   const double* alpha_hat, const double* mu, const double* nu, int H, int W,
+                   int bw, int n_basic, double eps, double h, double* scratch, double* beta_hat,
+                   double* sums, hipStream_t st);
+
 }  // namespace ddk

@@ -1152,6 +1152,101 @@ extern "C" dd_status dd_cost(dd_ctx* c, dd_cost_report* r) {
   return DD_OK;
 }
 
+extern "C" dd_status dd_certificate(dd_ctx* c, dd_cert_report* r, double* alpha_hat,
+                                   double* beta_hat) {
+  if (!c || !r) return DD_EINVAL;
+  if (c->last_part < 0) return fail(c, DD_ESTATE, "no half-iteration on this level yet");
+  const Level& l = c->L[c->lev];
+  const int nb = c->nb;
+  const long long npx = (long long)l.H * l.W;
+  // 1. edge weights per basic cell (the same overlap means as the refinement's gluing)
+  ddk::RefineParams R{};
+  R.Hc = l.H;
+  R.Wc = l.W;
+  R.bwc = l.bw;
+  R.eps = c->eps;
+  R.mu_c = l.mu;
+  R.alpha_a_c = c->alpha[0];
+  R.alpha_b_c = c->alpha[1];
+  double *dq = nullptr, *dV = nullptr, *ah = nullptr, *bh = nullptr, *scr = nullptr,
+         *sums = nullptr;
+  const int na = c->cells[0].n;
+  auto release = [&]() {
+    hipFree(dq);
+    hipFree(dV);
+    hipFree(ah);
+    hipFree(bh);
+    hipFree(scr);
+    hipFree(sums);
+  };
+  if (dmalloc(&dq, 2 * (size_t)nb) || dmalloc(&dV, (size_t)na) || dmalloc(&ah, (size_t)npx) ||
+      dmalloc(&bh, (size_t)npx) || dmalloc(&scr, 2 * (size_t)npx) || dmalloc(&sums, 4)) {
+    release();
+    return fail(c, DD_ENOMEM, "certificate scratch");
+  }
+  ddk::launch_glue_ratios(R, dq, c->st);
+  std::vector<double> q(2 * (size_t)nb);
+  hipError_t e = hipMemcpyAsync(q.data(), dq, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost,
+                                c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  if (e != hipSuccess) {
+    release();
+    return fail(c, DD_EHIP, "certificate: %s", hipGetErrorString(e));
+  }
+  // 2. least-squares potential on the A-cells, both orientations of every edge
+  std::vector<int> cellA(nb, 0);
+  for (int k = 0; k < na; k++) {
+    const int4 t = c->cells[0].hq[k];
+    const int ids[4] = {t.x, t.y, t.z, t.w};
+    for (int a = 0; a < 4; a++)
+      if (ids[a] >= 0) cellA[ids[a]] = k;
+  }
+  std::vector<int> ea, eb;
+  std::vector<double> w;
+  for (int k = 0; k < c->cells[1].n; k++) {
+    const int4 t = c->cells[1].hq[k];
+    const int all[4] = {t.x, t.y, t.z, t.w};
+    for (int a = 0; a < 4; a++)
+      for (int b = 0; b < 4; b++)
+        if (a != b && all[a] >= 0 && all[b] >= 0) {
+          ea.push_back(cellA[all[a]]);
+          eb.push_back(cellA[all[b]]);
+          w.push_back(q[2 * all[a]] + q[2 * all[b] + 1]);
+        }
+  }
+  std::vector<double> V;
+  glue_solve(na, ea, eb, w, V);
+  // 3. glued potential; 4. Y-iteration over the stored support and the sums
+  e = hipMemcpyAsync(dV, V.data(), sizeof(double) * na, hipMemcpyHostToDevice, c->st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_glue_apply, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, c->st,
+                       c->alpha[0], dV, c->eps, l.H, l.W, ah);
+    ddk::launch_cert_y(c->row_off, c->row_len, c->col, ah, l.mu, l.nu, l.H, l.W, l.bw, nb,
+                       c->eps, l.h, scr, bh, sums, c->st);
+    e = hipGetLastError();
+  }
+  double hs[4] = {0, 0, 0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(hs, sums, sizeof hs, hipMemcpyDeviceToHost, c->st);
+  if (e == hipSuccess && alpha_hat)
+    e = hipMemcpyAsync(alpha_hat, ah, sizeof(double) * npx, hipMemcpyDeviceToHost, c->st);
+  if (e == hipSuccess && beta_hat)
+    e = hipMemcpyAsync(beta_hat, bh, sizeof(double) * npx, hipMemcpyDeviceToHost, c->st);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
+  release();
+  if (e != hipSuccess) return fail(c, DD_EHIP, "certificate: %s", hipGetErrorString(e));
+  memset(r, 0, sizeof(*r));
+  r->primal = c->last.obj / c->eps;
+  r->dual = (hs[0] + hs[1]) / c->eps - hs[2];
+  r->gap = r->primal - r->dual;
+  r->rel_gap = r->gap / r->primal;
+  r->sum_nu = hs[2];
+  r->n_uncovered = (int64_t)hs[3];
+  r->n_edges = (int)w.size();
+  r->level = c->lev;
+  r->eps = c->eps;
+  return DD_OK;
+}
+
 extern "C" dd_status dd_level_info(const dd_ctx* c, int* level, int* H, int* W, int* n_basic,
                                    int* na, int* nbb, double* eps) {
   if (!c) return DD_EINVAL;

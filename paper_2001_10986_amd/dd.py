@@ -26,7 +26,7 @@ EXPORTED = ["dd_options_default", "dd_init", "dd_half_iterate", "dd_set_eps", "d
             "dd_batch_half_iterate", "dd_batch_run_schedule", "dd_batch_schedule_step",
             "dd_batch_info", "dd_batch_free", "dd_set_launch", "dd_batch_set_launch",
             "dd_autotune", "dd_batch_autotune", "dd_get_launch",
-            "dd_batch_last_error"]
+            "dd_batch_last_error", "dd_certificate"]
 
 DD_BATCH_GRAPH = 1
 DD_PREC_SPLIT, DD_PREC_FP64 = 0, 1
@@ -94,6 +94,15 @@ class CostReport(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class CertReport(C.Structure):
+    _fields_ = [("primal", C.c_double), ("dual", C.c_double), ("gap", C.c_double),
+                ("rel_gap", C.c_double), ("sum_nu", C.c_double), ("n_uncovered", C.c_int64),
+                ("n_edges", C.c_int), ("level", C.c_int), ("eps", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class PlanView(C.Structure):
     _fields_ = [("level", C.c_int), ("H", C.c_int), ("W", C.c_int), ("eps", C.c_double),
                 ("n_basic", C.c_int64), ("nnz", C.c_int64), ("row_ptr", C.c_void_p),
@@ -124,6 +133,7 @@ def _load():
     lib.dd_refine.argtypes = [C.c_void_p]
     lib.dd_run_schedule.argtypes = [C.c_void_p, P(RunStats)]
     lib.dd_cost.argtypes = [C.c_void_p, P(CostReport)]
+    lib.dd_certificate.argtypes = [C.c_void_p, P(CertReport), C.c_void_p, C.c_void_p]
     lib.dd_export_plan.argtypes = [C.c_void_p, P(PlanView)]
     lib.dd_import_state.argtypes = [C.c_void_p, P(PlanView)]
     lib.dd_cell_results.argtypes = [C.c_void_p] + [C.c_void_p] * 5
@@ -269,6 +279,23 @@ class Problem:
         r = CostReport()
         self._chk(lib.dd_cost(self._h, C.byref(r)), "dd_cost")
         return r.as_dict()
+
+    def certificate(self, potentials=False):
+        """Primal-dual certificate of the current iterate (dd_certificate); with
+        potentials=True also the glued alpha_hat and beta_hat (H x W, FP64)."""
+        r = CertReport()
+        if not potentials:
+            self._chk(lib.dd_certificate(self._h, C.byref(r), None, None), "dd_certificate")
+            return r.as_dict()
+        info = self.level_info()
+        H, W = info["H"], info["W"]
+        a = np.empty(H * W, dtype=np.float64)
+        b = np.empty(H * W, dtype=np.float64)
+        self._chk(lib.dd_certificate(self._h, C.byref(r), a.ctypes.data, b.ctypes.data),
+                  "dd_certificate")
+        out = r.as_dict()
+        out["alpha_hat"], out["beta_hat"] = a.reshape(H, W), b.reshape(H, W)
+        return out
 
     def level_info(self):
         v = [C.c_int() for _ in range(6)]
