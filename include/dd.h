@@ -213,8 +213,8 @@ dd_status dd_export_plan(dd_ctx* ctx, dd_plan_view* view);
  * view->level; rows sorted, no duplicates); for resume and tests. */
 dd_status dd_import_state(dd_ctx* ctx, const dd_plan_view* view);
 
-/* Primal-dual certificate of the current iterate (Sec. 6, "Estimating the
- * primal-dual gap"; relative gap of eq. RelPDGap in Sec. 7).
+/* Primal-dual certificate of the current iterate (Sec. 6.3, "Estimating the
+ * primal-dual gap"; relative gap of eq. RelPDGap in Sec. 7.3).
  *  - primal = KL(pi|K) - |K| of the last half-iteration's cell plans
  *    (the sum of their cell objectives divided by eps), K = exp(-c/eps) mu nu;
  *  - the X-potentials of the two partitions are glued on the A-cell graph:

@@ -2,8 +2,8 @@
 infrastructure only: tests, the smoke check and the bench's CPU leg use it;
 the product path never does).
 
-Follows Sec. 6 "Estimating the primal-dual gap" and the relative PD gap of
-Sec. 7 (eq. RelPDGap), with the dual objective J of eq.
+Follows Sec. 6.3 "Estimating the primal-dual gap" and the relative PD gap of
+Sec. 7.3 (eq. RelPDGap), with the dual objective J of eq.
 EntropicOTDualObjective:
 
     J(u, v) = int log u dmu + int log v dnu - int u (x) v dK + |K|,
@@ -31,7 +31,7 @@ Steps, in the paper's order:
    After it, int u_hat (x) v_hat dK = |nu| = 1.
 5. Relative PD gap (KL(pi|K) - J) / (KL(pi|K) - |K|); the primal score
    KL(pi|K) - |K| of the DD plan is the sum of the composite-cell objectives
-   (Sec. 6: summed over the cells of the last half-iteration).
+   (Sec. 6.3: summed over the cells of the last half-iteration).
 
 Parity pinned by: weak and strong duality against the dense entropic optimum,
 exact recovery of a planted gradient by the Helmholtz step, and the gap of a

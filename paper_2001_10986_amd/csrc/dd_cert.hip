@@ -1,4 +1,4 @@
-// Kernels of the primal-dual certificate (Sec. 6, "Estimating the primal-dual
+// Kernels of the primal-dual certificate (Sec. 6.3, "Estimating the primal-dual
 // gap"): the exact Y-iteration of the glued X-potential over the support of
 // the stored plan, and the FP64 sums of the dual objective J
 // (eq. EntropicOTDualObjective).  Not part of a sweep; FP64 throughout.
