@@ -53,9 +53,9 @@ def dual_objective(alpha, beta, C, mu, nu, eps):
 def primal_score(plan, C, mu, nu, eps):
     """KL(pi|K) - |K| = sum pi log(pi/K) - |pi| (Definition "Kullback-Leibler divergence")."""
     P = np.asarray(plan, dtype=np.float64)
-    K = np.exp(-C / eps) * np.outer(mu, nu)
+    logK = -C / eps + np.log(mu)[:, None] + np.log(nu)[None, :]  # log form: K underflows at small eps
     pos = P > 0
-    return float(np.sum(P[pos] * np.log(P[pos] / K[pos])) - P.sum())
+    return float(np.sum(P[pos] * (np.log(P[pos]) - logK[pos])) - P.sum())
 
 
 def graph_edges(alpha_a, alpha_b, mu, eps, basic, cells_a, cells_b):
