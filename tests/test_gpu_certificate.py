@@ -10,19 +10,20 @@ from paper_2001_10986_amd import datagen
 pytestmark = pytest.mark.gpu
 
 
-def _gpu_state(N, n_half, seed=7):
+def _gpu_state(N, n_half, seed=7, precision=0):
     from paper_2001_10986_amd import dd
     mu, nu = datagen.small_pair(N, 4, seed=seed)
     eps = 4.0 / N ** 2
-    g = dd.Problem(mu, nu, [(0, eps, n_half)], s=4, n_levels=1)
+    g = dd.Problem(mu, nu, [(0, eps, n_half)], s=4, n_levels=1, precision=precision)
     for ell in range(n_half):
         g.half_iterate(ell % 2)
     return g, mu.ravel(), nu.ravel(), eps
 
 
-@pytest.mark.parametrize("N,n_half", [(32, 3), (32, 12), (48, 8)])
-def test_certificate_matches_oracle(N, n_half):
-    g, mu, nu, eps = _gpu_state(N, n_half)
+# precision 0: FP32 bulk with FP64 bookkeeping; 1: the FP64 instantiation
+@pytest.mark.parametrize("N,n_half,precision", [(32, 3, 0), (32, 12, 0), (48, 8, 0), (32, 12, 1)])
+def test_certificate_matches_oracle(N, n_half, precision):
+    g, mu, nu, eps = _gpu_state(N, n_half, precision=precision)
     r = g.certificate(potentials=True)
     e = g.export()
     obj = g.cost()["obj"]
