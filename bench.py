@@ -211,7 +211,8 @@ def main():
     tc = time.perf_counter()
     pd = g.certificate()
     pd = {"rel_gap": pd["rel_gap"], "primal": pd["primal"], "dual": pd["dual"],
-          "n_uncovered": pd["n_uncovered"], "seconds": time.perf_counter() - tc,
+          "n_uncovered": pd["n_uncovered"], "cg_iters": pd["cg_iters"],
+          "cg_rel_resid": pd["cg_rel_resid"], "seconds": time.perf_counter() - tc,
           "note": "relative PD gap (KL(pi|K)-J)/(KL(pi|K)-|K|) of the glued dual candidate"}
     progress(f"certificate: relative PD gap {pd['rel_gap']:.3e}")
 

@@ -221,7 +221,8 @@ dd_status dd_import_state(dd_ctx* ctx, const dd_plan_view* view);
  *    every pair of A-cells meeting one B-cell gives an edge in each
  *    orientation with weight log q (mu-weighted means of u_A/u_B and u_B/u_A
  *    over the two overlaps), V minimises sum (V(J2) - V(J1) - log q)^2 with
- *    mean zero, alpha_hat = alpha_A + eps V on each A-cell;
+ *    mean zero (conjugate gradients on the device, relative residual 1e-12
+ *    or at most 20 000 steps), alpha_hat = alpha_A + eps V on each A-cell;
  *  - beta_hat is the exact Y-iteration of alpha_hat, summed over the stored
  *    support of the plan (entries below the truncation threshold are left
  *    out, as in the sweeps); then int u_hat v_hat dK = |nu| and
@@ -231,7 +232,7 @@ dd_status dd_import_state(dd_ctx* ctx, const dd_plan_view* view);
  * skip); beta_hat is NaN where no stored entry reaches a pixel (counted in
  * n_uncovered; the dual is then not a valid bound).  Synchronises the
  * context's stream.  DD_ESTATE if no half-iteration ran on this level.
- * Allocates and frees device scratch (4 H*W doubles). */
+ * Allocates and frees device scratch (4 H*W doubles plus the A-cell graph). */
 typedef struct {
   double primal;
   double dual;
@@ -242,6 +243,8 @@ typedef struct {
   int n_edges;
   int level;
   double eps;
+  int cg_iters;            /* conjugate-gradient steps of the gluing solve */
+  double cg_rel_resid;     /* its final residual relative to the right-hand side */
 } dd_cert_report;
 
 dd_status dd_certificate(dd_ctx* ctx, dd_cert_report* report, double* alpha_hat,

@@ -106,7 +106,116 @@ __global__ void k_cert_sums(const double* alpha_hat, const double* mu, const dou
   if (threadIdx.x < 4) atomicAdd(&sums[threadIdx.x], red[threadIdx.x][0]);
 }
 
+// Right-hand side of the normal equations of the gluing least squares:
+// rhs(J) = sum of log q over the oriented edges ending at J minus the sum over
+// those starting at J; inc_e holds (edge << 1) | (J is the edge's head).
+__global__ void k_cert_rhs(const int* inc_ptr, const int* inc_e, const int* e_ia,
+                           const int* e_ib, const double* q, int na, double* rhs) {
+  const int J = blockIdx.x * blockDim.x + threadIdx.x;
+  if (J >= na) return;
+  double s = 0;
+  for (int k = inc_ptr[J]; k < inc_ptr[J + 1]; k++) {
+    const int e = inc_e[k] >> 1;
+    const double w = q[2 * e_ia[e]] + q[2 * e_ib[e] + 1];
+    s += (inc_e[k] & 1) ? w : -w;
+  }
+  rhs[J] = s;
+}
+
+constexpr int kCgThreads = 1024;
+
+__device__ double cg_reduce(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = kCgThreads / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double out = red[0];
+  __syncthreads();
+  return out;
+}
+
+// Conjugate gradients for L V = rhs in one workgroup, L the graph Laplacian
+// of the A-cell graph (deg on the diagonal, -w for each neighbour); L is
+// singular on constants and rhs sums to zero, so the iterates stay in the
+// complement; V is shifted to mean zero at the end.  Each thread owns the
+// rows J = tid + k*1024 of x, r and Ap; p is read across threads, through
+// agent-scope loads after a release fence and the barrier.  The loop ends
+// for all waves at the same step (every test reads workgroup-reduced values).
+__global__ __launch_bounds__(kCgThreads) void k_cert_cg(
+    const int* adj_ptr, const int* adj_idx, const double* adj_w, const double* deg,
+    const double* b, int na, int max_it, double tol2, double* x, double* r, double* p,
+    double* Ap, double* info) {
+  __shared__ double red[kCgThreads];
+  const int tid = threadIdx.x;
+  double loc = 0;
+  for (int J = tid; J < na; J += kCgThreads) {
+    x[J] = 0;
+    r[J] = b[J];
+    p[J] = b[J];
+    loc += b[J] * b[J];
+  }
+  double rr = cg_reduce(loc, red);
+  const double bb = rr;
+  __threadfence();
+  __syncthreads();
+  __threadfence();
+  int it = 0;
+  while (it < max_it && rr > tol2 * bb && rr > 0) {
+    loc = 0;
+    for (int J = tid; J < na; J += kCgThreads) {
+      double v = deg[J] * p[J];
+      for (int k = adj_ptr[J]; k < adj_ptr[J + 1]; k++)
+        v -= adj_w[k] * __hip_atomic_load(&p[adj_idx[k]], __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+      Ap[J] = v;
+      loc += p[J] * v;
+    }
+    const double pAp = cg_reduce(loc, red);
+    if (!(pAp > 0)) break;
+    const double a = rr / pAp;
+    loc = 0;
+    for (int J = tid; J < na; J += kCgThreads) {
+      x[J] += a * p[J];
+      r[J] -= a * Ap[J];
+      loc += r[J] * r[J];
+    }
+    const double rr2 = cg_reduce(loc, red);
+    const double beta = rr2 / rr;
+    rr = rr2;
+    for (int J = tid; J < na; J += kCgThreads) p[J] = r[J] + beta * p[J];
+    __threadfence();
+    __syncthreads();
+    __threadfence();
+    it++;
+  }
+  loc = 0;
+  for (int J = tid; J < na; J += kCgThreads) loc += x[J];
+  const double mean = cg_reduce(loc, red) / (na > 0 ? na : 1);
+  for (int J = tid; J < na; J += kCgThreads) x[J] -= mean;
+  if (tid == 0) {
+    info[0] = it;
+    info[1] = rr;
+    info[2] = bb;
+  }
+}
+
 }  // namespace
+
+void launch_cert_glue(const int* inc_ptr, const int* inc_e, const int* e_ia, const int* e_ib,
+                      const double* q, const int* adj_ptr, const int* adj_idx,
+                      const double* adj_w, const double* deg, int na, int max_it, double tol2,
+                      double* work, double* V, double* info, hipStream_t st) {
+  double* rhs = work;
+  double* r = work + na;
+  double* p = work + 2 * (size_t)na;
+  double* Ap = work + 3 * (size_t)na;
+  hipLaunchKernelGGL(k_cert_rhs, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, st, inc_ptr,
+                     inc_e, e_ia, e_ib, q, na, rhs);
+  hipLaunchKernelGGL(k_cert_cg, dim3(1), dim3(kCgThreads), 0, st, adj_ptr, adj_idx, adj_w, deg,
+                     rhs, na, max_it, tol2, V, r, p, Ap, info);
+}
 
 void launch_cert_y(const int64_t* row_off, const int* row_len, const int* col,
                    const double* alpha_hat, const double* mu, const double* nu, int H, int W,

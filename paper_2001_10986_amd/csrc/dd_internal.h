@@ -173,6 +173,16 @@ void launch_interp(const double* fglued_c, int Hc, int Wc, double* fa, double* f
 // the stored support (-eps log sum_x exp((alpha_hat(x) - c(x,y))/eps) mu(x)),
 // sums[0..3] = (sum alpha_hat mu, sum beta_hat nu, sum nu, uncovered pixels).
 // scratch holds 2*H*W doubles; beta_hat H*W; sums 4.
+// Gluing potential of the certificate on the device: right-hand side from the
+// per-basic-cell overlap means q and the oriented edges (e_ia -> e_ib, basic
+// cell ids; inc_* the edges incident to each A-cell, (edge << 1) | head), then
+// conjugate gradients on the A-cell Laplacian (adj_* neighbours with edge
+// counts, deg the diagonal) in one workgroup, mean zero.  work holds 4*na
+// doubles; info[0..2] = (iterations, final r.r, initial r.r).
+void launch_cert_glue(const int* inc_ptr, const int* inc_e, const int* e_ia, const int* e_ib,
+                      const double* q, const int* adj_ptr, const int* adj_idx,
+                      const double* adj_w, const double* deg, int na, int max_it, double tol2,
+                      double* work, double* V, double* info, hipStream_t st);
 void launch_cert_y(const int64_t* row_off, const int* row_len, const int* col,
                    const double* alpha_hat, const double* mu, const double* nu, int H, int W,
                    int bw, int n_basic, double eps, double h, double* scratch, double* beta_hat,

@@ -1159,7 +1159,60 @@ extern "C" dd_status dd_certificate(dd_ctx* c, dd_cert_report* r, double* alpha_
   const Level& l = c->L[c->lev];
   const int nb = c->nb;
   const long long npx = (long long)l.H * l.W;
-  // 1. edge weights per basic cell (the same overlap means as the refinement's gluing)
+  const int na = c->cells[0].n;
+  // geometry of the A-cell graph (host bookkeeping, no data): every ordered
+  // pair of basic cells in one B-cell is an oriented edge between their A-cells
+  std::vector<int> cellA(nb, 0);
+  for (int k = 0; k < na; k++) {
+    const int4 t = c->cells[0].hq[k];
+    const int ids[4] = {t.x, t.y, t.z, t.w};
+    for (int a = 0; a < 4; a++)
+      if (ids[a] >= 0) cellA[ids[a]] = k;
+  }
+  std::vector<int> e_ia, e_ib;
+  for (int k = 0; k < c->cells[1].n; k++) {
+    const int4 t = c->cells[1].hq[k];
+    const int all[4] = {t.x, t.y, t.z, t.w};
+    for (int a = 0; a < 4; a++)
+      for (int b = 0; b < 4; b++)
+        if (a != b && all[a] >= 0 && all[b] >= 0) {
+          e_ia.push_back(all[a]);
+          e_ib.push_back(all[b]);
+        }
+  }
+  const int ne = (int)e_ia.size();
+  std::vector<int> inc_ptr(na + 1, 0), inc_e(2 * (size_t)ne);
+  for (int e = 0; e < ne; e++) {
+    inc_ptr[cellA[e_ia[e]] + 1]++;
+    inc_ptr[cellA[e_ib[e]] + 1]++;
+  }
+  for (int J = 0; J < na; J++) inc_ptr[J + 1] += inc_ptr[J];
+  std::vector<std::vector<std::pair<int, int>>> nbr(na);
+  {
+    std::vector<int> fill(inc_ptr.begin(), inc_ptr.end() - 1);
+    for (int e = 0; e < ne; e++) {
+      const int Ja = cellA[e_ia[e]], Jb = cellA[e_ib[e]];
+      inc_e[fill[Ja]++] = e << 1;
+      inc_e[fill[Jb]++] = (e << 1) | 1;
+      nbr[Ja].push_back({Jb, 1});
+      nbr[Jb].push_back({Ja, 1});
+    }
+  }
+  std::vector<int> adj_ptr(na + 1, 0), adj_idx;
+  std::vector<double> adj_w, deg(na, 0.0);
+  for (int J = 0; J < na; J++) {
+    auto& v = nbr[J];
+    std::sort(v.begin(), v.end());
+    for (size_t k = 0; k < v.size();) {
+      size_t m = k;
+      while (m < v.size() && v[m].first == v[k].first) m++;
+      adj_idx.push_back(v[k].first);
+      adj_w.push_back((double)(m - k));
+      deg[J] += (double)(m - k);
+      k = m;
+    }
+    adj_ptr[J + 1] = (int)adj_idx.size();
+  }
   ddk::RefineParams R{};
   R.Hc = l.H;
   R.Wc = l.W;
@@ -1169,8 +1222,9 @@ extern "C" dd_status dd_certificate(dd_ctx* c, dd_cert_report* r, double* alpha_
   R.alpha_a_c = c->alpha[0];
   R.alpha_b_c = c->alpha[1];
   double *dq = nullptr, *dV = nullptr, *ah = nullptr, *bh = nullptr, *scr = nullptr,
-         *sums = nullptr;
-  const int na = c->cells[0].n;
+         *sums = nullptr, *work = nullptr, *d_adjw = nullptr, *d_deg = nullptr;
+  int *d_ia = nullptr, *d_ib = nullptr, *d_incp = nullptr, *d_ince = nullptr, *d_adjp = nullptr,
+      *d_adji = nullptr;
   auto release = [&]() {
     hipFree(dq);
     hipFree(dV);
@@ -1178,54 +1232,52 @@ extern "C" dd_status dd_certificate(dd_ctx* c, dd_cert_report* r, double* alpha_
     hipFree(bh);
     hipFree(scr);
     hipFree(sums);
+    hipFree(work);
+    hipFree(d_adjw);
+    hipFree(d_deg);
+    hipFree(d_ia);
+    hipFree(d_ib);
+    hipFree(d_incp);
+    hipFree(d_ince);
+    hipFree(d_adjp);
+    hipFree(d_adji);
   };
+  const size_t nadj = adj_idx.size();
   if (dmalloc(&dq, 2 * (size_t)nb) || dmalloc(&dV, (size_t)na) || dmalloc(&ah, (size_t)npx) ||
-      dmalloc(&bh, (size_t)npx) || dmalloc(&scr, 2 * (size_t)npx) || dmalloc(&sums, 4)) {
+      dmalloc(&bh, (size_t)npx) || dmalloc(&scr, 2 * (size_t)npx) || dmalloc(&sums, 8) ||
+      dmalloc(&work, 4 * (size_t)na) || dmalloc(&d_adjw, nadj) || dmalloc(&d_deg, (size_t)na) ||
+      dmalloc(&d_ia, (size_t)ne) || dmalloc(&d_ib, (size_t)ne) ||
+      dmalloc(&d_incp, (size_t)na + 1) || dmalloc(&d_ince, 2 * (size_t)ne) ||
+      dmalloc(&d_adjp, (size_t)na + 1) || dmalloc(&d_adji, nadj)) {
     release();
     return fail(c, DD_ENOMEM, "certificate scratch");
   }
-  ddk::launch_glue_ratios(R, dq, c->st);
-  std::vector<double> q(2 * (size_t)nb);
-  hipError_t e = hipMemcpyAsync(q.data(), dq, sizeof(double) * 2 * nb, hipMemcpyDeviceToHost,
-                                c->st);
-  if (e == hipSuccess) e = hipStreamSynchronize(c->st);
-  if (e != hipSuccess) {
-    release();
-    return fail(c, DD_EHIP, "certificate: %s", hipGetErrorString(e));
-  }
-  // 2. least-squares potential on the A-cells, both orientations of every edge
-  std::vector<int> cellA(nb, 0);
-  for (int k = 0; k < na; k++) {
-    const int4 t = c->cells[0].hq[k];
-    const int ids[4] = {t.x, t.y, t.z, t.w};
-    for (int a = 0; a < 4; a++)
-      if (ids[a] >= 0) cellA[ids[a]] = k;
-  }
-  std::vector<int> ea, eb;
-  std::vector<double> w;
-  for (int k = 0; k < c->cells[1].n; k++) {
-    const int4 t = c->cells[1].hq[k];
-    const int all[4] = {t.x, t.y, t.z, t.w};
-    for (int a = 0; a < 4; a++)
-      for (int b = 0; b < 4; b++)
-        if (a != b && all[a] >= 0 && all[b] >= 0) {
-          ea.push_back(cellA[all[a]]);
-          eb.push_back(cellA[all[b]]);
-          w.push_back(q[2 * all[a]] + q[2 * all[b] + 1]);
-        }
-  }
-  std::vector<double> V;
-  glue_solve(na, ea, eb, w, V);
-  // 3. glued potential; 4. Y-iteration over the stored support and the sums
-  e = hipMemcpyAsync(dV, V.data(), sizeof(double) * na, hipMemcpyHostToDevice, c->st);
+  hipError_t e = hipSuccess;
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    if (e == hipSuccess && bytes > 0)
+      e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->st);
+  };
+  up(d_ia, e_ia.data(), sizeof(int) * ne);
+  up(d_ib, e_ib.data(), sizeof(int) * ne);
+  up(d_incp, inc_ptr.data(), sizeof(int) * (na + 1));
+  up(d_ince, inc_e.data(), sizeof(int) * 2 * (size_t)ne);
+  up(d_adjp, adj_ptr.data(), sizeof(int) * (na + 1));
+  up(d_adji, adj_idx.data(), sizeof(int) * nadj);
+  up(d_adjw, adj_w.data(), sizeof(double) * nadj);
+  up(d_deg, deg.data(), sizeof(double) * na);
+  double hs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (e == hipSuccess) {
+    // 1. overlap means per basic cell; 2. least-squares potential V on the device
+    ddk::launch_glue_ratios(R, dq, c->st);
+    ddk::launch_cert_glue(d_incp, d_ince, d_ia, d_ib, dq, d_adjp, d_adji, d_adjw, d_deg, na,
+                          std::min(20 * na + 100, 20000), 1e-24, work, dV, sums + 4, c->st);
+    // 3. glued potential; 4. Y-iteration over the stored support and the sums
     hipLaunchKernelGGL(k_glue_apply, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, c->st,
                        c->alpha[0], dV, c->eps, l.H, l.W, ah);
     ddk::launch_cert_y(c->row_off, c->row_len, c->col, ah, l.mu, l.nu, l.H, l.W, l.bw, nb,
                        c->eps, l.h, scr, bh, sums, c->st);
     e = hipGetLastError();
   }
-  double hs[4] = {0, 0, 0, 0};
   if (e == hipSuccess) e = hipMemcpyAsync(hs, sums, sizeof hs, hipMemcpyDeviceToHost, c->st);
   if (e == hipSuccess && alpha_hat)
     e = hipMemcpyAsync(alpha_hat, ah, sizeof(double) * npx, hipMemcpyDeviceToHost, c->st);
@@ -1241,9 +1293,11 @@ extern "C" dd_status dd_certificate(dd_ctx* c, dd_cert_report* r, double* alpha_
   r->rel_gap = r->gap / r->primal;
   r->sum_nu = hs[2];
   r->n_uncovered = (int64_t)hs[3];
-  r->n_edges = (int)w.size();
+  r->n_edges = ne;
   r->level = c->lev;
   r->eps = c->eps;
+  r->cg_iters = (int)hs[4];
+  r->cg_rel_resid = hs[6] > 0 ? std::sqrt(hs[5] / hs[6]) : 0.0;
   return DD_OK;
 }
 

@@ -97,7 +97,8 @@ class CostReport(C.Structure):
 class CertReport(C.Structure):
     _fields_ = [("primal", C.c_double), ("dual", C.c_double), ("gap", C.c_double),
                 ("rel_gap", C.c_double), ("sum_nu", C.c_double), ("n_uncovered", C.c_int64),
-                ("n_edges", C.c_int), ("level", C.c_int), ("eps", C.c_double)]
+                ("n_edges", C.c_int), ("level", C.c_int), ("eps", C.c_double),
+                ("cg_iters", C.c_int), ("cg_rel_resid", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
