@@ -195,14 +195,22 @@ dd_status dd_set_eps(dd_ctx* ctx, double eps);
 
 /* Coarse-to-fine step (Sec. 6.4): the basic marginals of the next level by
  * eq. (FineBasicMarginals); the potentials of partition A are glued with the
- * help of those of B (least squares of Sec. 6.3), bilinearly interpolated to
- * the fine pixels and used for both partitions.  DD_ESTATE on the finest level. */
+ * help of those of B (the least squares of Sec. 6.3 on the A-cell graph with
+ * both orientations of every edge, solved on the device as in
+ * dd_certificate), bilinearly interpolated to the fine pixels and used for
+ * both partitions.  Allocates and frees device scratch.  DD_ESTATE on the
+ * finest level. */
 dd_status dd_refine(dd_ctx* ctx);
 
 /* Run the whole schedule given at dd_init from the current state. */
 dd_status dd_run_schedule(dd_ctx* ctx, dd_run_stats* stats);
 
-/* FP64 diagnostics of the current state and of the last half-iteration. */
+/* FP64 diagnostics (Sec. 7.3 "Solution quality": the transport cost, the
+ * L1 marginal errors of X and Y, the sparsity of the basic marginals).
+ * err_y, mass_drift and nnz describe the current state; cost, obj and err_x
+ * the cell plans of the last half-iteration on this level (the primal
+ * iterate of Sec. 6.3), and eps is the eps that half-iteration ran with (the
+ * current eps if none ran yet).  Synchronises the context's stream. */
 dd_status dd_cost(dd_ctx* ctx, dd_cost_report* report);
 
 /* Export the state (Algorithm 2 outputs) into caller buffers; fills the
@@ -231,7 +239,11 @@ dd_status dd_import_state(dd_ctx* ctx, const dd_plan_view* view);
  * alpha_hat and beta_hat: optional host buffers of H*W doubles (NULL to
  * skip); beta_hat is NaN where no stored entry reaches a pixel (counted in
  * n_uncovered; the dual is then not a valid bound).  Synchronises the
- * context's stream.  DD_ESTATE if no half-iteration ran on this level.
+ * context's stream.  DD_ESTATE if no half-iteration ran on this level or eps
+ * changed after the last one (the primal score belongs to that eps).
+ * DD_ENOTCONV (a warning; the report is filled) if the CG solve stopped at
+ * its step cap above the residual bound: V is then not the least-squares
+ * solution and the dual bounds a less good candidate.
  * Allocates and frees device scratch (4 H*W doubles plus the A-cell graph). */
 typedef struct {
   double primal;

@@ -55,7 +55,7 @@ void* dd_mlp_get_stream(const dd_mlp* net);
 /* ---- use with a domain-decomposition context (include/dd.h) ----
  *
  * Cell features (768 per cell, the network's input): [0,64) 64 mu_J/|mu_J|
- * on the cell's 8x8 pixel block; [64,640) 256 nu_J/|nu_J| on a 24x24 pixel
+ * on the cell's 8x8 pixel block; [64,640) 576 nu_J/|nu_J| on a 24x24 pixel
  * window around the block moved by the cell's integer shift
  * d_J = round(mean_nu - mean_mu); [640] log(h^2/eps); [641] the nu_J mass
  * outside the window (fraction); [642,644) d_J / 8; [644,708) the potential

@@ -1044,13 +1044,17 @@ int ddo_refine(ddo_ctx* c) {
   int *cellA = malloc(sizeof(int) * c->nb);
   for (int k = 0; k < na; k++)
     for (int q = 0; q < c->cells[0][k].nq; q++) cellA[c->cells[0][k].q[q]] = k;
-  int ne = 0, cap = 6 * c->nc[1] + 8;
+  int ne = 0, cap = 12 * c->nc[1] + 8;
   int *ea = malloc(sizeof(int) * cap), *eb = malloc(sizeof(int) * cap);
   double* w = malloc(sizeof(double) * cap);
+  /* every ordered pair of basic cells of one B-cell gives an oriented edge
+   * between their A-cells: the weight depends on the orientation, and the
+   * least squares takes both (the same graph as the certificate, Sec. 6.3) */
   for (int k = 0; k < c->nc[1]; k++) {
     const cell_t* C = &c->cells[1][k];
     for (int q1 = 0; q1 < C->nq; q1++)
-      for (int q2 = q1 + 1; q2 < C->nq; q2++) {
+      for (int q2 = 0; q2 < C->nq; q2++) {
+        if (q2 == q1) continue;
         int b1 = C->q[q1], b2 = C->q[q2];
         /* log q(J1,J2) = log fint_{b1} u_A/u_B + log fint_{b2} u_B/u_A */
         double lq = log_mean_ratio(cl, s, b1, c->aA, c->aB, eps, 1.0) +

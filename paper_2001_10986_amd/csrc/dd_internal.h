@@ -10,8 +10,8 @@ constexpr int kS = 4;          // basic cell edge in pixels (the only supported 
 constexpr int kCellPx = 64;    // a composite cell is a virtual 8x8 pixel block
 constexpr int kNRegBins = 5;   // register-resident solver bins: 1,2,4,8,16 waves
 constexpr int kRegMaxU = 1024; // largest Y-support kept in registers (16 waves x 64)
-constexpr int kStreamSlabs = 8;                // streamed solver: slabs of 1024 support points
-constexpr int kStreamMaxU = kStreamSlabs * 1024;
+constexpr int kStreamSlabs = 8;                // streamed solver: unions of up to 8 x 1024 points
+constexpr int kStreamMaxU = kStreamSlabs * 1024;  // (processed in slabs of 512, dd_kernels.hip)
 constexpr size_t kStreamTileFloats = (size_t)kStreamMaxU * 64;  // tile buffer per workgroup
 constexpr int kNBins = kNRegBins + 2;          // + streamed solver + log-domain solver
 constexpr int kFeatIn = 768;                   // warm-start network input width

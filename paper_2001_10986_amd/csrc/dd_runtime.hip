@@ -270,6 +270,9 @@ struct dd_ctx {
   double* px_scratch = nullptr;
   int64_t px_cap = 0;
   dd_iter_stats last{};
+  double last_eps = 0;  // eps of the half-iteration whose results `last` holds
+  int refine_glue_iters = 0;       // CG steps of the last refinement's gluing solve
+  double refine_glue_resid = 0;    // and its final relative residual
   static_assert(DD_N_KERNELS == ddk::kNKernels, "kernel count of the ABI and the launcher");
   Runner run;  // this context's own sweeps
   // warm start by the network
@@ -874,6 +877,7 @@ static dd_status sweep_finish(dd_ctx* c, int part, const IterStatsDev& d, float 
     }
   c->nnz = d.nnz;
   c->last = r;
+  c->last_eps = c->eps;
   c->last_part = part;
   if (out) *out = r;
   return d.n_failed > 0 ? DD_ENOTCONV : DD_OK;
@@ -921,49 +925,136 @@ extern "C" dd_status dd_half_iterate(dd_ctx* c, int part, dd_iter_stats* out) {
   return sweep_finish(c, part, r.hstats[0], ms, kev ? mk : nullptr, out);
 }
 
-// Least-squares gluing potential on the cells of partition A (Sec. 6.3):
-// min sum_e (V[b_e] - V[a_e] - w_e)^2 by conjugate gradients, mean zero.
-// The sign follows the path-product form of the glued scalings,
-// V(J2) - V(J1) ~ log q(J1,J2).
-static void glue_solve(int n, const std::vector<int>& ea, const std::vector<int>& eb,
-                       const std::vector<double>& w, std::vector<double>& V) {
-  std::vector<double> rhs(n, 0.0), r(n), p(n), Ap(n);
-  V.assign(n, 0.0);
-  const size_t ne = w.size();
-  for (size_t e = 0; e < ne; e++) {
-    rhs[eb[e]] += w[e];
-    rhs[ea[e]] -= w[e];
+// Gluing potential V on the cells of partition A of the current level
+// (Sec. 6.3), solved on the device.  The graph: every ordered pair of basic
+// cells of one B-cell is an oriented edge between their A-cells (the weight
+// depends on the orientation, so both are taken).  Weights: log q(J1,J2) =
+// log of the mu-mean of u_A/u_B over the first basic cell plus that of
+// u_B/u_A over the second (one kernel, per basic cell).  V minimises
+// sum_e (V(J2) - V(J1) - log q_e)^2 with mean zero: the sign follows the
+// path-product form of the glued scalings, V(J2) - V(J1) ~ log q(J1,J2).
+// The normal equations (graph Laplacian with edge counts as weights) are
+// solved by conjugate gradients in one workgroup.  The host assembles only
+// the geometry of the graph.
+namespace {
+struct GlueScratch {
+  double *dq = nullptr, *work = nullptr, *adjw = nullptr, *deg = nullptr;
+  int *ia = nullptr, *ib = nullptr, *incp = nullptr, *ince = nullptr, *adjp = nullptr,
+      *adji = nullptr;
+  int na = 0, ne = 0, max_it = 0;
+  ~GlueScratch() {
+    hipFree(dq);
+    hipFree(work);
+    hipFree(adjw);
+    hipFree(deg);
+    hipFree(ia);
+    hipFree(ib);
+    hipFree(incp);
+    hipFree(ince);
+    hipFree(adjp);
+    hipFree(adji);
   }
-  r = rhs;
-  p = rhs;
-  double rr = 0;
-  for (int i = 0; i < n; i++) rr += r[i] * r[i];
-  const double bb = rr;
-  for (int it = 0; it < 20 * n + 100 && rr > 1e-28 * bb && rr > 0; it++) {
-    std::fill(Ap.begin(), Ap.end(), 0.0);
-    for (size_t e = 0; e < ne; e++) {
-      const double d = p[eb[e]] - p[ea[e]];
-      Ap[eb[e]] += d;
-      Ap[ea[e]] -= d;
-    }
-    double pAp = 0;
-    for (int i = 0; i < n; i++) pAp += p[i] * Ap[i];
-    if (!(pAp > 0)) break;
-    const double a = rr / pAp;
-    double rr2 = 0;
-    for (int i = 0; i < n; i++) {
-      V[i] += a * p[i];
-      r[i] -= a * Ap[i];
-      rr2 += r[i] * r[i];
-    }
-    const double beta = rr2 / rr;
-    rr = rr2;
-    for (int i = 0; i < n; i++) p[i] = r[i] + beta * p[i];
+};
+}  // namespace
+
+constexpr double kGlueTol2 = 1e-24;  // squared relative residual of the CG solve
+constexpr int kGlueMaxIt = 20000;
+
+// Enqueue the solve on c->st: dV (na doubles) receives V, info[0..2] the CG
+// steps and the final and initial squared residual norms.
+static dd_status enqueue_glue(dd_ctx* c, GlueScratch& g, double* dV, double* info) {
+  const Level& l = c->L[c->lev];
+  const int nb = c->nb;
+  const int na = c->cells[0].n;
+  std::vector<int> cellA(nb, 0);
+  for (int k = 0; k < na; k++) {
+    const int4 t = c->cells[0].hq[k];
+    const int ids[4] = {t.x, t.y, t.z, t.w};
+    for (int a = 0; a < 4; a++)
+      if (ids[a] >= 0) cellA[ids[a]] = k;
   }
-  double mean = 0;
-  for (int i = 0; i < n; i++) mean += V[i];
-  mean /= n;
-  for (int i = 0; i < n; i++) V[i] -= mean;
+  std::vector<int> e_ia, e_ib;
+  for (int k = 0; k < c->cells[1].n; k++) {
+    const int4 t = c->cells[1].hq[k];
+    const int all[4] = {t.x, t.y, t.z, t.w};
+    for (int a = 0; a < 4; a++)
+      for (int b = 0; b < 4; b++)
+        if (a != b && all[a] >= 0 && all[b] >= 0) {
+          e_ia.push_back(all[a]);
+          e_ib.push_back(all[b]);
+        }
+  }
+  const int ne = (int)e_ia.size();
+  std::vector<int> inc_ptr(na + 1, 0), inc_e(2 * (size_t)ne);
+  for (int e = 0; e < ne; e++) {
+    inc_ptr[cellA[e_ia[e]] + 1]++;
+    inc_ptr[cellA[e_ib[e]] + 1]++;
+  }
+  for (int J = 0; J < na; J++) inc_ptr[J + 1] += inc_ptr[J];
+  std::vector<std::vector<int>> nbr(na);
+  {
+    std::vector<int> fill(inc_ptr.begin(), inc_ptr.end() - 1);
+    for (int e = 0; e < ne; e++) {
+      const int Ja = cellA[e_ia[e]], Jb = cellA[e_ib[e]];
+      inc_e[fill[Ja]++] = e << 1;
+      inc_e[fill[Jb]++] = (e << 1) | 1;
+      nbr[Ja].push_back(Jb);
+      nbr[Jb].push_back(Ja);
+    }
+  }
+  std::vector<int> adj_ptr(na + 1, 0), adj_idx;
+  std::vector<double> adj_w, deg(na, 0.0);
+  for (int J = 0; J < na; J++) {
+    auto& v = nbr[J];
+    std::sort(v.begin(), v.end());
+    for (size_t k = 0; k < v.size();) {
+      size_t m = k;
+      while (m < v.size() && v[m] == v[k]) m++;
+      adj_idx.push_back(v[k]);
+      adj_w.push_back((double)(m - k));
+      deg[J] += (double)(m - k);
+      k = m;
+    }
+    adj_ptr[J + 1] = (int)adj_idx.size();
+  }
+  const size_t nadj = adj_idx.size();
+  g.na = na;
+  g.ne = ne;
+  g.max_it = std::min(20 * na + 100, kGlueMaxIt);
+  if (dmalloc(&g.dq, 2 * (size_t)nb) || dmalloc(&g.work, 4 * (size_t)na + 4) ||
+      dmalloc(&g.adjw, nadj + 1) || dmalloc(&g.deg, (size_t)na) || dmalloc(&g.ia, (size_t)ne + 1) ||
+      dmalloc(&g.ib, (size_t)ne + 1) || dmalloc(&g.incp, (size_t)na + 1) ||
+      dmalloc(&g.ince, 2 * (size_t)ne + 1) || dmalloc(&g.adjp, (size_t)na + 1) ||
+      dmalloc(&g.adji, nadj + 1))
+    return fail(c, DD_ENOMEM, "gluing scratch");
+  hipError_t e = hipSuccess;
+  auto up = [&](void* dst, const void* src, size_t bytes) {
+    if (e == hipSuccess && bytes > 0)
+      e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->st);
+  };
+  up(g.ia, e_ia.data(), sizeof(int) * ne);
+  up(g.ib, e_ib.data(), sizeof(int) * ne);
+  up(g.incp, inc_ptr.data(), sizeof(int) * (na + 1));
+  up(g.ince, inc_e.data(), sizeof(int) * 2 * (size_t)ne);
+  up(g.adjp, adj_ptr.data(), sizeof(int) * (na + 1));
+  up(g.adji, adj_idx.data(), sizeof(int) * nadj);
+  up(g.adjw, adj_w.data(), sizeof(double) * nadj);
+  up(g.deg, deg.data(), sizeof(double) * na);
+  if (e != hipSuccess) return fail(c, DD_EHIP, "gluing upload: %s", hipGetErrorString(e));
+  ddk::RefineParams R{};
+  R.Hc = l.H;
+  R.Wc = l.W;
+  R.bwc = l.bw;
+  R.eps = c->eps;
+  R.mu_c = l.mu;
+  R.alpha_a_c = c->alpha[0];
+  R.alpha_b_c = c->alpha[1];
+  ddk::launch_glue_ratios(R, g.dq, c->st);
+  ddk::launch_cert_glue(g.incp, g.ince, g.ia, g.ib, g.dq, g.adjp, g.adji, g.adjw, g.deg, na,
+                        g.max_it, kGlueTol2, g.work, dV, info, c->st);
+  e = hipGetLastError();
+  if (e != hipSuccess) return fail(c, DD_EHIP, "gluing launch: %s", hipGetErrorString(e));
+  return DD_OK;
 }
 
 __global__ void k_glue_apply(const double* aA, const double* V, double eps, int Hc, int Wc,
@@ -999,49 +1090,30 @@ extern "C" dd_status dd_refine(dd_ctx* c) {
   R.row_len_c = c->row_len;
   R.col_c = c->col;
   R.val_c = c->val;
-  // 1. gluing weights per basic cell, then the least-squares potential on the host
-  const int nbc = c->nb;
-  double* dq = nullptr;
-  HIPCHK(c, dmalloc(&dq, 2 * (size_t)nbc));
-  ddk::launch_glue_ratios(R, dq, c->st);
-  std::vector<double> q(2 * (size_t)nbc);
-  HIPCHK(c, hipMemcpyAsync(q.data(), dq, sizeof(double) * 2 * nbc, hipMemcpyDeviceToHost, c->st));
-  HIPCHK(c, hipStreamSynchronize(c->st));
-  hipFree(dq);
-  const int na = c->cells[0].n;
-  std::vector<int> cellA(nbc);
-  for (int k = 0; k < na; k++) {
-    const int4 t = c->cells[0].hq[k];
-    const int ids[4] = {t.x, t.y, t.z, t.w};
-    for (int a = 0; a < 4; a++)
-      if (ids[a] >= 0) cellA[ids[a]] = k;
-  }
-  std::vector<int> ea, eb;
-  std::vector<double> w;
-  for (int k = 0; k < c->cells[1].n; k++) {
-    const int4 t = c->cells[1].hq[k];
-    int ids[4], n = 0;
-    const int all[4] = {t.x, t.y, t.z, t.w};
-    for (int a = 0; a < 4; a++)
-      if (all[a] >= 0) ids[n++] = all[a];
-    for (int a = 0; a < n; a++)
-      for (int b = a + 1; b < n; b++) {
-        ea.push_back(cellA[ids[a]]);
-        eb.push_back(cellA[ids[b]]);
-        w.push_back(q[2 * ids[a]] + q[2 * ids[b] + 1]);
-      }
-  }
-  std::vector<double> V;
-  glue_solve(na, ea, eb, w, V);
-  double *dV = nullptr, *fg = nullptr;
-  HIPCHK(c, dmalloc(&dV, na));
+  // 1. gluing potential of the A-cells (device), glued coarse potential
+  double *dV = nullptr, *fg = nullptr, *dinfo = nullptr;
+  HIPCHK(c, dmalloc(&dV, (size_t)c->cells[0].n));
   HIPCHK(c, dmalloc(&fg, (size_t)lc.H * lc.W));
-  HIPCHK(c, hipMemcpyAsync(dV, V.data(), sizeof(double) * na, hipMemcpyHostToDevice, c->st));
+  HIPCHK(c, dmalloc(&dinfo, 4));
   {
+    GlueScratch gs;
+    dd_status gst = enqueue_glue(c, gs, dV, dinfo);
+    if (gst != DD_OK) {
+      hipFree(dV);
+      hipFree(fg);
+      hipFree(dinfo);
+      return gst;
+    }
     long long n = (long long)lc.H * lc.W;
     hipLaunchKernelGGL(k_glue_apply, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->st,
                        c->alpha[0], dV, c->eps, lc.H, lc.W, fg);
+    double hinfo[3] = {0, 0, 0};
+    HIPCHK(c, hipMemcpyAsync(hinfo, dinfo, sizeof hinfo, hipMemcpyDeviceToHost, c->st));
+    HIPCHK(c, hipStreamSynchronize(c->st));  // the scratch of gs is released after this
+    c->refine_glue_iters = (int)hinfo[0];
+    c->refine_glue_resid = hinfo[2] > 0 ? std::sqrt(hinfo[1] / hinfo[2]) : 0.0;
   }
+  hipFree(dinfo);
   // 2. fine potentials
   double *fa = nullptr, *fb = nullptr;
   const size_t nf = (size_t)lf.H * lf.W;
@@ -1145,6 +1217,7 @@ extern "C" dd_status dd_cost(dd_ctx* c, dd_cost_report* r) {
   r->eps = c->eps;
   r->last_partition = c->last_part;
   if (c->last_part >= 0) {
+    r->eps = c->last_eps;
     r->cost = c->last.cost;
     r->obj = c->last.obj;
     r->err_x = c->last.err_x;
@@ -1156,128 +1229,39 @@ extern "C" dd_status dd_certificate(dd_ctx* c, dd_cert_report* r, double* alpha_
                                    double* beta_hat) {
   if (!c || !r) return DD_EINVAL;
   if (c->last_part < 0) return fail(c, DD_ESTATE, "no half-iteration on this level yet");
+  if (c->eps != c->last_eps)
+    return fail(c, DD_ESTATE, "eps changed after the last half-iteration (%g -> %g)",
+                c->last_eps, c->eps);
   const Level& l = c->L[c->lev];
   const int nb = c->nb;
   const long long npx = (long long)l.H * l.W;
-  const int na = c->cells[0].n;
-  // geometry of the A-cell graph (host bookkeeping, no data): every ordered
-  // pair of basic cells in one B-cell is an oriented edge between their A-cells
-  std::vector<int> cellA(nb, 0);
-  for (int k = 0; k < na; k++) {
-    const int4 t = c->cells[0].hq[k];
-    const int ids[4] = {t.x, t.y, t.z, t.w};
-    for (int a = 0; a < 4; a++)
-      if (ids[a] >= 0) cellA[ids[a]] = k;
-  }
-  std::vector<int> e_ia, e_ib;
-  for (int k = 0; k < c->cells[1].n; k++) {
-    const int4 t = c->cells[1].hq[k];
-    const int all[4] = {t.x, t.y, t.z, t.w};
-    for (int a = 0; a < 4; a++)
-      for (int b = 0; b < 4; b++)
-        if (a != b && all[a] >= 0 && all[b] >= 0) {
-          e_ia.push_back(all[a]);
-          e_ib.push_back(all[b]);
-        }
-  }
-  const int ne = (int)e_ia.size();
-  std::vector<int> inc_ptr(na + 1, 0), inc_e(2 * (size_t)ne);
-  for (int e = 0; e < ne; e++) {
-    inc_ptr[cellA[e_ia[e]] + 1]++;
-    inc_ptr[cellA[e_ib[e]] + 1]++;
-  }
-  for (int J = 0; J < na; J++) inc_ptr[J + 1] += inc_ptr[J];
-  std::vector<std::vector<std::pair<int, int>>> nbr(na);
-  {
-    std::vector<int> fill(inc_ptr.begin(), inc_ptr.end() - 1);
-    for (int e = 0; e < ne; e++) {
-      const int Ja = cellA[e_ia[e]], Jb = cellA[e_ib[e]];
-      inc_e[fill[Ja]++] = e << 1;
-      inc_e[fill[Jb]++] = (e << 1) | 1;
-      nbr[Ja].push_back({Jb, 1});
-      nbr[Jb].push_back({Ja, 1});
-    }
-  }
-  std::vector<int> adj_ptr(na + 1, 0), adj_idx;
-  std::vector<double> adj_w, deg(na, 0.0);
-  for (int J = 0; J < na; J++) {
-    auto& v = nbr[J];
-    std::sort(v.begin(), v.end());
-    for (size_t k = 0; k < v.size();) {
-      size_t m = k;
-      while (m < v.size() && v[m].first == v[k].first) m++;
-      adj_idx.push_back(v[k].first);
-      adj_w.push_back((double)(m - k));
-      deg[J] += (double)(m - k);
-      k = m;
-    }
-    adj_ptr[J + 1] = (int)adj_idx.size();
-  }
-  ddk::RefineParams R{};
-  R.Hc = l.H;
-  R.Wc = l.W;
-  R.bwc = l.bw;
-  R.eps = c->eps;
-  R.mu_c = l.mu;
-  R.alpha_a_c = c->alpha[0];
-  R.alpha_b_c = c->alpha[1];
-  double *dq = nullptr, *dV = nullptr, *ah = nullptr, *bh = nullptr, *scr = nullptr,
-         *sums = nullptr, *work = nullptr, *d_adjw = nullptr, *d_deg = nullptr;
-  int *d_ia = nullptr, *d_ib = nullptr, *d_incp = nullptr, *d_ince = nullptr, *d_adjp = nullptr,
-      *d_adji = nullptr;
+  double *dV = nullptr, *ah = nullptr, *bh = nullptr, *scr = nullptr, *sums = nullptr;
   auto release = [&]() {
-    hipFree(dq);
     hipFree(dV);
     hipFree(ah);
     hipFree(bh);
     hipFree(scr);
     hipFree(sums);
-    hipFree(work);
-    hipFree(d_adjw);
-    hipFree(d_deg);
-    hipFree(d_ia);
-    hipFree(d_ib);
-    hipFree(d_incp);
-    hipFree(d_ince);
-    hipFree(d_adjp);
-    hipFree(d_adji);
   };
-  const size_t nadj = adj_idx.size();
-  if (dmalloc(&dq, 2 * (size_t)nb) || dmalloc(&dV, (size_t)na) || dmalloc(&ah, (size_t)npx) ||
-      dmalloc(&bh, (size_t)npx) || dmalloc(&scr, 2 * (size_t)npx) || dmalloc(&sums, 8) ||
-      dmalloc(&work, 4 * (size_t)na) || dmalloc(&d_adjw, nadj) || dmalloc(&d_deg, (size_t)na) ||
-      dmalloc(&d_ia, (size_t)ne) || dmalloc(&d_ib, (size_t)ne) ||
-      dmalloc(&d_incp, (size_t)na + 1) || dmalloc(&d_ince, 2 * (size_t)ne) ||
-      dmalloc(&d_adjp, (size_t)na + 1) || dmalloc(&d_adji, nadj)) {
+  if (dmalloc(&dV, (size_t)c->cells[0].n) || dmalloc(&ah, (size_t)npx) ||
+      dmalloc(&bh, (size_t)npx) || dmalloc(&scr, 2 * (size_t)npx) || dmalloc(&sums, 8)) {
     release();
     return fail(c, DD_ENOMEM, "certificate scratch");
   }
-  hipError_t e = hipSuccess;
-  auto up = [&](void* dst, const void* src, size_t bytes) {
-    if (e == hipSuccess && bytes > 0)
-      e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, c->st);
-  };
-  up(d_ia, e_ia.data(), sizeof(int) * ne);
-  up(d_ib, e_ib.data(), sizeof(int) * ne);
-  up(d_incp, inc_ptr.data(), sizeof(int) * (na + 1));
-  up(d_ince, inc_e.data(), sizeof(int) * 2 * (size_t)ne);
-  up(d_adjp, adj_ptr.data(), sizeof(int) * (na + 1));
-  up(d_adji, adj_idx.data(), sizeof(int) * nadj);
-  up(d_adjw, adj_w.data(), sizeof(double) * nadj);
-  up(d_deg, deg.data(), sizeof(double) * na);
   double hs[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (e == hipSuccess) {
-    // 1. overlap means per basic cell; 2. least-squares potential V on the device
-    ddk::launch_glue_ratios(R, dq, c->st);
-    ddk::launch_cert_glue(d_incp, d_ince, d_ia, d_ib, dq, d_adjp, d_adji, d_adjw, d_deg, na,
-                          std::min(20 * na + 100, 20000), 1e-24, work, dV, sums + 4, c->st);
-    // 3. glued potential; 4. Y-iteration over the stored support and the sums
-    hipLaunchKernelGGL(k_glue_apply, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, c->st,
-                       c->alpha[0], dV, c->eps, l.H, l.W, ah);
-    ddk::launch_cert_y(c->row_off, c->row_len, c->col, ah, l.mu, l.nu, l.H, l.W, l.bw, nb,
-                       c->eps, l.h, scr, bh, sums, c->st);
-    e = hipGetLastError();
+  GlueScratch gs;
+  // 1-2. overlap means and the least-squares potential V on the device
+  dd_status gst = enqueue_glue(c, gs, dV, sums + 4);
+  if (gst != DD_OK) {
+    release();
+    return gst;
   }
+  // 3. glued potential; 4. Y-iteration over the stored support and the sums
+  hipLaunchKernelGGL(k_glue_apply, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, c->st,
+                     c->alpha[0], dV, c->eps, l.H, l.W, ah);
+  ddk::launch_cert_y(c->row_off, c->row_len, c->col, ah, l.mu, l.nu, l.H, l.W, l.bw, nb, c->eps,
+                     l.h, scr, bh, sums, c->st);
+  hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(hs, sums, sizeof hs, hipMemcpyDeviceToHost, c->st);
   if (e == hipSuccess && alpha_hat)
     e = hipMemcpyAsync(alpha_hat, ah, sizeof(double) * npx, hipMemcpyDeviceToHost, c->st);
@@ -1293,11 +1277,14 @@ extern "C" dd_status dd_certificate(dd_ctx* c, dd_cert_report* r, double* alpha_
   r->rel_gap = r->gap / r->primal;
   r->sum_nu = hs[2];
   r->n_uncovered = (int64_t)hs[3];
-  r->n_edges = ne;
+  r->n_edges = gs.ne;
   r->level = c->lev;
   r->eps = c->eps;
   r->cg_iters = (int)hs[4];
   r->cg_rel_resid = hs[6] > 0 ? std::sqrt(hs[5] / hs[6]) : 0.0;
+  // the step cap reached before the residual bound: V is not the least-squares
+  // solution and the dual is a bound for a less good candidate
+  if (r->cg_iters >= gs.max_it && hs[5] > kGlueTol2 * hs[6]) return DD_ENOTCONV;
   return DD_OK;
 }
 
@@ -1775,6 +1762,7 @@ struct Snapshot {
   int64_t capE = 0, npx = 0, nnz = 0;
   int nb = 0, part = 0, last_part = -1;
   dd_iter_stats last{};
+  double last_eps = 0;
   bool prev_valid = false;
   int warm_fresh[2] = {1, 1};
   int warm_level[2] = {1, 1};
@@ -1806,6 +1794,7 @@ static dd_status snap_take(dd_ctx* c, int part, Snapshot& s) {
   s.part = part;
   s.last_part = c->last_part;
   s.last = c->last;
+  s.last_eps = c->last_eps;
   s.prev_valid = c->prev_valid;
   s.warm_fresh[0] = c->warm_fresh[0];
   s.warm_fresh[1] = c->warm_fresh[1];
@@ -1840,6 +1829,7 @@ static dd_status snap_restore(dd_ctx* c, const Snapshot& s) {
   c->nnz = s.nnz;
   c->last_part = s.last_part;
   c->last = s.last;
+  c->last_eps = s.last_eps;
   c->prev_valid = s.prev_valid;
   c->warm_fresh[0] = s.warm_fresh[0];
   c->warm_fresh[1] = s.warm_fresh[1];

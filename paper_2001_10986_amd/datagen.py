@@ -63,6 +63,24 @@ def eps_schedule(N, n_levels, eps_start=1.0, final_eps=None):
     return [tuple(s) for s in stages]
 
 
+def paper_schedule(N, coarsest=8, final_factor=0.25):
+    """Stage list of the paper's own protocol (Sec. 7.1 "Multi-scale and
+    eps-scaling"), in unit coordinates: layers from a coarsest side of
+    `coarsest` pixels up to N; on each layer with pixel spacing h_l, 4
+    half-iterations at eps = 2 h_l^2, then 2 at h_l^2 and 2 at h_l^2/2, then
+    refinement; on the finest layer 2 more at final_factor * h^2 (the paper:
+    a quarter of the squared pixel spacing).  Returns (stages, n_levels)."""
+    n_levels = int(round(np.log2(N // coarsest))) + 1
+    if coarsest << (n_levels - 1) != N:
+        raise ValueError("N must be coarsest * 2^k")
+    stages = []
+    for lev in range(n_levels):
+        h2 = (1.0 / (coarsest << lev)) ** 2
+        stages += [(lev, 2.0 * h2, 4), (lev, h2, 2), (lev, 0.5 * h2, 2)]
+    stages.append((n_levels - 1, final_factor / N ** 2, 2))
+    return stages, n_levels
+
+
 # --- the benchmark configurations (image k of config c uses seed 1000*c + k) ---
 
 def config1_pair():
