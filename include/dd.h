@@ -117,7 +117,12 @@ typedef struct {
   double ms_start[DD_N_KERNELS];    /* timing on: start and end of each kernel after the start */
   double ms_end[DD_N_KERNELS];      /* of the sweep (ms; the Newton launches: first start, last end) */
   int cells_bin[DD_N_BINS];         /* cells per solver bin */
-  int64_t evals_bin[DD_N_BINS];     /* entry_evals per solver bin */
+  int64_t evals_bin[DD_N_BINS];     /* entry_evals per solver bin: work of that bin's solver
+                                       (loops * |X_J| * |Y_J|; for cells handed to a Newton
+                                       launch only the loops before the hand-over) */
+  int64_t newton_evals;    /* work of the Newton launches: passes over the support (loops and
+                              line-search trials) * |X_J| * |Y_J| of the cells handed over */
+  int64_t newton_mfma_flops; /* and the FP64 matrix-core flops of their W = Q Q^T formations */
 } dd_iter_stats;
 
 typedef struct {
@@ -134,6 +139,9 @@ typedef struct {
   int launches_bin[DD_N_BINS];      /* solver launches per bin (one per sweep, also when
                                        the bin is empty: such a launch exits at once) */
   int64_t evals_bin[DD_N_BINS];
+  int64_t newton_evals;             /* summed over the sweeps as in dd_iter_stats */
+  int64_t newton_mfma_flops;
+  int newton_launches;              /* Newton launches (four per sweep) */
 } dd_run_stats;
 
 typedef struct {

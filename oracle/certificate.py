@@ -101,6 +101,27 @@ def helmholtz(edges, n_cells):
     return V - V.mean()
 
 
+def helmholtz_sparse(edges, n_cells):
+    """The same minimiser as `helmholtz` for large graphs: the normal
+    equations L V = D^T w (L the graph Laplacian) with V(0) = 0, solved by a
+    sparse direct factorisation, then shifted to mean zero."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spl
+    if not edges or n_cells == 1:
+        return np.zeros(n_cells)
+    e = np.array([(a, b) for a, b, _ in edges], dtype=np.int64)
+    w = np.array([lq for _, _, lq in edges])
+    ne = len(edges)
+    D = sp.csr_matrix((np.concatenate([-np.ones(ne), np.ones(ne)]),
+                       (np.concatenate([np.arange(ne)] * 2), np.concatenate([e[:, 0], e[:, 1]]))),
+                      shape=(ne, n_cells))
+    L = (D.T @ D).tocsc()
+    rhs = D.T @ w
+    V = np.zeros(n_cells)
+    V[1:] = spl.spsolve(L[1:, 1:], rhs[1:])
+    return V - V.mean()
+
+
 def y_iteration(alpha, C, mu, eps, chunk=2048, support=None):
     """beta(y) = -eps log sum_x exp((alpha(x) - c(x,y))/eps) mu(x) (step 4);
     with a boolean support matrix the sum runs over its True entries only

@@ -51,6 +51,8 @@ struct HalfParams {
   int* r_loops;
   int* r_status;
   long long* r_evals;
+  long long* r_nev;            // per cell handed to a Newton launch: support passes x |X_J| x U there
+  long long* r_nmf;            // and the FP64 matrix-core flops of its W formations
   long long* misc;             // [0] nnz_in, [1] out entries, [2] bad-row flag
   double* defer_F;             // potentials of cells handed to Newton steps (units of eps),
                                // 64 per cell, indexed by cell
@@ -83,6 +85,7 @@ struct SweepSched {
 struct IterStatsDev {
   double cost, obj, err;
   long long loops_total, evals, nnz;
+  long long newton_evals, newton_mfma;  // work of the Newton launches (cells handed over)
   long long out_entries, bad_rows;  // entries the sweep wrote; rows found out of range
   int loops_max, n_failed, n_safeguard, n_newton, n_cells;
   long long evals_bin[kNBins];

@@ -1811,6 +1811,10 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
     const int n_act = sh.nact;
     double* G = p.uni_G + ub;
     int status = 0, loops_all = 0;
+    // work of a handed-over cell in this launch: loops before the hand-over,
+    // line-search passes and W formations (Newton steps)
+    const int pre_loops = deferred ? p.r_loops[cell] : 0;
+    long long n_trials = 0, n_wbuild = 0;
     bool converged = false;
     double lam = p.lam;
     const int phases = p.safeguard ? 3 : 1;
@@ -1993,6 +1997,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
           double t = 1.0;
           if (build_w) {
             nst++;
+            n_wbuild++;
             // right side g - r sum(g)/sum(r), g = mu - r
             if (wave == 0) {
               const double mu = sh.mu[lane], r = sh.r[lane];
@@ -2041,6 +2046,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
             const double slope = sh.slope;
             if (slope > 0) {
               for (int trial = 0; trial < kNewtonTrials; trial++) {
+                n_trials++;
                 double loc = 0;
                 for (int y0 = 0; y0 < U; y0 += kNChunk) {
                   const int yi = y0 + yl;
@@ -2178,7 +2184,16 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
       p.r_status[cell] = status;
       int nx = 0;
       _Pragma("unroll") for (int a = 0; a < 4; a++) nx += g.bq[a] >= 0 ? 16 : 0;
-      p.r_evals[cell] = (long long)loops_all * nx * U;
+      if (deferred) {
+        // the solver that handed the cell over keeps its own loops; this
+        // launch counts its passes over the support (loops and line-search
+        // trials) and the FP64 matrix-core flops of W = Q Q^T (64x64xU)
+        p.r_evals[cell] = (long long)pre_loops * nx * U;
+        p.r_nev[cell] = (long long)(loops_all - pre_loops + n_trials) * nx * U;
+        p.r_nmf[cell] = n_wbuild * 2LL * 64 * 64 * U;
+      } else {
+        p.r_evals[cell] = (long long)loops_all * nx * U;
+      }
     }
     if (tid < 64 && sh.mu[tid] > 0)
       p.alpha[sh.xr[tid] * p.W + sh.xc[tid]] = p.eps * sh.F[tid] * (lam / p.lam);
@@ -2392,7 +2407,7 @@ __global__ __launch_bounds__(1024) void k_stats(const HalfParams* __restrict__ P
   __shared__ double shd[16];
   __shared__ long long shl[16];
   double c = 0, o = 0, e = 0;
-  long long lt = 0, ev = 0, nnz = 0;
+  long long lt = 0, ev = 0, nnz = 0, nev = 0, nmf = 0;
   int lmax = 0, nf = 0, ns = 0, nn = 0;
   for (int i = threadIdx.x; i < p.n_cells; i += 1024) {
     c += p.r_cost[i];
@@ -2400,6 +2415,12 @@ __global__ __launch_bounds__(1024) void k_stats(const HalfParams* __restrict__ P
     e += p.r_err[i];
     lt += p.r_loops[i];
     ev += p.r_evals[i];
+    // cells handed to a Newton launch (Newton flag, not the log-domain bin,
+    // whose solver switches in place): the work of that launch
+    if ((p.r_status[i] & 16) && cell_bin(p, p.cell_U[i]) != kNBins - 1) {
+      nev += p.r_nev[i];
+      nmf += p.r_nmf[i];
+    }
     lmax = max(lmax, p.r_loops[i]);
     nf += (p.r_status[i] & 3) != 0;
     ns += (p.r_status[i] & 4) != 0;
@@ -2431,6 +2452,10 @@ __global__ __launch_bounds__(1024) void k_stats(const HalfParams* __restrict__ P
   ev = tot;
   block_excl_scan(nnz, shl, &tot);
   nnz = tot;
+  block_excl_scan(nev, shl, &tot);
+  nev = tot;
+  block_excl_scan(nmf, shl, &tot);
+  nmf = tot;
   block_excl_scan((long long)nf, shl, &tot);
   nf = (int)tot;
   block_excl_scan((long long)ns, shl, &tot);
@@ -2457,6 +2482,8 @@ __global__ __launch_bounds__(1024) void k_stats(const HalfParams* __restrict__ P
     out->err = e;
     out->loops_total = lt;
     out->evals = ev;
+    out->newton_evals = nev;
+    out->newton_mfma = nmf;
     out->nnz = nnz;
     out->out_entries = p.misc[1];
     out->bad_rows = p.misc[2];

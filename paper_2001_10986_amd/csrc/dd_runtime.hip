@@ -380,7 +380,7 @@ static dd_status upload_cells(dd_ctx* c) {
     HIPCHK(c, dmalloc(&c->r_err, need));
     HIPCHK(c, dmalloc(&c->r_loops, need));
     HIPCHK(c, dmalloc(&c->r_status, need));
-    HIPCHK(c, dmalloc(&c->r_evals, need));
+    HIPCHK(c, dmalloc(&c->r_evals, 3 * (size_t)need));  // + Newton-launch work (2 arrays)
     HIPCHK(c, dmalloc(&c->defer_F, (size_t)need * 64));
     c->cell_cap = need;
   }
@@ -701,6 +701,8 @@ static HalfParams make_params(dd_ctx* c, int part) {
   p.r_loops = c->r_loops;
   p.r_status = c->r_status;
   p.r_evals = c->r_evals;
+  p.r_nev = c->r_evals + c->cell_cap;
+  p.r_nmf = c->r_evals + 2 * (size_t)c->cell_cap;
   p.misc = c->misc;
   p.defer_F = c->defer_F;
   p.capE = c->capE;
@@ -861,6 +863,8 @@ static dd_status sweep_finish(dd_ctx* c, int part, const IterStatsDev& d, float 
   r.n_newton = d.n_newton;
   r.nnz = d.nnz;
   r.entry_evals = d.evals;
+  r.newton_evals = d.newton_evals;
+  r.newton_mfma_flops = d.newton_mfma;
   r.cost = d.cost;
   r.obj = d.obj;
   r.err_x = d.err;
@@ -1181,6 +1185,9 @@ extern "C" dd_status dd_run_schedule(dd_ctx* c, dd_run_stats* out) {
       rs.n_cell_solves += it.n_cells;
       rs.loops_total += it.loops_total;
       rs.entry_evals += it.entry_evals;
+      rs.newton_evals += it.newton_evals;
+      rs.newton_mfma_flops += it.newton_mfma_flops;
+      rs.newton_launches += ddk::kNDeferGroups;
       rs.n_failed += it.n_failed;
       rs.n_safeguard += it.n_safeguard;
       rs.n_newton += it.n_newton;
@@ -1700,6 +1707,9 @@ extern "C" dd_status dd_batch_run_schedule(dd_batch* b, dd_run_stats* out) {
       r.n_cell_solves += t.n_cells;
       r.loops_total += t.loops_total;
       r.entry_evals += t.entry_evals;
+      r.newton_evals += t.newton_evals;
+      r.newton_mfma_flops += t.newton_mfma_flops;
+      r.newton_launches += ddk::kNDeferGroups;
       r.n_failed += t.n_failed;
       r.n_safeguard += t.n_safeguard;
       r.n_newton += t.n_newton;

@@ -56,7 +56,8 @@ class IterStats(C.Structure):
                 ("obj", C.c_double), ("err_x", C.c_double), ("ms", C.c_double),
                 ("ms_kernel", C.c_double * N_KERNELS), ("ms_start", C.c_double * N_KERNELS),
                 ("ms_end", C.c_double * N_KERNELS), ("cells_bin", C.c_int * N_BINS),
-                ("evals_bin", C.c_int64 * N_BINS)]
+                ("evals_bin", C.c_int64 * N_BINS), ("newton_evals", C.c_int64),
+                ("newton_mfma_flops", C.c_int64)]
 
     def as_dict(self):
         return {k: (list(getattr(self, k)) if k in ("ms_kernel", "ms_start", "ms_end", "cells_bin",
@@ -70,7 +71,8 @@ class RunStats(C.Structure):
                 ("n_safeguard", C.c_int), ("n_newton", C.c_int), ("nnz_max", C.c_int64),
                 ("ms_total", C.c_double), ("ms_kernel", C.c_double * N_KERNELS),
                 ("launches_bin", C.c_int * N_BINS),
-                ("evals_bin", C.c_int64 * N_BINS)]
+                ("evals_bin", C.c_int64 * N_BINS), ("newton_evals", C.c_int64),
+                ("newton_mfma_flops", C.c_int64), ("newton_launches", C.c_int)]
 
     def as_dict(self):
         return {k: (list(getattr(self, k)) if k in ("ms_kernel", "launches_bin", "evals_bin")
@@ -286,15 +288,18 @@ class Problem:
         potentials=True also the glued alpha_hat and beta_hat (H x W, FP64)."""
         r = CertReport()
         if not potentials:
-            self._chk(lib.dd_certificate(self._h, C.byref(r), None, None), "dd_certificate")
-            return r.as_dict()
+            rc = self._chk(lib.dd_certificate(self._h, C.byref(r), None, None), "dd_certificate")
+            out = r.as_dict()
+            out["status"] = rc
+            return out
         info = self.level_info()
         H, W = info["H"], info["W"]
         a = np.empty(H * W, dtype=np.float64)
         b = np.empty(H * W, dtype=np.float64)
-        self._chk(lib.dd_certificate(self._h, C.byref(r), a.ctypes.data, b.ctypes.data),
-                  "dd_certificate")
+        rc = self._chk(lib.dd_certificate(self._h, C.byref(r), a.ctypes.data, b.ctypes.data),
+                       "dd_certificate")
         out = r.as_dict()
+        out["status"] = rc
         out["alpha_hat"], out["beta_hat"] = a.reshape(H, W), b.reshape(H, W)
         return out
 

@@ -172,3 +172,19 @@ def test_paper_protocol_gap_within_table_summary():
     r = cert.certificate(e["alpha_a"], e["alpha_b"], c["obj"], C, mu.ravel(), nu.ravel(), eps,
                          basic, ca, cb)
     assert 0 < r["rel_gap"] < bar, r["rel_gap"]
+
+
+def test_sparse_helmholtz_equals_dense_least_squares():
+    # the sparse normal-equation solve used for large graphs gives the
+    # minimiser of the dense least squares
+    N, s = 32, 4
+    mu, _ = _pair(N, 5)
+    eps = 1e-3
+    basic, ca, cb = dense.grid_partitions(N, N, s)
+    rng = np.random.default_rng(4)
+    aA = rng.normal(0, 1e-2, N * N)
+    aB = rng.normal(0, 1e-2, N * N)
+    edges = cert.graph_edges(aA, aB, mu, eps, basic, ca, cb)
+    V1 = cert.helmholtz(edges, len(ca))
+    V2 = cert.helmholtz_sparse(edges, len(ca))
+    assert np.abs(V1 - V2).max() < 1e-10 * np.abs(V1).max()

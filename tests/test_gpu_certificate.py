@@ -55,9 +55,93 @@ def test_certificate_on_the_256_schedule():
     r = g.certificate()
     print(f"256x256 schedule: primal {r['primal']:.10g} dual {r['dual']:.10g} "
           f"rel gap {r['rel_gap']:.4e}", flush=True)
-    assert r["n_uncovered"] == 0
+    assert r["n_uncovered"] == 0 and r["status"] == 0
     assert abs(r["sum_nu"] - 1.0) < 1e-12
-    # weak duality (up to the X-marginal tolerance): a positive gap; measured
-    # 9.8e-3 on this schedule, shrinking slowly with more half-iterations at
-    # the final eps
-    assert 0 < r["rel_gap"] < 2e-2
+    # weak duality (up to the X-marginal tolerance): a positive gap.  How
+    # small it gets is set by the schedule: this one starts the hierarchy at
+    # 64x64, where two half-iterations per eps stage leave the coarse plan far
+    # from the optimum (the oracle on a 64x64 pair: relative gap 0.25 after
+    # that level alone, 1.8e-4 with the hierarchy from 8x8); the bar against
+    # the paper's table is in test_paper_protocol_gap_within_table_summary
+    assert 0 < r["rel_gap"]
+    assert r["cg_rel_resid"] <= 1e-12
+
+
+def _table(size):
+    import json
+    import os
+    tab = json.load(open(os.path.join(os.path.dirname(__file__), "golden",
+                                      "table_summary_pd_gap.json")))
+    k = tab["sizes"].index(size)
+    return tab["rel_pd_gap_mean"][k] + 2 * tab["rel_pd_gap_std"][k]
+
+
+@pytest.mark.parametrize("N", [64, 1024])
+def test_paper_protocol_gap_within_table_summary(N):
+    # The paper's protocol (Sec. 7.1: layers from 8x8, 4/2/2 half-iterations
+    # at eps = 2, 1, 1/2 dx_l^2, then 2 at dx^2/4; Err 1e-4) on the GPU: the
+    # relative PD gap of eq. RelPDGap must lie in the range Table "Summary"
+    # prints for that size (mean plus two standard deviations over its 45
+    # pairs).  At 64x64 the oracle runs the same protocol on the same pair and
+    # both certificates are compared.
+    from paper_2001_10986_amd import dd
+    if N == 64:
+        mu, nu = datagen.small_pair(N, 8, seed=11)
+    else:
+        mu, nu, _ = datagen.config3_pair(N=N)
+    stages, nlev = datagen.paper_schedule(N)
+    g = dd.Problem(mu, nu, stages, s=4, n_levels=nlev, err_tol=1e-4)
+    rs = g.run_schedule()
+    c = g.cost()
+    r = g.certificate()
+    print(f"{N}x{N} paper protocol: {rs['n_half_iters']} half-iterations, err_x {c['err_x']:.3e}, "
+          f"rel gap {r['rel_gap']:.4e} (table bar {_table(N):.2e}), cg {r['cg_iters']}", flush=True)
+    assert rs["n_half_iters"] == 8 * nlev + 2 and rs["n_failed"] == 0
+    assert c["err_x"] <= 1e-4 and c["err_y"] <= 1e-6
+    assert r["status"] == 0 and r["n_uncovered"] == 0
+    assert 0 < r["rel_gap"] < _table(N)
+    if N == 64:
+        from oracle import ddo
+        o = ddo.Oracle(mu, nu, s=4, n_levels=nlev, eps=stages[0][1], err_tol=1e-4, accel=0,
+                       newton_after=0)
+        o.run_schedule(stages)
+        e = o.export()
+        C = dense.grid_cost(N, N, 1.0 / N)
+        basic, ca, cb = dense.grid_partitions(N, N, 4)
+        ro = cert.certificate(e["alpha_a"], e["alpha_b"], o.cost()["obj"], C, mu.ravel(),
+                              nu.ravel(), stages[-1][1], basic, ca, cb)
+        print(f"  oracle (plain iteration): rel gap {ro['rel_gap']:.4e}", flush=True)
+        assert 0 < ro["rel_gap"] < _table(N)
+    g.close()
+
+
+def test_gluing_solve_with_several_rows_per_thread():
+    # 512x512 (4096 A-cells: four rows of the one-workgroup CG per thread):
+    # the glued potential against the oracle's graph weights and sparse
+    # least-squares solve on the same exported state
+    from paper_2001_10986_amd import dd
+    N = 512
+    mu, nu, _ = datagen.config3_pair(N=N)
+    stages, nlev = datagen.paper_schedule(N)
+    g = dd.Problem(mu, nu, stages, s=4, n_levels=nlev, err_tol=1e-4)
+    g.run_schedule()
+    r = g.certificate(potentials=True)
+    e = g.export()
+    eps = stages[-1][1]
+    basic, ca, cb = dense.grid_partitions(N, N, 4)
+    assert len(ca) == 4096
+    edges = cert.graph_edges(e["alpha_a"].ravel(), e["alpha_b"].ravel(), mu.ravel(), eps, basic,
+                             ca, cb)
+    assert r["n_edges"] == len(edges)
+    V = cert.helmholtz_sparse(edges, len(ca))
+    ah = e["alpha_a"].ravel().copy()
+    for J, cell in enumerate(ca):
+        for i in cell:
+            ah[basic[i]] += eps * V[J]
+    scale = np.abs(ah).max()
+    d = np.abs(r["alpha_hat"].ravel() - ah).max()
+    print(f"512x512: cg {r['cg_iters']} steps, rel resid {r['cg_rel_resid']:.2e}, "
+          f"max |alpha_hat diff| {d:.3e} of {scale:.3e}", flush=True)
+    assert r["status"] == 0 and r["cg_iters"] < 20000 and r["cg_rel_resid"] <= 1e-12
+    assert d <= 1e-9 * scale
+    g.close()
