@@ -221,6 +221,21 @@ dd_status dd_run_schedule(dd_ctx* ctx, dd_run_stats* stats);
  * current eps if none ran yet).  Synchronises the context's stream. */
 dd_status dd_cost(dd_ctx* ctx, dd_cost_report* report);
 
+/* dd_cost without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same report as dd_cost, computed by the same kernels; their
+ * scratch (H*W + 768 doubles) is a static device array of
+ * 2^22 + 768 doubles (32 MiB) on every GPU the library runs on, held until
+ * the process ends, so the current level may have at most 2^22 pixels
+ * (2048 x 2048); larger levels are rejected with DD_ECAPACITY (dd_cost has
+ * no such limit).  The array is cleared by a kernel on every call.  Every
+ * call on one GPU shares that array: calls that overlap on one GPU (contexts
+ * on different streams, other threads) race and must be serialised by the
+ * caller.  Allocates nothing on the device or in pinned memory (the host
+ * read-back buffer belongs to the context); synchronises the context's
+ * stream. */
+dd_status dd_cost_noalloc(dd_ctx* ctx, dd_cost_report* report);
+
 /* Export the state (Algorithm 2 outputs) into caller buffers; fills the
  * scalar fields of *view first, so a call with NULL pointers returns sizes. */
 dd_status dd_export_plan(dd_ctx* ctx, dd_plan_view* view);

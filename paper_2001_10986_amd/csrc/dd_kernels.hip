@@ -15,6 +15,7 @@
 
 #include <float.h>
 #include <math.h>
+#include <algorithm>
 
 namespace ddk {
 
@@ -2731,10 +2732,19 @@ __global__ void k_diag_final(const double* part, int n, double* out3) {
   }
 }
 
+__global__ void k_zero_d(double* p, long long n) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0.0;
+}
+
 void launch_diag(const int64_t* row_off, const int* row_len, const int* col, const double* val,
                  const double* mu, const double* nu, int H, int W, int bw, int n_basic,
                  double* scratch_px, double* out3, hipStream_t st) {
-  hipMemsetAsync(scratch_px, 0, sizeof(double) * (size_t)H * W, st);
+  // the accumulator is cleared by a kernel (no memset node if a caller captures the launches)
+  const long long npx = (long long)H * W;
+  const unsigned zb = (unsigned)std::min<long long>((npx + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_zero_d, dim3(zb > 0 ? zb : 1), dim3(256), 0, st, scratch_px, npx);
   hipLaunchKernelGGL(k_diag_scatter, dim3(n_basic), dim3(64), 0, st, row_off, row_len, col, val,
                      n_basic, scratch_px);
   // the slots live behind the H*W accumulator (scratch_px holds H*W + 3*kDiagBlocks)

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -271,6 +272,8 @@ struct dd_ctx {
   int64_t px_cap = 0;
   dd_iter_stats last{};
   double last_eps = 0;  // eps of the half-iteration whose results `last` holds
+  int device = 0;                  // HIP device the context was created on
+  double* noalloc_scratch = nullptr;  // device address of this device's dd_cost_noalloc scratch
   int refine_glue_iters = 0;       // CG steps of the last refinement's gluing solve
   double refine_glue_resid = 0;    // and its final relative residual
   static_assert(DD_N_KERNELS == ddk::kNKernels, "kernel count of the ABI and the launcher");
@@ -550,6 +553,38 @@ static dd_status init_level0(dd_ctx* c) {
   return upload_cells(c);
 }
 
+// ---- scratch of the allocation-free diagnostics (dd_cost_noalloc) -------
+// The per-pixel Y-marginal accumulator and the block partial sums of the
+// diagnostics kernels live in a file-scope device array: one copy on every
+// GPU the library runs on, held until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in for
+// the symbol); it uses the device address looked up once per device, with
+// that device current, at the first dd_init on it.
+constexpr int64_t kNoAllocMaxPx = int64_t(1) << 22;  // 2048 x 2048 pixels
+static __device__ __align__(256) double dd_cost_scratch[kNoAllocMaxPx + 3 * ddk::kDiagBlocks];
+constexpr int kMaxDevices = 64;
+static std::mutex g_noalloc_mu;
+static double* g_noalloc_ptr[kMaxDevices] = {};
+
+static hipError_t noalloc_scratch_ptr(int dev, double** out) {
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  if (!g_noalloc_ptr[dev]) {
+    int prev = 0;
+    hipError_t e = hipGetDevice(&prev);
+    if (e != hipSuccess) return e;
+    if (prev != dev && (e = hipSetDevice(dev)) != hipSuccess) return e;
+    void* ptr = nullptr;
+    e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(dd_cost_scratch));
+    if (prev != dev) (void)hipSetDevice(prev);
+    if (e != hipSuccess) return e;
+    if (!ptr) return hipErrorInvalidSymbol;
+    g_noalloc_ptr[dev] = static_cast<double*>(ptr);
+  }
+  *out = g_noalloc_ptr[dev];
+  return hipSuccess;
+}
+
 extern "C" dd_status dd_init(const double* mu, const double* nu, int H, int W, int s, int nlev,
                              const dd_stage* schedule, int n_stages, const dd_options* opt,
                              dd_ctx** out) {
@@ -637,6 +672,13 @@ extern "C" dd_status dd_init(const double* mu, const double* nu, int H, int W, i
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
     return bail(fail(c, DD_EHIP, "no HIP device"));
+  c->device = dev;
+  {
+    const hipError_t e = noalloc_scratch_ptr(dev, &c->noalloc_scratch);
+    if (e != hipSuccess)
+      return bail(fail(c, DD_EHIP, "address of the static diagnostics scratch: %s",
+                       hipGetErrorString(e)));
+  }
   {
     const size_t need = ddk::sweep_max_static_lds();
     if (need == 0 || need > (size_t)lds_max)
@@ -1206,13 +1248,12 @@ extern "C" dd_status dd_run_schedule(dd_ctx* c, dd_run_stats* out) {
   return worst;
 }
 
-extern "C" dd_status dd_cost(dd_ctx* c, dd_cost_report* r) {
-  if (!c || !r) return DD_EINVAL;
+// The diagnostics of dd_cost with the given scratch (H*W + 3*kDiagBlocks
+// doubles on the context's device).
+static dd_status cost_report(dd_ctx* c, double* scratch, dd_cost_report* r) {
   const Level& l = c->L[c->lev];
-  dd_status s = ensure_px(c, (int64_t)l.H * l.W + 3 * ddk::kDiagBlocks);
-  if (s) return s;
   ddk::launch_diag(c->row_off, c->row_len, c->col, c->val, l.mu, l.nu, l.H, l.W, l.bw, c->nb,
-                   c->px_scratch, c->dscal, c->st);
+                   scratch, c->dscal, c->st);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipMemcpyAsync(c->hscal, c->dscal, sizeof(double) * 3, hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
@@ -1230,6 +1271,27 @@ extern "C" dd_status dd_cost(dd_ctx* c, dd_cost_report* r) {
     r->err_x = c->last.err_x;
   }
   return DD_OK;
+}
+
+extern "C" dd_status dd_cost(dd_ctx* c, dd_cost_report* r) {
+  if (!c || !r) return DD_EINVAL;
+  const Level& l = c->L[c->lev];
+  dd_status s = ensure_px(c, (int64_t)l.H * l.W + 3 * ddk::kDiagBlocks);
+  if (s) return s;
+  return cost_report(c, c->px_scratch, r);
+}
+
+extern "C" dd_status dd_cost_noalloc(dd_ctx* c, dd_cost_report* r) {
+  if (!c || !r) return DD_EINVAL;
+  const Level& l = c->L[c->lev];
+  const int64_t npx = (int64_t)l.H * l.W;
+  if (npx > kNoAllocMaxPx)
+    return fail(c, DD_ECAPACITY,
+                "dd_cost_noalloc: level %d has %lld pixels, more than the %lld its static "
+                "scratch holds (dd_cost has no such limit)",
+                c->lev, (long long)npx, (long long)kNoAllocMaxPx);
+  if (!c->noalloc_scratch) return fail(c, DD_ESTATE, "dd_cost_noalloc: scratch not set up");
+  return cost_report(c, c->noalloc_scratch, r);
 }
 
 extern "C" dd_status dd_certificate(dd_ctx* c, dd_cert_report* r, double* alpha_hat,

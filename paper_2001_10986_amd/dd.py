@@ -26,7 +26,7 @@ EXPORTED = ["dd_options_default", "dd_init", "dd_half_iterate", "dd_set_eps", "d
             "dd_batch_half_iterate", "dd_batch_run_schedule", "dd_batch_schedule_step",
             "dd_batch_info", "dd_batch_free", "dd_set_launch", "dd_batch_set_launch",
             "dd_autotune", "dd_batch_autotune", "dd_get_launch",
-            "dd_batch_last_error", "dd_certificate"]
+            "dd_batch_last_error", "dd_certificate", "dd_cost_noalloc"]
 
 DD_BATCH_GRAPH = 1
 DD_PREC_SPLIT, DD_PREC_FP64 = 0, 1
@@ -136,6 +136,7 @@ def _load():
     lib.dd_refine.argtypes = [C.c_void_p]
     lib.dd_run_schedule.argtypes = [C.c_void_p, P(RunStats)]
     lib.dd_cost.argtypes = [C.c_void_p, P(CostReport)]
+    lib.dd_cost_noalloc.argtypes = [C.c_void_p, P(CostReport)]
     lib.dd_certificate.argtypes = [C.c_void_p, P(CertReport), C.c_void_p, C.c_void_p]
     lib.dd_export_plan.argtypes = [C.c_void_p, P(PlanView)]
     lib.dd_import_state.argtypes = [C.c_void_p, P(PlanView)]
@@ -281,6 +282,13 @@ class Problem:
     def cost(self):
         r = CostReport()
         self._chk(lib.dd_cost(self._h, C.byref(r)), "dd_cost")
+        return r.as_dict()
+
+    def cost_noalloc(self):
+        """dd_cost_noalloc: the same report from a static device scratch (no
+        device allocation; levels of at most 2^22 pixels)."""
+        r = CostReport()
+        self._chk(lib.dd_cost_noalloc(self._h, C.byref(r)), "dd_cost_noalloc")
         return r.as_dict()
 
     def certificate(self, potentials=False):
