@@ -263,3 +263,83 @@ def test_newton_fallback_same_cell_optima_in_a_sweep():
     assert res[4][0]["loops_total"] < 0.5 * res[0][0]["loops_total"]
     assert np.abs(res[4][1] - res[0][1]).max() < 1e-9 * res[0][1].max()
     assert abs(res[4][0]["cost"] - res[0][0]["cost"]) < 1e-10
+
+
+def test_small_eps_limit_is_the_monotone_rearrangement():
+    # 8 x N images whose rows all carry the same profile, mu = U(rows) (x) a,
+    # nu = U(rows) (x) b: with c = |x-y|^2 the optimal plan keeps every row
+    # and moves mass along it monotonically, so the unregularised W2^2 is the
+    # one of the 1D profiles (north-west corner rule on the sorted CDFs).  As
+    # eps falls through the schedule the DD cost must approach that closed
+    # form monotonically, down to the discrete optimum once eps << h^2.
+    N, H = 32, 8
+    c = np.arange(N)
+    a = np.exp(-((c - 10) / 4.0) ** 2) + 0.3 * np.exp(-((c - 24) / 3.0) ** 2) + 0.02
+    b = np.exp(-((c - 18) / 5.0) ** 2) + 0.02
+    a /= a.sum()
+    b /= b.sum()
+    mu, nu = np.tile(a / H, (H, 1)), np.tile(b / H, (H, 1))
+    h = 1.0 / N
+    w = dense.monotone_w2sq((c + 0.5) * h, a, (c + 0.5) * h, b)
+    # (the oracle's accelerated cell solver: the same stopping test and fixed
+    # point; the plain one needs ~1e6 loops at the last eps, where the cells
+    # are nearly disconnected)
+    o = ddo.Oracle(mu, nu, s=4, n_levels=1, eps=4 * h * h, err_tol=1e-9, trunc=0.0,
+                   n_threads=2)
+    gaps = []
+    for f in (4.0, 1.0, 0.25, 1.0 / 16):
+        o.set_eps(f * h * h)
+        for k in range(10):
+            st = o.half_iterate(k % 2)
+        gaps.append(st["cost"] - w)
+    assert all(gaps[i + 1] < gaps[i] for i in range(len(gaps) - 1)), gaps
+    assert gaps[0] > 0.02 * w and abs(gaps[-1]) < 1e-6 * w, gaps
+
+
+def test_safeguard_reaches_the_same_cell_optimum():
+    # Sec. 7.4 safeguard: a cell that hits the loop cap is solved again at
+    # 2 eps from its stored potential, then at eps from that solution.  With
+    # a cap of 160 loops four cells of the first config-1 sweep go through
+    # it; each must reach the unique cell optimum (Proposition "Optimal
+    # entropic transport couplings" (i)) of the uncapped plain solve within
+    # the stopping tolerance.
+    mu, nu, cfg = datagen.config1_pair()
+    eps = cfg["stages"][0][1]
+    kw = dict(s=4, n_levels=1, eps=eps, accel=0, newton_after=0, n_threads=2)
+    ref = ddo.Oracle(mu, nu, **kw)
+    ref.half_iterate(0)
+    rr = ref.cell_results(0)
+    o = ddo.Oracle(mu, nu, max_iter=160, **kw)
+    st = o.half_iterate(0)
+    r = o.cell_results(0)
+    sg = (r["status"] & 4) != 0
+    assert st["n_safeguard"] == sg.sum() > 0 and st["n_failed"] == 0
+    assert rr["loops"][sg].min() > 160  # the cap forced them through the detour
+    m_cell = np.array([mu.reshape(4, 8, 4, 8)[i // 4, :, i % 4, :].sum() for i in range(16)])
+    assert np.all(r["err_x"][sg] <= 1e-5 * m_cell[sg])
+    assert np.all(np.abs(r["cost"][sg] - rr["cost"][sg]) <= 1e-5 * rr["cost"][sg])
+    # cells that did not need it ran the same solve
+    assert np.array_equal(r["loops"][~sg], rr["loops"][~sg])
+
+
+def test_multiscale_schedule_ends_at_the_entropic_optimum():
+    # two levels (8x8 -> 16x16), eps 1 -> (1/16)^2, then 60 more
+    # half-iterations at the final eps, tight tolerance and no truncation:
+    # the end state is the full-grid entropic optimum (the DD fixed point,
+    # Thm. "Linear convergence"), computed here by the dense Newton solver
+    N, s = 16, 4
+    mu, nu = datagen.small_pair(N, 3, seed=41)
+    stages = datagen.eps_schedule(N, 2)
+    stages = stages[:-1] + [(stages[-1][0], stages[-1][1], stages[-1][2] + 60)]
+    o = ddo.Oracle(mu, nu, s=s, n_levels=2, eps=stages[0][1], err_tol=1e-11, trunc=0.0,
+                   max_iter=200000, accel=0, newton_after=0, n_threads=2)
+    st = o.run_schedule(stages)
+    eps = stages[-1][1]
+    C = dense.grid_cost(N, N, 1.0 / N)
+    P = dense.entropic_ot_newton(C, mu.ravel(), nu.ravel(), eps)[2]
+    basic, _, _ = dense.grid_partitions(N, N, s)
+    assert o.level_info()["level"] == 1 and st["n_failed"] == 0
+    assert np.abs(o.basic_marginals() - _basic_marg_dense(P, basic)).max() < 1e-8
+    # the cost of a plan whose X-marginal is off by Err = 1e-11 can move by
+    # Err * max c, 2e-11 here: 1e-8 relative to the cost of 0.03
+    assert abs(o.cost()["cost"] - (C * P).sum()) < 1e-8 * (C * P).sum()
