@@ -86,6 +86,16 @@ void* dd_mlp_get_stream(const dd_mlp* net);
  * cell's index in its partition (int32); at most cap rows in an unspecified
  * order (device buffers of the caller); *n_out = rows written.  Synchronises. */
 dd_status dd_set_warm_start(dd_ctx* ctx, dd_mlp* net, int policy, float min_rms);
+
+/* dd_set_warm_prediction: a prediction from elsewhere for the next
+ * dd_half_iterate only (then forgotten): y_dev holds one row of 64 floats per
+ * cell of that sweep's partition (cells numbered row-major), in the
+ * network's output units (the change of the centred potential, units of
+ * 16 h^2/eps); it is applied by the same kernel and eligibility rule as the
+ * network's output (Y-support of at most 512 points, RMS of the change at
+ * least min_rms), and replaces the network on that sweep.  The device buffer
+ * stays the caller's and must live until that sweep has run. */
+dd_status dd_set_warm_prediction(dd_ctx* ctx, const float* y_dev, float min_rms);
 dd_status dd_warm_start_count(dd_ctx* ctx, int* n_sweeps, long long* n_cells);
 dd_status dd_collect_cells(dd_ctx* ctx, float* x_dev, float* t_dev, float* mask_dev,
                            int* cell_dev, int cap, int* n_out);

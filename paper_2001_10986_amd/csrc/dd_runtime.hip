@@ -283,6 +283,8 @@ struct dd_ctx {
   int warm_policy = 0;
   float warm_min_rms = 0.f;
   int* warm_count = nullptr;        // cells warm-started, summed over sweeps (device)
+  const float* warm_given = nullptr;  // one-shot prediction for the next sweep (caller's device rows)
+  float warm_given_rms = 0.f;
   int warm_fresh[2] = {1, 1};     // no sweep of this partition since init/refine/eps change
   int warm_level[2] = {1, 1};     // no sweep of this partition since init/refine
   unsigned short* warm_X = nullptr;
@@ -788,6 +790,14 @@ static dd_status warm_start(dd_ctx* c, const HalfParams& p) {
   return DD_OK;
 }
 
+extern "C" dd_status dd_set_warm_prediction(dd_ctx* c, const float* y_dev, float min_rms) {
+  if (!c || !(min_rms >= 0)) return DD_EINVAL;
+  if (c->in_batch) return fail(c, DD_ESTATE, "the context belongs to a batch");
+  c->warm_given = y_dev;
+  c->warm_given_rms = min_rms;
+  return DD_OK;
+}
+
 extern "C" dd_status dd_set_warm_start(dd_ctx* c, dd_mlp* net, int policy, float min_rms) {
   if (!c || policy < 0 || policy > 3 || !(min_rms >= 0)) return DD_EINVAL;
   if (net) {
@@ -949,7 +959,18 @@ extern "C" dd_status dd_half_iterate(dd_ctx* c, int part, dd_iter_stats* out) {
   const bool warm = c->warm_net && c->warm_policy > 0 &&
                     (c->warm_policy == 2 || (c->warm_policy == 1 && c->warm_fresh[part]) ||
                      (c->warm_policy == 3 && c->warm_level[part]));
-  if (warm) {
+  if (c->warm_given) {
+    // a prediction handed in by dd_set_warm_prediction replaces the network
+    // on this sweep (same apply kernel, same eligibility rule)
+    if (!c->warm_count) {
+      HIPCHK(c, dmalloc(&c->warm_count, 1));
+      HIPCHK(c, hipMemsetAsync(c->warm_count, 0, sizeof(int), c->st));
+    }
+    ddk::launch_warm_apply(p, c->warm_given, c->warm_given_rms, c->warm_count, c->st);
+    HIPCHK(c, hipGetLastError());
+    c->warm_given = nullptr;
+    c->n_warm_sweeps++;
+  } else if (warm) {
     dd_status ws = warm_start(c, p);
     if (ws) return ws;
     c->n_warm_sweeps++;

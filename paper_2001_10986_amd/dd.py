@@ -26,7 +26,8 @@ EXPORTED = ["dd_options_default", "dd_init", "dd_half_iterate", "dd_set_eps", "d
             "dd_batch_half_iterate", "dd_batch_run_schedule", "dd_batch_schedule_step",
             "dd_batch_info", "dd_batch_free", "dd_set_launch", "dd_batch_set_launch",
             "dd_autotune", "dd_batch_autotune", "dd_get_launch",
-            "dd_batch_last_error", "dd_certificate", "dd_cost_noalloc"]
+            "dd_batch_last_error", "dd_certificate", "dd_cost_noalloc",
+            "dd_set_warm_prediction"]
 
 DD_BATCH_GRAPH = 1
 DD_PREC_SPLIT, DD_PREC_FP64 = 0, 1
@@ -147,6 +148,8 @@ def _load():
     lib.dd_last_error.argtypes = [C.c_void_p]
     lib.dd_last_error.restype = C.c_char_p
     lib.dd_set_warm_start.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_float]
+    lib.dd_set_warm_prediction.argtypes = [C.c_void_p, C.c_void_p, C.c_float]
+    lib.dd_set_warm_prediction.restype = C.c_int
     lib.dd_warm_start_count.argtypes = [C.c_void_p, P(C.c_int), P(C.c_longlong)]
     lib.dd_warm_start_count.restype = C.c_int
     lib.dd_collect_cells.argtypes = [C.c_void_p] + [C.c_void_p] * 4 + [C.c_int, P(C.c_int)]
@@ -383,6 +386,15 @@ class Problem:
         self._chk(lib.dd_set_warm_start(self._h, None if net is None else net.handle,
                                         policy if net is not None else 0, float(min_rms)),
                   "dd_set_warm_start")
+
+    def set_warm_prediction(self, y, min_rms=0.0):
+        """dd_set_warm_prediction: apply the rows of the torch CUDA float32
+        tensor y (cells of the next sweep's partition x 64, network output
+        units) as the start of the next half-iteration only."""
+        assert y.is_cuda and y.dtype.itemsize == 4 and y.is_contiguous()
+        self._warm_pred = y  # keep it alive until the sweep has run
+        self._chk(lib.dd_set_warm_prediction(self._h, C.c_void_p(y.data_ptr()), float(min_rms)),
+                  "dd_set_warm_prediction")
 
     def warm_start_count(self):
         """(sweeps that ran the network, cells that took its start) since init."""

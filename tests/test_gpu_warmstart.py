@@ -144,3 +144,69 @@ def test_learned_warm_start_keeps_accuracy(torch):
         assert rs["n_failed"] == 0 and c["err_x"] <= 1e-5 and c["err_y"] <= 1e-5
         assert abs(c["cost"] - p["cost"]) <= 1e-5 * p["cost"]
     assert res["learned"][2][0] > 0 and res["every_sweep"][2][1] > 0
+
+
+def test_prediction_of_the_converged_change_restarts_at_the_solution(torch):
+    # Pins the apply step of the learned start: the targets collected from a
+    # sweep (the change of the centred potential that each solve made) are
+    # handed back as the prediction for the same sweep from the same state.
+    # Every such cell then starts at its converged potential up to a
+    # constant, so its solve stops after the first loop with the same plan
+    # and potential; a wrong sign, scale, centring or cell index would send
+    # it away from the solution.
+    from paper_2001_10986_amd import dd
+    N = 64
+    mu, nu = datagen.small_pair(N, 4, seed=29)
+    # two levels down to eps = 2 h^2 (most unions <= 512 points), then the
+    # change to eps = h^2: the next sweep's cells are away from their solution
+    sched = datagen.eps_schedule(N, 2)
+    eps = sched[-1][1]
+    g = dd.Problem(mu, nu, sched[:-1], s=4, n_levels=2)
+    g.run_schedule()
+    g.set_eps(eps)
+    part = 0
+    s0 = g.export()
+    g.half_iterate(part)
+    r1 = g.cell_results()
+    e1 = g.export()
+    nc = len(r1["loops"])
+    X = torch.zeros((nc, 768), device="cuda")
+    T = torch.zeros((nc, 64), device="cuda")
+    M = torch.zeros((nc, 64), device="cuda")
+    ids = torch.zeros(nc, dtype=torch.int32, device="cuda")
+    n = g.collect_cells(X, T, M, ids)
+    assert n >= 20
+    g.import_state(s0["level"], s0["eps"], s0["row_ptr"], s0["col"], s0["val"], s0["alpha_a"],
+                   s0["alpha_b"])
+    Y = torch.zeros((nc, 64), device="cuda")
+    Y[ids[:n].long()] = T[:n]
+    g.set_warm_prediction(Y, 0.0)
+    g.half_iterate(part)
+    r2 = g.cell_results()
+    e2 = g.export()
+    warm = ids[:n].cpu().numpy()
+    print("cells", nc, "given a prediction", n, "loops first run", int(r1["loops"][warm].sum()),
+          "restart", int(r2["loops"][warm].sum()), "max", int(r2["loops"][warm].max()), flush=True)
+    assert r1["loops"][warm].min() >= 2
+    assert r2["loops"][warm].max() <= 2
+    # the other cells started where they did the first time
+    rest = np.setdiff1d(np.arange(nc), warm)
+    assert np.array_equal(r1["loops"][rest], r2["loops"][rest])
+    # potentials: the converged ones up to one constant per cell (cell
+    # geometry from the oracle's partition tables)
+    from oracle import ddo
+    cells_p = ddo.Oracle(mu, nu, s=4, n_levels=1, eps=eps).cells(part)  # 64x64 geometry
+    d = (e2["alpha_a"] - e1["alpha_a"]) / eps
+    bw = N // 4
+    for k in warm:
+        blk = np.concatenate([d[4 * (b // bw):4 * (b // bw) + 4, 4 * (b % bw):4 * (b % bw) + 4].ravel()
+                              for b in cells_p[k] if b >= 0])
+        assert np.ptp(blk) < 1e-5, (k, np.ptp(blk))
+    # and the plans: the basic marginals of both runs
+    bm1 = np.zeros((len(e1["row_ptr"]) - 1, N * N))
+    bm2 = np.zeros_like(bm1)
+    for bm, e in ((bm1, e1), (bm2, e2)):
+        for b in range(bm.shape[0]):
+            bm[b, e["col"][e["row_ptr"][b]:e["row_ptr"][b + 1]]] = \
+                e["val"][e["row_ptr"][b]:e["row_ptr"][b + 1]]
+    assert np.abs(bm1 - bm2).max() < 1e-5 * bm1.sum(axis=1).max()
