@@ -234,6 +234,15 @@ static double phi1(double b) {
   return expm1(b) - b;
 }
 
+/* Cost of moving mass between pixels (dr, dc) apart, in units of h^p:
+ * c(x,y) = h(x - y) with h(z) = |z|^p, p > 1 strictly convex (Sec. 7.1; the
+ * quadratic cost p = 2 is the paper's experiments, exact in integers). */
+static double cost_units(double dr, double dc, double p) {
+  double d2 = dr * dr + dc * dc;
+  if (p == 2.0) return d2;
+  return d2 > 0 ? pow(d2, 0.5 * p) : 0.0;
+}
+
 /* Newton iterations from F (loops it0+1 ...); same outputs as sinkhorn_log.
  * Each iteration is one Y-iteration (a loop), the stopping test, then either
  * a damped Newton step or, when the line search fails or after
@@ -248,7 +257,8 @@ static double phi1(double b) {
  *     c_y = sum_x p_x(y) a(x) -- both terms are non-negative sums, so the
  *     test stays meaningful when the increase is far below the size of Phi. */
 static int newton_log(int nx, const int* xr, const int* xc, const double* mu, int ny,
-                      const int* yr, const int* yc, const double* nu, double lam, double tol,
+                      const int* yr, const int* yc, const double* nu, double lam, double cp,
+                      double tol,
                       int it0, int maxit, double* F, double* G, int* loops, double* err_out) {
   int n = 0;
   for (int i = 0; i < nx; i++) n += mu[i] > 0;
@@ -283,14 +293,14 @@ static int newton_log(int nx, const int* xr, const int* xc, const double* mu, in
       for (int a = 0; a < n; a++) {
         int i = act[a];
         double dr = xr[i] - yr[j], dc = xc[i] - yc[j];
-        double e = F[i] + lm[a] - lam * (dr * dr + dc * dc);
+        double e = F[i] + lm[a] - lam * cost_units(dr, dc, cp);
         if (e > m) m = e;
       }
       double s = 0;
       for (int a = 0; a < n; a++) {
         int i = act[a];
         double dr = xr[i] - yr[j], dc = xc[i] - yc[j];
-        double v = exp(F[i] + lm[a] - lam * (dr * dr + dc * dc) - m);
+        double v = exp(F[i] + lm[a] - lam * cost_units(dr, dc, cp) - m);
         P[(size_t)a * ny + j] = v;
         s += v;
       }
@@ -373,14 +383,15 @@ static int newton_log(int nx, const int* xr, const int* xc, const double* mu, in
 
 /* Log-domain Sinkhorn of Remark "Sinkhorn algorithm", in the dual variables
  * F = f/eps, G = g/eps, with plan pi(x,y) = exp(F(x)+G(y)-C(x,y)) mu(x) nu(y)
- * and C = lam*|x-y|^2 (integer pixel offsets).  Warm start F, first a
+ * and C = lam*|x-y|^p (integer pixel offsets, cost_units).  Warm start F, first a
  * Y-iteration; after each Y-iteration the L1 error of the X-marginal is
  * checked and the solver stops there, so the Y-marginal holds exactly
  * (Sec. 6.2).  Returns 0 when converged, 1 at the iteration cap, 2 when a
  * value went non-finite. */
 static int sinkhorn_log(int nx, const int* xr, const int* xc, const double* mu,
                         int ny, const int* yr, const int* yc, const double* nu,
-                        double lam, double tol, int maxit, int accel, int newton_after,
+                        double lam, double cp, double tol, int maxit, int accel,
+                        int newton_after,
                         double* F, double* G, double* Fh, int* loops, double* err_out,
                         int* used_newton) {
   double* lmu = (double*)malloc(sizeof(double) * (size_t)nx);
@@ -406,13 +417,13 @@ static int sinkhorn_log(int nx, const int* xr, const int* xc, const double* mu,
       double m = -INFINITY;
       for (int i = 0; i < nx; i++) {
         double dr = xr[i] - yr[j], dc = xc[i] - yc[j];
-        double e = F[i] + lmu[i] - lam * (dr * dr + dc * dc);
+        double e = F[i] + lmu[i] - lam * cost_units(dr, dc, cp);
         if (e > m) m = e;
       }
       double s = 0;
       for (int i = 0; i < nx; i++) {
         double dr = xr[i] - yr[j], dc = xc[i] - yc[j];
-        s += exp(F[i] + lmu[i] - lam * (dr * dr + dc * dc) - m);
+        s += exp(F[i] + lmu[i] - lam * cost_units(dr, dc, cp) - m);
       }
       G[j] = -(m + log(s));
     }
@@ -423,13 +434,13 @@ static int sinkhorn_log(int nx, const int* xr, const int* xc, const double* mu,
       double m = -INFINITY;
       for (int j = 0; j < ny; j++) {
         double dr = xr[i] - yr[j], dc = xc[i] - yc[j];
-        double e = G[j] + lnu[j] - lam * (dr * dr + dc * dc);
+        double e = G[j] + lnu[j] - lam * cost_units(dr, dc, cp);
         if (e > m) m = e;
       }
       double s = 0;
       for (int j = 0; j < ny; j++) {
         double dr = xr[i] - yr[j], dc = xc[i] - yc[j];
-        s += exp(G[j] + lnu[j] - lam * (dr * dr + dc * dc) - m);
+        s += exp(G[j] + lnu[j] - lam * cost_units(dr, dc, cp) - m);
       }
       Fh[i] = -(m + log(s));
       if (mu[i] > 0) err += mu[i] * fabs(exp(F[i] - Fh[i]) - 1.0);
@@ -457,7 +468,7 @@ static int sinkhorn_log(int nx, const int* xr, const int* xc, const double* mu,
       free(lnu);
       free(Fp);
       *used_newton = 1;
-      return newton_log(nx, xr, xc, mu, ny, yr, yc, nu, lam, tol, it, maxit, F, G, loops,
+      return newton_log(nx, xr, xc, mu, ny, yr, yc, nu, lam, cp, tol, it, maxit, F, G, loops,
                         err_out);
     }
   }
@@ -470,15 +481,16 @@ static int sinkhorn_log(int nx, const int* xr, const int* xc, const double* mu,
   return rc;
 }
 
-int ddo_cell_solve(int nx, const int* xr, const int* xc, const double* mu, int ny,
-                   const int* yr, const int* yc, const double* nu, double lam,
-                   double tol, int max_iter, int accel, int newton_after, double* F,
-                   double* G, double* plan, int* loops, double* err) {
-  if (nx <= 0 || ny <= 0 || !(lam > 0) || max_iter < 1) return -1;
+int ddo_cell_solve_p(int nx, const int* xr, const int* xc, const double* mu, int ny,
+                     const int* yr, const int* yc, const double* nu, double lam, double cost_p,
+                     double tol, int max_iter, int accel, int newton_after, double* F,
+                     double* G, double* plan, int* loops, double* err) {
+  if (nx <= 0 || ny <= 0 || !(lam > 0) || max_iter < 1 || !(cost_p > 1)) return -1;
   double* Fh = (double*)malloc(sizeof(double) * (size_t)nx);
   if (!Fh) return -2;
   int used = 0;
-  int rc = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nu, lam, tol, max_iter, accel,
+  const double cp = cost_p;
+  int rc = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nu, lam, cp, tol, max_iter, accel,
                         newton_after, F, G, Fh, loops, err, &used);
   free(Fh);
   if (used && rc >= 0) rc += 16;
@@ -488,11 +500,19 @@ int ddo_cell_solve(int nx, const int* xr, const int* xc, const double* mu, int n
         double dr = xr[i] - yr[j], dc = xc[i] - yc[j];
         plan[(size_t)i * ny + j] =
             (mu[i] > 0 && nu[j] > 0)
-                ? exp(F[i] + G[j] - lam * (dr * dr + dc * dc)) * mu[i] * nu[j]
+                ? exp(F[i] + G[j] - lam * cost_units(dr, dc, cp)) * mu[i] * nu[j]
                 : 0.0;
       }
   }
   return rc;
+}
+
+int ddo_cell_solve(int nx, const int* xr, const int* xc, const double* mu, int ny,
+                   const int* yr, const int* yc, const double* nu, double lam,
+                   double tol, int max_iter, int accel, int newton_after, double* F,
+                   double* G, double* plan, int* loops, double* err) {
+  return ddo_cell_solve_p(nx, xr, xc, mu, ny, yr, yc, nu, lam, 2.0, tol, max_iter, accel,
+                          newton_after, F, G, plan, loops, err);
 }
 
 /* ------------------------------------------------------------ one cell */
@@ -586,7 +606,8 @@ static void balance(int nq, int ny, double* const* nuq, const double* mass_mu) {
 static void solve_cell(const ddo_ctx* c, int part, const cell_t* C, cell_out_t* o) {
   const lvl_t* l = &c->L[c->lev];
   const int s = c->s, nq = C->nq, nx = nq * s * s;
-  const double eps = c->eps, lam = l->h * l->h / eps;
+  const double cp = c->opt.cost_p, hp = pow(l->h, cp);
+  const double eps = c->eps, lam = hp / eps;
   memset(o, 0, sizeof(*o));
   o->nq = nq;
   int32_t* ys = NULL;
@@ -621,7 +642,7 @@ static void solve_cell(const ddo_ctx* c, int part, const cell_t* C, cell_out_t* 
   double tol = c->opt.err_tol * muJ, err = 0;
   int loops = 0;
   int used = 0;
-  int rc = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nuJ, lam, tol, c->opt.max_iter,
+  int rc = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nuJ, lam, cp, tol, c->opt.max_iter,
                         c->opt.accel, c->opt.newton_after, F, G, Fh, &loops, &err, &used);
   o->loops = loops;
   if (rc != 0 && c->opt.safeguard) {
@@ -630,11 +651,11 @@ static void solve_cell(const ddo_ctx* c, int part, const cell_t* C, cell_out_t* 
      * doubling, warm-started from the stored potential. */
     int l2 = 0, l3 = 0;
     for (int k = 0; k < nx; k++) F[k] = F0[k] * 0.5;
-    int r2 = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nuJ, lam * 0.5, tol, c->opt.max_iter,
+    int r2 = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nuJ, lam * 0.5, cp, tol, c->opt.max_iter,
                           c->opt.accel, c->opt.newton_after, F, G, Fh, &l2, &err, &used);
     if (r2 != 2) {
       for (int k = 0; k < nx; k++) F[k] *= 2.0;
-      rc = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nuJ, lam, tol, c->opt.max_iter,
+      rc = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nuJ, lam, cp, tol, c->opt.max_iter,
                         c->opt.accel, c->opt.newton_after, F, G, Fh, &l3, &err, &used);
     } else {
       rc = 2;
@@ -659,11 +680,11 @@ static void solve_cell(const ddo_ctx* c, int part, const cell_t* C, cell_out_t* 
     int q = k / (s * s);
     for (int j = 0; j < ny; j++) {
       double dr = xr[k] - yr[j], dc = xc[k] - yc[j];
-      double d2 = dr * dr + dc * dc;
-      double e = F[k] + G[j] - lam * d2;
+      double cu = cost_units(dr, dc, cp);
+      double e = F[k] + G[j] - lam * cu;
       double pi = exp(e) * mu[k] * nuJ[j];
       nuq[q][j] += pi;
-      double cxy = l->h * l->h * d2;
+      double cxy = hp * cu;
       cost += cxy * pi;
       if (pi > 0) {
         double nug = l->nu[ys[j]];
@@ -781,11 +802,13 @@ int ddo_init(const double* mu, const double* nu, int H, int W, int s, int nlev, 
     sn += nu[p];
   }
   if (fabs(sm - 1) > 1e-9 || fabs(sn - 1) > 1e-9) return -1;
+  if (!(opt->cost_p == 0 || opt->cost_p > 1)) return -1;
   ddo_ctx* c = calloc(1, sizeof(ddo_ctx));
   if (!c) return -2;
   c->nlev = nlev;
   c->s = s;
   c->opt = *opt;
+  if (c->opt.cost_p == 0) c->opt.cost_p = 2.0;
   c->eps = eps;
   c->L = calloc((size_t)nlev, sizeof(lvl_t));
   int mx = H > W ? H : W;

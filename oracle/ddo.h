@@ -19,7 +19,7 @@
  *    level is the 2x2 block-sum push-forward of the next finer one (Sec. 6.4).
  *  - pixel (r,c) of a level with spacing h sits at ((c+1/2)h, (r+1/2)h);
  *    c(x,y) = |x-y|^2 (Sec. 7.1).  h = 1/max(H,W) at the finest level and
- *    doubles per coarser level.
+ *    doubles per coarser level.  Optionally c(x,y) = |x-y|^p, p > 1.
  *  - basic cells are s x s pixel blocks; partition A groups 2x2 basic cells,
  *    partition B the same offset by one basic cell (Sec. 7.1).  Basic cells
  *    in a composite cell are ordered row-major, pixels in a basic cell too.
@@ -44,6 +44,7 @@ typedef struct {
   int safeguard;     /* 1: re-solve failed cells at 2*eps, then eps (Sec. 7.4) */
   int accel;         /* 1: Chebyshev-accelerated X-iteration, 0: plain Sinkhorn */
   int newton_after;  /* >0: switch a cell to Newton steps after this many loops; 0: never */
+  double cost_p;     /* c(x,y) = |x-y|^p, p > 1 (Sec. 7.1: h(x-y), h strictly convex); 0 = 2 */
 } ddo_opts;
 
 typedef struct {
@@ -106,6 +107,12 @@ int ddo_cell_results(const ddo_ctx* c, double* cost, double* obj, double* err_x,
  * eps) is the warm start; on return G holds the Y potential of the last
  * Y-update and plan (nx*ny, row-major by x) the plan of that Y-update.
  * Returns 0 converged, 1 at the cap, 2 non-finite, +16 when Newton ran. */
+/* the same with c = lam*|x-y|^cost_p, cost_p > 1 */
+int ddo_cell_solve_p(int nx, const int* xr, const int* xc, const double* mu,
+                     int ny, const int* yr, const int* yc, const double* nu,
+                     double lam, double cost_p, double tol, int max_iter, int accel,
+                     int newton_after, double* F, double* G, double* plan, int* loops,
+                     double* err);
 int ddo_cell_solve(int nx, const int* xr, const int* xc, const double* mu,
                    int ny, const int* yr, const int* yc, const double* nu,
                    double lam, double tol, int max_iter, int accel, int newton_after,

@@ -16,7 +16,7 @@ _lib = None
 class Opts(C.Structure):
     _fields_ = [("err_tol", C.c_double), ("trunc", C.c_double), ("max_iter", C.c_int),
                 ("n_threads", C.c_int), ("safeguard", C.c_int), ("accel", C.c_int),
-                ("newton_after", C.c_int)]
+                ("newton_after", C.c_int), ("cost_p", C.c_double)]
 
 
 class Stage(C.Structure):
@@ -67,6 +67,10 @@ def lib():
         _lib.ddo_cell_solve.argtypes = ([C.c_int] + [C.c_void_p] * 3 + [C.c_int] + [C.c_void_p] * 3
                                         + [C.c_double, C.c_double, C.c_int, C.c_int, C.c_int]
                                         + [C.c_void_p] * 5)
+        _lib.ddo_cell_solve_p.argtypes = ([C.c_int] + [C.c_void_p] * 3 + [C.c_int]
+                                          + [C.c_void_p] * 3
+                                          + [C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
+                                             C.c_int] + [C.c_void_p] * 5)
     return _lib
 
 
@@ -82,13 +86,14 @@ class Oracle:
     """One problem instance of the oracle; mirrors the C-ABI of the GPU library."""
 
     def __init__(self, mu, nu, s=4, n_levels=1, eps=1.0, err_tol=1e-5, trunc=1e-15,
-                 max_iter=50000, n_threads=0, safeguard=1, accel=1, newton_after=384):
+                 max_iter=50000, n_threads=0, safeguard=1, accel=1, newton_after=384,
+                 cost_p=2.0):
         mu = np.ascontiguousarray(mu, dtype=np.float64)
         nu = np.ascontiguousarray(nu, dtype=np.float64)
         assert mu.shape == nu.shape and mu.ndim == 2
         self.H, self.W = mu.shape
         self.s, self.n_levels = s, n_levels
-        o = Opts(err_tol, trunc, max_iter, n_threads, safeguard, accel, newton_after)
+        o = Opts(err_tol, trunc, max_iter, n_threads, safeguard, accel, newton_after, cost_p)
         h = C.c_void_p()
         rc = lib().ddo_init(_dp(mu), _dp(nu), self.H, self.W, s, n_levels, eps, C.byref(o),
                             C.byref(h))
@@ -201,9 +206,11 @@ class Oracle:
         return out
 
 
-def cell_solve(xr, xc, mu, yr, yc, nu, lam, tol, max_iter, F0=None, accel=0, newton_after=0):
+def cell_solve(xr, xc, mu, yr, yc, nu, lam, tol, max_iter, F0=None, accel=0, newton_after=0,
+               cost_p=2.0):
     """Solve one cell problem with the oracle's log-domain Sinkhorn (optionally
-    accelerated, optionally switching to Newton steps after newton_after loops)."""
+    accelerated, optionally switching to Newton steps after newton_after loops);
+    cost lam * |dx|^cost_p in units of eps."""
     xr = np.ascontiguousarray(xr, dtype=np.int32)
     xc = np.ascontiguousarray(xc, dtype=np.int32)
     yr = np.ascontiguousarray(yr, dtype=np.int32)
@@ -216,9 +223,9 @@ def cell_solve(xr, xc, mu, yr, yc, nu, lam, tol, max_iter, F0=None, accel=0, new
     plan = np.zeros((nx, ny))
     loops = C.c_int()
     err = C.c_double()
-    rc = lib().ddo_cell_solve(nx, _p(xr), _p(xc), _p(mu), ny, _p(yr), _p(yc), _p(nu), lam, tol,
-                              max_iter, accel, newton_after, _p(F), _p(G), _p(plan),
-                              C.byref(loops), C.byref(err))
+    rc = lib().ddo_cell_solve_p(nx, _p(xr), _p(xc), _p(mu), ny, _p(yr), _p(yc), _p(nu), lam,
+                                cost_p, tol, max_iter, accel, newton_after, _p(F), _p(G),
+                                _p(plan), C.byref(loops), C.byref(err))
     if rc < 0:
         raise ValueError(f"ddo_cell_solve failed ({rc})")
     return {"F": F, "G": G, "plan": plan, "loops": loops.value, "err": err.value, "rc": rc & 15,

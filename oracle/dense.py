@@ -112,11 +112,13 @@ def dd_dense(C, mu, nu, eps, cells_a, cells_b, basic, pi0, n_half, tol=1e-13,
     return plans
 
 
-def grid_cost(H, W, h):
-    """Dense |x-y|^2 between the pixel centres of an H x W grid with spacing h."""
+def grid_cost(H, W, h, p=2.0):
+    """Dense |x-y|^p between the pixel centres of an H x W grid with spacing h."""
     r, c = np.divmod(np.arange(H * W), W)
-    d2 = (r[:, None] - r[None, :]) ** 2 + (c[:, None] - c[None, :]) ** 2
-    return d2.astype(np.float64) * h * h
+    d2 = ((r[:, None] - r[None, :]) ** 2 + (c[:, None] - c[None, :]) ** 2).astype(np.float64)
+    if p == 2.0:
+        return d2 * h * h
+    return np.sqrt(d2) ** p * h ** p
 
 
 def grid_partitions(H, W, s):
@@ -148,10 +150,11 @@ def grid_partitions(H, W, s):
     return basic, parts[0], parts[1]
 
 
-def monotone_w2sq(x, a, y, b):
+def monotone_w2sq(x, a, y, b, p=2.0):
     """W2^2 between sum a_i delta_{x_i} and sum b_j delta_{y_j} on the line
     (north-west corner rule on the sorted supports: the optimal plan of a
-    strictly convex cost h(x-y) is the monotone one)."""
+    strictly convex cost h(x-y) is the monotone one); with p != 2 the cost
+    of that plan for |x-y|^p."""
     ix, iy = np.argsort(x), np.argsort(y)
     x, a = np.asarray(x, float)[ix], np.asarray(a, float)[ix]
     y, b = np.asarray(y, float)[iy], np.asarray(b, float)[iy]
@@ -160,7 +163,7 @@ def monotone_w2sq(x, a, y, b):
     tot = 0.0
     while i < len(x) and j < len(y):
         m = min(ra, rb)
-        tot += m * (x[i] - y[j]) ** 2
+        tot += m * abs(x[i] - y[j]) ** p
         ra -= m
         rb -= m
         if ra <= 1e-300:
