@@ -4,8 +4,9 @@
  * Schmitzer, "Domain decomposition for entropy regularized optimal transport".
  *
  * The problem (eq. "Problem", Sec. 3): for probability images mu, nu on the
- * same H x W pixel grid and c(x,y) = |x-y|^2 (Sec. 7.1), minimise
- * eps*KL(pi | exp(-c/eps) mu (x) nu) over couplings pi of mu and nu.
+ * same H x W pixel grid and c(x,y) = |x-y|^2 (Sec. 7.1; optionally |x-y|^p,
+ * dd_options.cost_p), minimise eps*KL(pi | exp(-c/eps) mu (x) nu) over
+ * couplings pi of mu and nu.
  *
  * The state of a problem is the one of Algorithm 2: the Y-marginals nu_i of
  * the plan on every basic cell X_i (s x s pixel blocks) and the X-potentials
@@ -89,6 +90,10 @@ typedef struct {
   int inputs_on_device;    /* 1: mu, nu passed to dd_init are device pointers; default 0 */
   int timing;              /* 1: record HIP events around every kernel of a sweep; default 0 */
   void* stream;            /* hipStream_t for all work of the context; default NULL */
+  double cost_p;           /* cost c(x,y) = |x-y|^p, 1 < p <= 16: a cost h(x-y) with h strictly
+                              convex (Sec. 7.1, Sec. 8; Monge setting of Sec. 5); default 2,
+                              the quadratic cost of the paper's experiments.  eps is in units
+                              of that cost (h^p per pixel^p on the unit square) */
 } dd_options;
 
 /* Kernels of one sweep (indices of the ms_kernel arrays): 0 cell sizes scan,

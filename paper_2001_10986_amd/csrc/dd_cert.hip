@@ -38,7 +38,8 @@ __global__ void k_cert_fill(unsigned long long* M, double* S, long long npx, dou
 template <int PASS>
 __global__ void k_cert_y(const int64_t* row_off, const int* row_len, const int* col,
                          const double* alpha_hat, const double* mu, int W, int bw, int n_basic,
-                         double inv_eps, double h2, unsigned long long* M, double* S) {
+                         double inv_eps, double hp, double half_p, unsigned long long* M,
+                         double* S) {
   const int lane = threadIdx.x & 63;
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
   const int n_waves = (gridDim.x * blockDim.x) >> 6;
@@ -57,8 +58,8 @@ __global__ void k_cert_y(const int64_t* row_off, const int* row_len, const int* 
           const long long px = (long long)xr * W + xc;
           const double mx = mu[px];
           if (!(mx > 0)) continue;
-          const double dr = xr - yr, dc = xc - yc;
-          const double t = (alpha_hat[px] - h2 * (dr * dr + dc * dc)) * inv_eps + log(mx);
+          const double t =
+              (alpha_hat[px] - hp * cost_units(xr - yr, xc - yc, half_p)) * inv_eps + log(mx);
           if (PASS == 0)
             acc = t > acc ? t : acc;
           else
@@ -219,8 +220,8 @@ void launch_cert_glue(const int* inc_ptr, const int* inc_e, const int* e_ia, con
 
 void launch_cert_y(const int64_t* row_off, const int* row_len, const int* col,
                    const double* alpha_hat, const double* mu, const double* nu, int H, int W,
-                   int bw, int n_basic, double eps, double h, double* scratch, double* beta_hat,
-                   double* sums, hipStream_t st) {
+                   int bw, int n_basic, double eps, double h, double half_p, double* scratch,
+                   double* beta_hat, double* sums, hipStream_t st) {
   const long long npx = (long long)H * W;
   unsigned long long* M = (unsigned long long*)scratch;
   double* S = scratch + npx;
@@ -228,9 +229,11 @@ void launch_cert_y(const int64_t* row_off, const int* row_len, const int* col,
                      npx, sums);
   const unsigned blocks = (unsigned)((n_basic + 3) / 4 < 65535 ? (n_basic + 3) / 4 : 65535);
   hipLaunchKernelGGL(k_cert_y<0>, dim3(blocks), dim3(256), 0, st, row_off, row_len, col,
-                     alpha_hat, mu, W, bw, n_basic, 1.0 / eps, h * h, M, S);
+                     alpha_hat, mu, W, bw, n_basic, 1.0 / eps, std::pow(h, 2.0 * half_p), half_p,
+                     M, S);
   hipLaunchKernelGGL(k_cert_y<1>, dim3(blocks), dim3(256), 0, st, row_off, row_len, col,
-                     alpha_hat, mu, W, bw, n_basic, 1.0 / eps, h * h, M, S);
+                     alpha_hat, mu, W, bw, n_basic, 1.0 / eps, std::pow(h, 2.0 * half_p), half_p,
+                     M, S);
   hipLaunchKernelGGL(k_cert_sums, dim3(1024), dim3(256), 0, st, alpha_hat, mu, nu, M, S, npx,
                      eps, beta_hat, sums);
 }

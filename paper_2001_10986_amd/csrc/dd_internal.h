@@ -23,7 +23,8 @@ struct HalfParams {
   int H, W, bh, bw;
   int n_cells, n_basic;
   int part;
-  double h, eps, lam;          // lam = h^2 / eps (cost in units of eps per pixel^2)
+  double h, eps, lam;          // lam = h^p / eps (cost in units of eps per pixel^p)
+  double half_p, hp;           // cost c = |x-y|^p: p/2 (1 for the quadratic cost) and h^p
   double err_tol, trunc;
   int max_iter, safeguard, accel;
   int newton_after;            // >0: hand a cell to Newton steps after this many loops
@@ -81,6 +82,15 @@ struct SweepSched {
   int stream_wgs;              // workgroups the streamed-solver buffers are sized for
   int wg_cells;                // register solvers: cells per workgroup (0: until the queue is empty)
 };
+
+// c(x,y) / h^p for pixel offsets (dr, dc): |d|^p with p = 2 half_p, a cost
+// h(x - y) with h strictly convex (Sec. 7.1); exact in integers for the
+// quadratic cost (half_p == 1, the paper's experiments).
+__device__ __forceinline__ double cost_units(int dr, int dc, double half_p) {
+  const int d2 = dr * dr + dc * dc;
+  if (half_p == 1.0) return (double)d2;
+  return d2 > 0 ? exp(half_p * log((double)d2)) : 0.0;
+}
 
 struct IterStatsDev {
   double cost, obj, err;
@@ -188,7 +198,7 @@ void launch_cert_glue(const int* inc_ptr, const int* inc_e, const int* e_ia, con
                       double* work, double* V, double* info, hipStream_t st);
 void launch_cert_y(const int64_t* row_off, const int* row_len, const int* col,
                    const double* alpha_hat, const double* mu, const double* nu, int H, int W,
-                   int bw, int n_basic, double eps, double h, double* scratch, double* beta_hat,
-                   double* sums, hipStream_t st);
+                   int bw, int n_basic, double eps, double h, double half_p, double* scratch,
+                   double* beta_hat, double* sums, hipStream_t st);
 
 }  // namespace ddk

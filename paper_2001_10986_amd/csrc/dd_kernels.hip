@@ -822,6 +822,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
     float P[8][8];
     int status = 0, loops_all = 0;
     double lam = p.lam;
+    const bool quad = p.half_p == 1.0;  // quadratic cost: row/column parts separate
     const int phases = p.safeguard ? 3 : 1;
     bool converged = false, deferred = false;
     double err_last = 0;
@@ -855,7 +856,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
 #pragma unroll
             for (int j = 0; j < 8; j++) {
               const int dc = dc0 - j;
-              const double e = sh.Fmu[xg * 8 + j] - (ldr + lam * (double)(dc * dc));
+              const double e = sh.Fmu[xg * 8 + j] - (quad ? ldr + lam * (double)(dc * dc) : lam * cost_units(dr, dc, p.half_p));
               mloc = e > mloc ? e : mloc;
             }
 #pragma unroll
@@ -868,7 +869,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
 #pragma unroll
             for (int j = 0; j < 8; j++) {
               const int dc = dc0 - j;
-              const double e = sh.Fmu[xg * 8 + j] - (ldr + lam * (double)(dc * dc)) - mloc;
+              const double e = sh.Fmu[xg * 8 + j] - (quad ? ldr + lam * (double)(dc * dc) : lam * cost_units(dr, dc, p.half_p)) - mloc;
               P[j][t] = valid ? fast_exp2((float)(e * kLog2e)) : 0.0f;
             }
             if (xg == 0 && valid) mbuf[yi] = mloc;
@@ -958,7 +959,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
                 // G(y) + log nu_J(y) = log w(y) - m(y): the FP32 logarithm of w
                 // is enough for the next absorbed potential (the loops go on)
                 const double e = (double)(fast_log2(wy) * kLn2f) - mbuf[yi] -
-                                 lam * (double)(dr * dr + dc * dc);
+                                 lam * cost_units(dr, dc, p.half_p);
                 mm = e > mm ? e : mm;
               }
             }
@@ -991,7 +992,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
                 const int rc = sh.yrc[yi];
                 const int dr = (rc >> 16) - xr, dc = (rc & 0xffff) - (g.C0 + j);
                 const double e = (double)(fast_log2(wy) * kLn2f) - mbuf[yi] -
-                                 lam * (double)(dr * dr + dc * dc) - mm;
+                                 lam * cost_units(dr, dc, p.half_p) - mm;
                 s += (double)fast_exp2((float)(e * kLog2e));
               }
             }
@@ -1080,7 +1081,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
 #pragma unroll
         for (int j = 0; j < 8; j++) {
           const int dc = dc0 - j;
-          s = fmaf((float)(dr * dr + dc * dc), P[j][t] * uu[j], s);
+          s = fmaf((float)cost_units(dr, dc, p.half_p), P[j][t] * uu[j], s);
         }
         v[t] = s;
       }
@@ -1101,7 +1102,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
       vq[1] = nuJ * (s1 / S);
       vq[2] = nuJ * (s2 / S);
       vq[3] = nuJ * (s3 / S);
-      cost_y = nuJ * ((double)cp / S) * (p.h * p.h);
+      cost_y = nuJ * ((double)cp / S) * p.hp;
       // nu_J(y) (G(y) + log(nu_J(y)/nu(y))) - nu_J(y),  G(y) = -(m(y) + log S(y))
       const bool key_ok = (unsigned)key < (unsigned)(p.H * p.W);
       if (nuJ > 0 && key_ok) obj_y = nuJ * (-(mbuf[yi] + log(S)) + log(nuJ) - log(p.nu[key])) - nuJ;
@@ -1225,6 +1226,7 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
 
     int status = 0, loops_all = 0;
     double lam = p.lam;
+    const bool quad = p.half_p == 1.0;  // quadratic cost: row/column parts separate
     const int phases = p.safeguard ? 3 : 1;
     bool converged = false, deferred = false;
     const int xr = g.R0 + xg;
@@ -1265,7 +1267,7 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
 #pragma unroll
             for (int j = 0; j < 8; j++) {
               const int dc = dc0 - j;
-              const double e = sh.Fmu[xg * 8 + j] - (ldr + lam * (double)(dc * dc));
+              const double e = sh.Fmu[xg * 8 + j] - (quad ? ldr + lam * (double)(dc * dc) : lam * cost_units(dr, dc, p.half_p));
               mloc = e > mloc ? e : mloc;
             }
 #pragma unroll
@@ -1277,7 +1279,7 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
 #pragma unroll
             for (int j = 0; j < 8; j++) {
               const int dc = dc0 - j;
-              const double e = sh.Fmu[xg * 8 + j] - (ldr + lam * (double)(dc * dc)) - mloc;
+              const double e = sh.Fmu[xg * 8 + j] - (quad ? ldr + lam * (double)(dc * dc) : lam * cost_units(dr, dc, p.half_p)) - mloc;
               P[j][tt] = valid ? fast_exp2((float)(e * kLog2e)) : 0.0f;
             }
             if (xg == 0 && valid) mbuf[yi] = mloc;
@@ -1409,11 +1411,12 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
                   split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
                   const int dr = r - xr;
                   const double gl = -(mbuf[yi] + log((double)S)) + log((double)nf) -
-                                    lam * (double)(dr * dr);
+                                    (quad ? lam * (double)(dr * dr) : 0.0);
 #pragma unroll
                   for (int j = 0; j < 8; j++) {
                     const int dc = c - (g.C0 + j);
-                    const double e = gl - lam * (double)(dc * dc);
+                    const double e = gl - (quad ? lam * (double)(dc * dc)
+                                                : lam * cost_units(dr, dc, p.half_p));
                     mm[j] = e > mm[j] ? e : mm[j];
                   }
                 }
@@ -1455,11 +1458,13 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
                   split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
                   const int dr = r - xr;
                   const double gl = -(mbuf[yi] + log((double)S)) + log((double)nf) -
-                                    lam * (double)(dr * dr);
+                                    (quad ? lam * (double)(dr * dr) : 0.0);
 #pragma unroll
                   for (int j = 0; j < 8; j++) {
                     const int dc = c - (g.C0 + j);
-                    const double e = gl - lam * (double)(dc * dc) - sh.mx[xg * 8 + j];
+                    const double e = gl - (quad ? lam * (double)(dc * dc)
+                                                : lam * cost_units(dr, dc, p.half_p)) -
+                                     sh.mx[xg * 8 + j];
                     sj[j] += (double)fast_exp2((float)(e * kLog2e));
                   }
                 }
@@ -1561,7 +1566,7 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
 #pragma unroll
           for (int j = 0; j < 8; j++) {
             const int dc = dc0 - j;
-            s = fmaf((float)(dr * dr + dc * dc), P[j][t] * uu[j], s);
+            s = fmaf((float)cost_units(dr, dc, p.half_p), P[j][t] * uu[j], s);
           }
           v[t] = s;
         }
@@ -1573,7 +1578,7 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
           const double s0 = sl_t, s1 = sr_t, s2 = sl_b, s3 = sr_b;
           const double S = (s0 + s1) + (s2 + s3);
           const double vq[4] = {nuJ * (s0 / S), nuJ * (s1 / S), nuJ * (s2 / S), nuJ * (s3 / S)};
-          cost_acc += nuJ * ((double)(c1 + c2) / S) * (p.h * p.h);
+          cost_acc += nuJ * ((double)(c1 + c2) / S) * p.hp;
           const bool key_ok = (unsigned)key < (unsigned)(p.H * p.W);
           if (nuJ > 0 && key_ok)
             obj_acc += nuJ * (-(mbuf[yi] + log(S)) + log(nuJ) - log(p.nu[key])) - nuJ;
@@ -1726,15 +1731,15 @@ DEVI double phi1d(double b) {
 // [1, 64] (the largest term is e^0), so the FP32 logarithm is accurate to
 // ~1e-7 absolute.
 template <class SH>
-DEVI double cond_plan(const SH& sh, int r, int c, int xs, double lam, double pk[4],
-                      int prec) {
+DEVI double cond_plan(const SH& sh, int r, int c, int xs, double lam, double half_p,
+                      double pk[4], int prec) {
   double e[4];
   double m = -INFINITY;
 #pragma unroll
   for (int k = 0; k < 4; k++) {
     const int x = xs + 16 * k;
     const int dr = r - sh.xr[x], dc = c - sh.xc[x];
-    e[k] = sh.Fmu[x] - lam * (double)(dr * dr + dc * dc);
+    e[k] = sh.Fmu[x] - lam * cost_units(dr, dc, half_p);
     m = e[k] > m ? e[k] : m;
   }
   m = row16_max(m);
@@ -1818,6 +1823,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
     long long n_trials = 0, n_wbuild = 0;
     bool converged = false;
     double lam = p.lam;
+    const bool quad = p.half_p == 1.0;  // quadratic cost: row/column parts separate
     const int phases = p.safeguard ? 3 : 1;
     for (int phase = 0; phase < phases; phase++) {
       if (phase == 1) {
@@ -1845,13 +1851,13 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
           double m = -INFINITY;
           for (int k = 0; k < 64; k++) {
             const int dr = r - sh.xr[k], dc = c - sh.xc[k];
-            const double e = sh.Fmu[k] - lam * (double)(dr * dr + dc * dc);
+            const double e = sh.Fmu[k] - lam * cost_units(dr, dc, p.half_p);
             m = e > m ? e : m;
           }
           double s = 0;
           for (int k = 0; k < 64; k++) {
             const int dr = r - sh.xr[k], dc = c - sh.xc[k];
-            const double e = sh.Fmu[k] - lam * (double)(dr * dr + dc * dc) - m;
+            const double e = sh.Fmu[k] - lam * cost_units(dr, dc, p.half_p) - m;
             s += ex(e, fp64);
           }
           const double nu = p.uni_nu[ub + yi];
@@ -1866,7 +1872,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
             int r, c;
             split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
             const int dr = r - sh.xr[x], dc = c - sh.xc[x];
-            const double e = G[yi] - lam * (double)(dr * dr + dc * dc);
+            const double e = G[yi] - lam * cost_units(dr, dc, p.half_p);
             if (e == -INFINITY) continue;
             if (e > m) {
               s = s * ex(m - e, fp64) + 1.0;
@@ -1940,7 +1946,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
             if (yi < U) {  // uniform within each 16-lane group
               int r, c;
               split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
-              const double lse = cond_plan(sh, r, c, xs, lam, pk, fp64 ? 2 : build_w ? 1 : 0);
+              const double lse = cond_plan(sh, r, c, xs, lam, p.half_p, pk, fp64 ? 2 : build_w ? 1 : 0);
               const double nu = p.uni_nu[ub + yi];
 #pragma unroll
               for (int k = 0; k < 4; k++) racc[k] += nu * pk[k];
@@ -2055,7 +2061,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
                     int r, c;
                     split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
                     double pk[4];
-                    cond_plan(sh, r, c, xs, lam, pk, fp64 ? 2 : 1);
+                    cond_plan(sh, r, c, xs, lam, p.half_p, pk, fp64 ? 2 : 1);
                     double a[4], cy = 0;
 #pragma unroll
                     for (int k = 0; k < 4; k++) {
@@ -2128,25 +2134,25 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
         double m = -INFINITY;
         for (int k = 0; k < 64; k++) {
           const int dr = r - sh.xr[k], dc = c - sh.xc[k];
-          const double e = sh.Fmu[k] - lam * (double)(dr * dr + dc * dc);
+          const double e = sh.Fmu[k] - lam * cost_units(dr, dc, p.half_p);
           m = e > m ? e : m;
         }
         for (int k = 0; k < 64; k++) {
           const int dr = r - sh.xr[k], dc = c - sh.xc[k];
-          const int d2 = dr * dr + dc * dc;
-          const double e = sh.Fmu[k] - lam * (double)d2 - m;
+          const double cu = cost_units(dr, dc, p.half_p);
+          const double e = sh.Fmu[k] - lam * cu - m;
           const double v = ex(e, fp64);
           const int qa = ((k >> 5) << 1) | ((k & 7) >> 2);
           sq[0] += qa == 0 ? v : 0.0;
           sq[1] += qa == 1 ? v : 0.0;
           sq[2] += qa == 2 ? v : 0.0;
           sq[3] += qa == 3 ? v : 0.0;
-          cs += v * (double)d2;
+          cs += v * cu;
         }
         const double nuJ = p.uni_nu[ub + yi];
         const double S = sq[0] + sq[1] + sq[2] + sq[3];
         _Pragma("unroll") for (int a = 0; a < 4; a++) vq[a] = nuJ * (sq[a] / S);
-        cost_acc += nuJ * (cs / S) * (p.h * p.h);
+        cost_acc += nuJ * (cs / S) * p.hp;
         const double Gy = gl - (nuJ > 0 ? log(nuJ) : 0.0);
         const bool key_ok = (unsigned)key < (unsigned)(p.H * p.W);
         obj_acc += (nuJ > 0 && key_ok) ? nuJ * (Gy + log(nuJ) - log(p.nu[key])) - nuJ : 0.0;

@@ -461,6 +461,7 @@ extern "C" void dd_options_default(dd_options* o) {
   o->inputs_on_device = 0;
   o->timing = 0;
   o->stream = nullptr;
+  o->cost_p = 2.0;
 }
 
 extern "C" void dd_free(dd_ctx* c) {
@@ -595,6 +596,8 @@ extern "C" dd_status dd_init(const double* mu, const double* nu, int H, int W, i
   if (!mu || !nu) return fail(nullptr, DD_EINVAL, "mu/nu is NULL");
   if (s != kS) return fail(nullptr, DD_EINVAL, "basic_cell must be %d", kS);
   if (nlev < 1 || nlev > 16) return fail(nullptr, DD_EINVAL, "n_levels out of range");
+  if (opt && !(opt->cost_p > 1.0 && opt->cost_p <= 16.0))
+    return fail(nullptr, DD_EINVAL, "cost exponent p must lie in (1, 16] (got %g)", opt->cost_p);
   if (H <= 0 || W <= 0 || W > 65536) return fail(nullptr, DD_EINVAL, "bad size");
   const int div = (2 * s) << (nlev - 1);
   if (H % div || W % div)
@@ -713,8 +716,10 @@ static HalfParams make_params(dd_ctx* c, int part) {
   p.n_basic = c->nb;
   p.part = part;
   p.h = l.h;
+  p.half_p = 0.5 * c->opt.cost_p;
+  p.hp = c->opt.cost_p == 2.0 ? l.h * l.h : std::pow(l.h, c->opt.cost_p);
   p.eps = c->eps;
-  p.lam = l.h * l.h / c->eps;
+  p.lam = p.hp / c->eps;
   p.err_tol = c->opt.err_tol;
   p.trunc = c->opt.trunc_threshold;
   p.max_iter = c->opt.max_sinkhorn_iter;
@@ -800,6 +805,8 @@ extern "C" dd_status dd_set_warm_prediction(dd_ctx* c, const float* y_dev, float
 
 extern "C" dd_status dd_set_warm_start(dd_ctx* c, dd_mlp* net, int policy, float min_rms) {
   if (!c || policy < 0 || policy > 3 || !(min_rms >= 0)) return DD_EINVAL;
+  if (net && c->opt.cost_p != 2.0)
+    return fail(c, DD_EINVAL, "the warm-start network's features assume the quadratic cost");
   if (net) {
     int n_in = 0, n_out = 0;
     dd_mlp_shape(net, &n_in, &n_out, nullptr, nullptr);
@@ -1350,7 +1357,7 @@ extern "C" dd_status dd_certificate(dd_ctx* c, dd_cert_report* r, double* alpha_
   hipLaunchKernelGGL(k_glue_apply, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, c->st,
                      c->alpha[0], dV, c->eps, l.H, l.W, ah);
   ddk::launch_cert_y(c->row_off, c->row_len, c->col, ah, l.mu, l.nu, l.H, l.W, l.bw, nb, c->eps,
-                     l.h, scr, bh, sums, c->st);
+                     l.h, 0.5 * c->opt.cost_p, scr, bh, sums, c->st);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(hs, sums, sizeof hs, hipMemcpyDeviceToHost, c->st);
   if (e == hipSuccess && alpha_hat)

@@ -34,7 +34,7 @@ def blob_image(H, W, n_blobs, seed, floor=1e-3, noise=0.0):
     return img / img.sum()
 
 
-def eps_schedule(N, n_levels, eps_start=1.0, final_eps=None):
+def eps_schedule(N, n_levels, eps_start=1.0, final_eps=None, p=2.0, level_factor=0.5):
     """Stage list [(level, eps, n_half_iterations)] of the multi-scale eps-scaling driver.
 
     Follows Sec. 7.1 ("Multi-scale and eps-scaling") in unit coordinates: on
@@ -42,15 +42,17 @@ def eps_schedule(N, n_levels, eps_start=1.0, final_eps=None):
     eps >= h_l^2/2; the first stage of a level runs 4 half-iterations
     (A,B,A,B), later ones 2; the next level starts at the last eps of the
     previous one (h_l^2/2 = 2 h_{l+1}^2).  On the finest level eps stops at
-    final_eps (default h^2) and 2 more half-iterations run there.
+    final_eps (default h^2) and 2 more half-iterations run there.  For a cost
+    |x-y|^p the thresholds are level_factor * h_l^p (default h_l^p / 2) and
+    the default final eps h^p.
     """
     if final_eps is None:
-        final_eps = (1.0 / N) ** 2
+        final_eps = (1.0 / N) ** p
     stages = []
     eps = float(eps_start)
     for lev in range(n_levels):
         Nl = N >> (n_levels - 1 - lev)
-        lo = 0.5 / Nl ** 2 if lev < n_levels - 1 else final_eps
+        lo = level_factor / Nl ** p if lev < n_levels - 1 else final_eps
         first = True
         while eps >= lo * (1 - 1e-12):
             stages.append([lev, eps, 4 if first else 2])

@@ -41,7 +41,7 @@ class Options(C.Structure):
     _fields_ = [("err_tol", C.c_double), ("trunc_threshold", C.c_double),
                 ("max_sinkhorn_iter", C.c_int), ("safeguard", C.c_int), ("accel", C.c_int),
                 ("newton_after", C.c_int), ("precision", C.c_int), ("inputs_on_device", C.c_int),
-                ("timing", C.c_int), ("stream", C.c_void_p)]
+                ("timing", C.c_int), ("stream", C.c_void_p), ("cost_p", C.c_double)]
 
 
 N_KERNELS, N_BINS = 12, 7
@@ -211,7 +211,7 @@ class Problem:
 
     def __init__(self, mu, nu, schedule, s=4, n_levels=1, err_tol=1e-5, trunc=1e-15,
                  max_iter=50000, safeguard=1, stream=None, timing=False, accel=1,
-                 newton_after=384, precision=DD_PREC_SPLIT):
+                 newton_after=384, precision=DD_PREC_SPLIT, cost_p=2.0):
         opt = Options()
         lib.dd_options_default(C.byref(opt))
         opt.err_tol, opt.trunc_threshold = err_tol, trunc
@@ -220,6 +220,7 @@ class Problem:
         opt.accel = int(accel)
         opt.newton_after = int(newton_after)
         opt.precision = int(precision)
+        opt.cost_p = float(cost_p)
         on_dev = hasattr(mu, "data_ptr") and getattr(mu, "is_cuda", False)
         if on_dev:
             import torch

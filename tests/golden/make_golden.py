@@ -12,7 +12,7 @@ the objective, the L1 marginal errors, nnz, and per basic cell (all of them,
 or a seeded sample) the mass |nu_i| and the barycentre of nu_i in pixel
 units of the finest grid (row, col): the basic-cell transport targets.
 
-Usage: python tests/golden/make_golden.py {config2,config3} [n_threads]
+Usage: python tests/golden/make_golden.py {config2,config3,power3} [n_threads]
 (config 3 takes about an hour and a half on 8 cores).
 """
 import json
@@ -51,7 +51,7 @@ def basic_summary(o, W, sample=None):
 def run(name, mu, nu, cfg, n_threads, sample=None):
     t = time.time()
     o = ddo.Oracle(mu, nu, s=cfg["s"], n_levels=cfg["n_levels"], eps=cfg["stages"][0][1],
-                   accel=0, newton_after=0, n_threads=n_threads)
+                   accel=0, newton_after=0, n_threads=n_threads, cost_p=cfg.get("cost_p", 2.0))
     st = o.run_schedule(cfg["stages"])
     c = o.cost()
     out = {
@@ -59,6 +59,7 @@ def run(name, mu, nu, cfg, n_threads, sample=None):
         "oracle": "FP64, plain Sinkhorn per cell (accel 0, newton_after 0), Err 1e-5, "
                   "trunc 1e-15, loop cap 50000 with the eps safeguard",
         "stages": [list(s) for s in cfg["stages"]],
+        "cost_p": cfg.get("cost_p", 2.0),
         "w2_sq": c["cost"], "obj": c["obj"], "err_x": c["err_x"], "err_y": c["err_y"],
         "mass_drift": c["mass_drift"], "nnz": int(c["nnz"]),
         "loops_total": int(st["loops_total"]), "loops_max": int(st["loops_max"]),
@@ -76,6 +77,13 @@ def main():
         mu, nu, cfg = datagen.config2_pair()
         out = run("config 2: 256x256 pair (images 0, 1; 8 blobs), levels 64->256, "
                   "eps 1 -> (1/256)^2", mu, nu, cfg, n_threads)
+    elif which == "power3":
+        mu, nu = datagen.small_pair(64, 4, seed=17)
+        cfg = dict(s=4, n_levels=2, cost_p=3.0,
+                   stages=datagen.eps_schedule(64, 2, p=3.0, level_factor=16.0,
+                                               final_eps=16.0 / 64 ** 3))
+        out = run("64x64 pair (4 blobs, seed 17), cost |x-y|^3, levels 32->64, eps 1 -> "
+                  "16 (1/64)^3", mu, nu, cfg, n_threads)
     elif which == "config3":
         mu, nu, cfg = datagen.config3_pair()
         out = run("config 3: 1024x1024 pair (16 blobs + U[0,0.1]*max noise), levels "
