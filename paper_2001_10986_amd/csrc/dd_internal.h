@@ -81,6 +81,7 @@ struct SweepSched {
   float* stream_nu;            // streamed solver: nu_J(y) in FP32, kStreamMaxU per workgroup
   int stream_wgs;              // workgroups the streamed-solver buffers are sized for
   int wg_cells;                // register solvers: cells per workgroup (0: until the queue is empty)
+  int quad;                    // 1: every problem of the sweep has the quadratic cost
 };
 
 // c(x,y) / h^p for pixel offsets (dr, dc): |d|^p with p = 2 half_p, a cost
@@ -90,6 +91,17 @@ __device__ __forceinline__ double cost_units(int dr, int dc, double half_p) {
   const int d2 = dr * dr + dc * dc;
   if (half_p == 1.0) return (double)d2;
   return d2 > 0 ? exp(half_p * log((double)d2)) : 0.0;
+}
+
+// The solvers are compiled twice: QUAD for sweeps whose problems all have the
+// quadratic cost (integer |d|^2, no transcendental work), and a general
+// instantiation that forms every cost through cost_units.
+template <bool QUAD>
+__device__ __forceinline__ double cost_q(int dr, int dc, double half_p) {
+  if constexpr (QUAD)
+    return (double)(dr * dr + dc * dc);
+  else
+    return cost_units(dr, dc, half_p);
 }
 
 struct IterStatsDev {

@@ -754,7 +754,7 @@ DEVI XUpdate x_update(float r, double mu, float u, float* lup, float* unew_out, 
   return o;
 }
 
-template <int NW>
+template <int NW, bool QUAD>
 __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restrict__ P,
                                                        SweepSched s, int bin) {
   __shared__ RegShared<NW> sh;
@@ -822,7 +822,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
     float P[8][8];
     int status = 0, loops_all = 0;
     double lam = p.lam;
-    const bool quad = p.half_p == 1.0;  // quadratic cost: row/column parts separate
+    constexpr bool quad = QUAD;  // quadratic cost: row and column parts separate
     const int phases = p.safeguard ? 3 : 1;
     bool converged = false, deferred = false;
     double err_last = 0;
@@ -856,7 +856,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
 #pragma unroll
             for (int j = 0; j < 8; j++) {
               const int dc = dc0 - j;
-              const double e = sh.Fmu[xg * 8 + j] - (quad ? ldr + lam * (double)(dc * dc) : lam * cost_units(dr, dc, p.half_p));
+              const double e = sh.Fmu[xg * 8 + j] - (quad ? ldr + lam * (double)(dc * dc) : lam * cost_q<QUAD>(dr, dc, p.half_p));
               mloc = e > mloc ? e : mloc;
             }
 #pragma unroll
@@ -869,7 +869,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
 #pragma unroll
             for (int j = 0; j < 8; j++) {
               const int dc = dc0 - j;
-              const double e = sh.Fmu[xg * 8 + j] - (quad ? ldr + lam * (double)(dc * dc) : lam * cost_units(dr, dc, p.half_p)) - mloc;
+              const double e = sh.Fmu[xg * 8 + j] - (quad ? ldr + lam * (double)(dc * dc) : lam * cost_q<QUAD>(dr, dc, p.half_p)) - mloc;
               P[j][t] = valid ? fast_exp2((float)(e * kLog2e)) : 0.0f;
             }
             if (xg == 0 && valid) mbuf[yi] = mloc;
@@ -959,7 +959,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
                 // G(y) + log nu_J(y) = log w(y) - m(y): the FP32 logarithm of w
                 // is enough for the next absorbed potential (the loops go on)
                 const double e = (double)(fast_log2(wy) * kLn2f) - mbuf[yi] -
-                                 lam * cost_units(dr, dc, p.half_p);
+                                 lam * cost_q<QUAD>(dr, dc, p.half_p);
                 mm = e > mm ? e : mm;
               }
             }
@@ -992,7 +992,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
                 const int rc = sh.yrc[yi];
                 const int dr = (rc >> 16) - xr, dc = (rc & 0xffff) - (g.C0 + j);
                 const double e = (double)(fast_log2(wy) * kLn2f) - mbuf[yi] -
-                                 lam * cost_units(dr, dc, p.half_p) - mm;
+                                 lam * cost_q<QUAD>(dr, dc, p.half_p) - mm;
                 s += (double)fast_exp2((float)(e * kLog2e));
               }
             }
@@ -1081,7 +1081,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
 #pragma unroll
         for (int j = 0; j < 8; j++) {
           const int dc = dc0 - j;
-          s = fmaf((float)cost_units(dr, dc, p.half_p), P[j][t] * uu[j], s);
+          s = fmaf((float)cost_q<QUAD>(dr, dc, p.half_p), P[j][t] * uu[j], s);
         }
         v[t] = s;
       }
@@ -1175,6 +1175,7 @@ DEVI float4* tile_at(float* base, int slab, int wave, int k, int lane) {
   return reinterpret_cast<float4*>(base) + ((size_t)((slab * kSW + wave) * 16 + k) * 64 + lane);
 }
 
+template <bool QUAD>
 __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __restrict__ P,
                                                         SweepSched s) {
   __shared__ StreamShared sh;
@@ -1226,7 +1227,7 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
 
     int status = 0, loops_all = 0;
     double lam = p.lam;
-    const bool quad = p.half_p == 1.0;  // quadratic cost: row/column parts separate
+    constexpr bool quad = QUAD;  // quadratic cost: row and column parts separate
     const int phases = p.safeguard ? 3 : 1;
     bool converged = false, deferred = false;
     const int xr = g.R0 + xg;
@@ -1267,7 +1268,7 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
 #pragma unroll
             for (int j = 0; j < 8; j++) {
               const int dc = dc0 - j;
-              const double e = sh.Fmu[xg * 8 + j] - (quad ? ldr + lam * (double)(dc * dc) : lam * cost_units(dr, dc, p.half_p));
+              const double e = sh.Fmu[xg * 8 + j] - (quad ? ldr + lam * (double)(dc * dc) : lam * cost_q<QUAD>(dr, dc, p.half_p));
               mloc = e > mloc ? e : mloc;
             }
 #pragma unroll
@@ -1279,7 +1280,7 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
 #pragma unroll
             for (int j = 0; j < 8; j++) {
               const int dc = dc0 - j;
-              const double e = sh.Fmu[xg * 8 + j] - (quad ? ldr + lam * (double)(dc * dc) : lam * cost_units(dr, dc, p.half_p)) - mloc;
+              const double e = sh.Fmu[xg * 8 + j] - (quad ? ldr + lam * (double)(dc * dc) : lam * cost_q<QUAD>(dr, dc, p.half_p)) - mloc;
               P[j][tt] = valid ? fast_exp2((float)(e * kLog2e)) : 0.0f;
             }
             if (xg == 0 && valid) mbuf[yi] = mloc;
@@ -1416,7 +1417,7 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
                   for (int j = 0; j < 8; j++) {
                     const int dc = c - (g.C0 + j);
                     const double e = gl - (quad ? lam * (double)(dc * dc)
-                                                : lam * cost_units(dr, dc, p.half_p));
+                                                : lam * cost_q<QUAD>(dr, dc, p.half_p));
                     mm[j] = e > mm[j] ? e : mm[j];
                   }
                 }
@@ -1463,7 +1464,7 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
                   for (int j = 0; j < 8; j++) {
                     const int dc = c - (g.C0 + j);
                     const double e = gl - (quad ? lam * (double)(dc * dc)
-                                                : lam * cost_units(dr, dc, p.half_p)) -
+                                                : lam * cost_q<QUAD>(dr, dc, p.half_p)) -
                                      sh.mx[xg * 8 + j];
                     sj[j] += (double)fast_exp2((float)(e * kLog2e));
                   }
@@ -1566,7 +1567,7 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
 #pragma unroll
           for (int j = 0; j < 8; j++) {
             const int dc = dc0 - j;
-            s = fmaf((float)cost_units(dr, dc, p.half_p), P[j][t] * uu[j], s);
+            s = fmaf((float)cost_q<QUAD>(dr, dc, p.half_p), P[j][t] * uu[j], s);
           }
           v[t] = s;
         }
@@ -1730,7 +1731,7 @@ DEVI double phi1d(double b) {
 // 2: FP64 exponentials and logarithm (FP64 instantiation).  s lies in
 // [1, 64] (the largest term is e^0), so the FP32 logarithm is accurate to
 // ~1e-7 absolute.
-template <class SH>
+template <bool QUAD, class SH>
 DEVI double cond_plan(const SH& sh, int r, int c, int xs, double lam, double half_p,
                       double pk[4], int prec) {
   double e[4];
@@ -1739,7 +1740,7 @@ DEVI double cond_plan(const SH& sh, int r, int c, int xs, double lam, double hal
   for (int k = 0; k < 4; k++) {
     const int x = xs + 16 * k;
     const int dr = r - sh.xr[x], dc = c - sh.xc[x];
-    e[k] = sh.Fmu[x] - lam * cost_units(dr, dc, half_p);
+    e[k] = sh.Fmu[x] - lam * cost_q<QUAD>(dr, dc, half_p);
     m = e[k] > m ? e[k] : m;
   }
   m = row16_max(m);
@@ -1760,7 +1761,7 @@ DEVI double cond_plan(const SH& sh, int r, int c, int xs, double lam, double hal
   return m + (prec == 2 ? log(s) : (double)fast_log2((float)s) * kLn2);
 }
 
-template <int NW>
+template <int NW, bool QUAD>
 __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restrict__ P,
                                                        SweepSched s, int mode) {
   constexpr int kBigThreads = NW * 64, kNChunk = BigShared<NW>::kNChunk;
@@ -1823,7 +1824,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
     long long n_trials = 0, n_wbuild = 0;
     bool converged = false;
     double lam = p.lam;
-    const bool quad = p.half_p == 1.0;  // quadratic cost: row/column parts separate
+    constexpr bool quad = QUAD;  // quadratic cost: row and column parts separate
     const int phases = p.safeguard ? 3 : 1;
     for (int phase = 0; phase < phases; phase++) {
       if (phase == 1) {
@@ -1851,13 +1852,13 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
           double m = -INFINITY;
           for (int k = 0; k < 64; k++) {
             const int dr = r - sh.xr[k], dc = c - sh.xc[k];
-            const double e = sh.Fmu[k] - lam * cost_units(dr, dc, p.half_p);
+            const double e = sh.Fmu[k] - lam * cost_q<QUAD>(dr, dc, p.half_p);
             m = e > m ? e : m;
           }
           double s = 0;
           for (int k = 0; k < 64; k++) {
             const int dr = r - sh.xr[k], dc = c - sh.xc[k];
-            const double e = sh.Fmu[k] - lam * cost_units(dr, dc, p.half_p) - m;
+            const double e = sh.Fmu[k] - lam * cost_q<QUAD>(dr, dc, p.half_p) - m;
             s += ex(e, fp64);
           }
           const double nu = p.uni_nu[ub + yi];
@@ -1872,7 +1873,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
             int r, c;
             split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
             const int dr = r - sh.xr[x], dc = c - sh.xc[x];
-            const double e = G[yi] - lam * cost_units(dr, dc, p.half_p);
+            const double e = G[yi] - lam * cost_q<QUAD>(dr, dc, p.half_p);
             if (e == -INFINITY) continue;
             if (e > m) {
               s = s * ex(m - e, fp64) + 1.0;
@@ -1946,7 +1947,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
             if (yi < U) {  // uniform within each 16-lane group
               int r, c;
               split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
-              const double lse = cond_plan(sh, r, c, xs, lam, p.half_p, pk, fp64 ? 2 : build_w ? 1 : 0);
+              const double lse = cond_plan<QUAD>(sh, r, c, xs, lam, p.half_p, pk, fp64 ? 2 : build_w ? 1 : 0);
               const double nu = p.uni_nu[ub + yi];
 #pragma unroll
               for (int k = 0; k < 4; k++) racc[k] += nu * pk[k];
@@ -2061,7 +2062,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
                     int r, c;
                     split_key(p.uni_key[ub + yi], p.W, invW, &r, &c);
                     double pk[4];
-                    cond_plan(sh, r, c, xs, lam, p.half_p, pk, fp64 ? 2 : 1);
+                    cond_plan<QUAD>(sh, r, c, xs, lam, p.half_p, pk, fp64 ? 2 : 1);
                     double a[4], cy = 0;
 #pragma unroll
                     for (int k = 0; k < 4; k++) {
@@ -2134,12 +2135,12 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
         double m = -INFINITY;
         for (int k = 0; k < 64; k++) {
           const int dr = r - sh.xr[k], dc = c - sh.xc[k];
-          const double e = sh.Fmu[k] - lam * cost_units(dr, dc, p.half_p);
+          const double e = sh.Fmu[k] - lam * cost_q<QUAD>(dr, dc, p.half_p);
           m = e > m ? e : m;
         }
         for (int k = 0; k < 64; k++) {
           const int dr = r - sh.xr[k], dc = c - sh.xc[k];
-          const double cu = cost_units(dr, dc, p.half_p);
+          const double cu = cost_q<QUAD>(dr, dc, p.half_p);
           const double e = sh.Fmu[k] - lam * cu - m;
           const double v = ex(e, fp64);
           const int qa = ((k >> 5) << 1) | ((k & 7) >> 2);
@@ -2529,8 +2530,9 @@ void launch_sweep_prep(const HalfParams* P, const SweepSched& s, const SweepStre
   post(2, st);
 }
 
-void launch_sweep_solve(const HalfParams* P, const SweepSched& s, const SweepStreams& ss,
-                        const SweepGrid& gr, hipEvent_t* ev) {
+template <bool QUAD>
+static void launch_solvers(const HalfParams* P, const SweepSched& s, const SweepStreams& ss,
+                           const SweepGrid& gr, hipEvent_t* ev) {
   auto pre = [&](int k, hipStream_t st) {
     if (ev) hipEventRecord(ev[2 * k], st);
   };
@@ -2545,40 +2547,40 @@ void launch_sweep_solve(const HalfParams* P, const SweepSched& s, const SweepStr
   for (int i = 0; i < 3; i++) hipStreamWaitEvent(ss.aux[i], ss.fork, 0);
   const int gs = gr.bin[5] < s.stream_wgs ? gr.bin[5] : s.stream_wgs;  // one tile buffer per workgroup
   pre(8, ss.aux[0]);
-  if (gs > 0) hipLaunchKernelGGL(k_solve_stream, dim3(gs), dim3(kSlab), 0, ss.aux[0], P, s);
+  if (gs > 0) hipLaunchKernelGGL(k_solve_stream<QUAD>, dim3(gs), dim3(kSlab), 0, ss.aux[0], P, s);
   post(8, ss.aux[0]);
   pre(9, ss.aux[0]);
-  hipLaunchKernelGGL(k_solve_big<kBigWaves>, dim3(gr.bin[6]), dim3(kBigWaves * 64), 0, ss.aux[0], P, s, 0);
+  hipLaunchKernelGGL((k_solve_big<kBigWaves, QUAD>), dim3(gr.bin[6]), dim3(kBigWaves * 64), 0, ss.aux[0], P, s, 0);
   post(9, ss.aux[0]);
   pre(kNKernels + 0, ss.aux[0]);
-  hipLaunchKernelGGL(k_solve_big<kNewtonWaves>, dim3(gr.newton), dim3(kNewtonWaves * 64), 0, ss.aux[0], P, s, 1 + 3);
+  hipLaunchKernelGGL((k_solve_big<kNewtonWaves, QUAD>), dim3(gr.newton), dim3(kNewtonWaves * 64), 0, ss.aux[0], P, s, 1 + 3);
   post(kNKernels + 0, ss.aux[0]);
   // the small-cell bins go first on their streams: launched behind the
   // persistent workgroups of the large bins they would wait for free compute
   // units until those drain
   pre(4, ss.aux[1]);
-  hipLaunchKernelGGL(k_solve_reg<2>, dim3(gr.bin[1]), dim3(128), 0, ss.aux[1], P, s, 1);
+  hipLaunchKernelGGL((k_solve_reg<2, QUAD>), dim3(gr.bin[1]), dim3(128), 0, ss.aux[1], P, s, 1);
   post(4, ss.aux[1]);
   pre(7, ss.aux[1]);
-  hipLaunchKernelGGL(k_solve_reg<16>, dim3(gr.bin[4]), dim3(1024), 0, ss.aux[1], P, s, 4);
+  hipLaunchKernelGGL((k_solve_reg<16, QUAD>), dim3(gr.bin[4]), dim3(1024), 0, ss.aux[1], P, s, 4);
   post(7, ss.aux[1]);
   pre(kNKernels + 1, ss.aux[1]);
-  hipLaunchKernelGGL(k_solve_big<kNewtonWaves>, dim3(gr.newton), dim3(kNewtonWaves * 64), 0, ss.aux[1], P, s, 1 + 2);
+  hipLaunchKernelGGL((k_solve_big<kNewtonWaves, QUAD>), dim3(gr.newton), dim3(kNewtonWaves * 64), 0, ss.aux[1], P, s, 1 + 2);
   post(kNKernels + 1, ss.aux[1]);
   pre(3, ss.aux[2]);
-  hipLaunchKernelGGL(k_solve_reg<1>, dim3(gr.bin[0]), dim3(64), 0, ss.aux[2], P, s, 0);
+  hipLaunchKernelGGL((k_solve_reg<1, QUAD>), dim3(gr.bin[0]), dim3(64), 0, ss.aux[2], P, s, 0);
   post(3, ss.aux[2]);
   pre(6, ss.aux[2]);
-  hipLaunchKernelGGL(k_solve_reg<8>, dim3(gr.bin[3]), dim3(512), 0, ss.aux[2], P, s, 3);
+  hipLaunchKernelGGL((k_solve_reg<8, QUAD>), dim3(gr.bin[3]), dim3(512), 0, ss.aux[2], P, s, 3);
   post(6, ss.aux[2]);
   pre(kNKernels + 2, ss.aux[2]);
-  hipLaunchKernelGGL(k_solve_big<kNewtonWaves>, dim3(gr.newton), dim3(kNewtonWaves * 64), 0, ss.aux[2], P, s, 1 + 1);
+  hipLaunchKernelGGL((k_solve_big<kNewtonWaves, QUAD>), dim3(gr.newton), dim3(kNewtonWaves * 64), 0, ss.aux[2], P, s, 1 + 1);
   post(kNKernels + 2, ss.aux[2]);
   pre(5, st);
-  hipLaunchKernelGGL(k_solve_reg<4>, dim3(gr.bin[2]), dim3(256), 0, st, P, s, 2);
+  hipLaunchKernelGGL((k_solve_reg<4, QUAD>), dim3(gr.bin[2]), dim3(256), 0, st, P, s, 2);
   post(5, st);
   pre(10, st);
-  hipLaunchKernelGGL(k_solve_big<kNewtonWaves>, dim3(gr.newton), dim3(kNewtonWaves * 64), 0, st, P, s, 1 + 0);
+  hipLaunchKernelGGL((k_solve_big<kNewtonWaves, QUAD>), dim3(gr.newton), dim3(kNewtonWaves * 64), 0, st, P, s, 1 + 0);
   post(10, st);
   // join
   for (int i = 0; i < 3; i++) {
@@ -2587,11 +2589,25 @@ void launch_sweep_solve(const HalfParams* P, const SweepSched& s, const SweepStr
   }
 }
 
+void launch_sweep_solve(const HalfParams* P, const SweepSched& s, const SweepStreams& ss,
+                        const SweepGrid& gr, hipEvent_t* ev) {
+  if (s.quad)
+    launch_solvers<true>(P, s, ss, gr, ev);
+  else
+    launch_solvers<false>(P, s, ss, gr, ev);
+}
+
 size_t sweep_max_static_lds() {
-  const void* ks[] = {(const void*)k_union, (const void*)k_solve_reg<1>, (const void*)k_solve_reg<2>,
-                      (const void*)k_solve_reg<4>, (const void*)k_solve_reg<8>,
-                      (const void*)k_solve_reg<16>, (const void*)k_solve_big<kBigWaves>,
-                      (const void*)k_solve_big<kNewtonWaves>};
+  const void* ks[] = {(const void*)k_union,
+                      (const void*)k_solve_reg<1, true>, (const void*)k_solve_reg<2, true>,
+                      (const void*)k_solve_reg<4, true>, (const void*)k_solve_reg<8, true>,
+                      (const void*)k_solve_reg<16, true>, (const void*)k_solve_big<kBigWaves, true>,
+                      (const void*)k_solve_big<kNewtonWaves, true>,
+                      (const void*)k_solve_reg<1, false>, (const void*)k_solve_reg<2, false>,
+                      (const void*)k_solve_reg<4, false>, (const void*)k_solve_reg<8, false>,
+                      (const void*)k_solve_reg<16, false>,
+                      (const void*)k_solve_big<kBigWaves, false>,
+                      (const void*)k_solve_big<kNewtonWaves, false>};
   size_t mx = 0;
   for (const void* k : ks) {
     hipFuncAttributes a;

@@ -189,9 +189,10 @@ static hipError_t runner_stream(Runner& r, int n_cells) {
   return hipSuccess;
 }
 
-static ddk::SweepSched runner_sched(const Runner& r, int n_prob) {
+static ddk::SweepSched runner_sched(const Runner& r, int n_prob, bool quad) {
   ddk::SweepSched sc{};
   sc.n_prob = n_prob;
+  sc.quad = quad ? 1 : 0;
   sc.cap = r.cap;
   sc.bin_count = r.bin_count;
   sc.bin_list = r.bin_list;
@@ -958,7 +959,7 @@ extern "C" dd_status dd_half_iterate(dd_ctx* c, int part, dd_iter_stats* out) {
   HIPCHK(c, runner_stream(r, p.n_cells));
   r.hP[0] = p;
   HIPCHK(c, hipMemcpyAsync(r.dP, r.hP, sizeof(HalfParams), hipMemcpyHostToDevice, c->st));
-  const ddk::SweepSched sc = runner_sched(r, 1);
+  const ddk::SweepSched sc = runner_sched(r, 1, c->opt.cost_p == 2.0);
   const ddk::SweepGrid gr = plan_grid(r, p.n_cells, p.n_cells, 1);
   hipEvent_t* kev = r.timing ? r.kev : nullptr;
   HIPCHK(c, hipEventRecord(r.ev0, c->st));
@@ -1501,12 +1502,12 @@ namespace {
 // What a captured sweep depends on besides the parameter array's contents.
 struct GraphKey {
   int n_prob = 0, total = 0, max_cells = 0, cap = 0, stream_wgs = 0, solver_pc = 0, newton_pc = 0,
-      stream_max = 0, wg_cells = 0;
+      stream_max = 0, wg_cells = 0, quad = 0;
   const void* ptr[7] = {};
   bool operator==(const GraphKey& o) const {
     if (n_prob != o.n_prob || total != o.total || max_cells != o.max_cells || cap != o.cap ||
         stream_wgs != o.stream_wgs || solver_pc != o.solver_pc || newton_pc != o.newton_pc ||
-        stream_max != o.stream_max || wg_cells != o.wg_cells)
+        stream_max != o.stream_max || wg_cells != o.wg_cells || quad != o.quad)
       return false;
     for (int i = 0; i < 7; i++)
       if (ptr[i] != o.ptr[i]) return false;
@@ -1601,7 +1602,9 @@ static dd_status batch_sweep(dd_batch* b, const int* parts, dd_iter_stats* out) 
   BHIPCHK(b, runner_stream(r, total));
   memcpy(r.hP, hp.data(), sizeof(HalfParams) * na);
   BHIPCHK(b, hipMemcpyAsync(r.dP, r.hP, sizeof(HalfParams) * na, hipMemcpyHostToDevice, r.main));
-  const ddk::SweepSched sc = runner_sched(r, na);
+  bool all_quad = true;
+  for (int i = 0; i < na; i++) all_quad = all_quad && hp[i].half_p == 1.0;
+  const ddk::SweepSched sc = runner_sched(r, na, all_quad);
   const ddk::SweepGrid gr = plan_grid(r, total, mx, na);
   const bool graph = (b->flags & DD_BATCH_GRAPH) != 0;
   hipEvent_t* kev = (!graph && r.timing) ? r.kev : nullptr;
@@ -1616,6 +1619,7 @@ static dd_status batch_sweep(dd_batch* b, const int* parts, dd_iter_stats* out) 
     key.newton_pc = r.newton_per_cu;
     key.stream_max = stream_limit(r);
     key.wg_cells = r.wg_cells;
+    key.quad = sc.quad;
     const void* ptrs[7] = {r.dP, r.dstats, r.bin_list, r.defer_list, r.stream_tile, r.stream_S,
                            r.stream_nu};
     for (int i = 0; i < 7; i++) key.ptr[i] = ptrs[i];
