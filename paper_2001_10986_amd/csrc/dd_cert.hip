@@ -125,16 +125,19 @@ __global__ void k_cert_rhs(const int* inc_ptr, const int* inc_e, const int* e_ia
 
 constexpr int kCgThreads = 1024;
 
+// Workgroup sum in a fixed order: a butterfly over the 64 lanes of each wave
+// (every lane ends with the wave's sum), one slot per wave in LDS, and every
+// thread adds the 16 slots itself (two barriers).
 __device__ double cg_reduce(double v, double* red) {
-  red[threadIdx.x] = v;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  for (int w = kCgThreads / 2; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
-    __syncthreads();
-  }
-  const double out = red[0];
-  __syncthreads();
-  return out;
+  double t = 0;
+#pragma unroll
+  for (int w = 0; w < kCgThreads / 64; w++) t += red[w];
+  __syncthreads();  // the slots are reused by the next reduction
+  return t;
 }
 
 // Conjugate gradients for L V = rhs in one workgroup, L the graph Laplacian
@@ -148,7 +151,7 @@ __global__ __launch_bounds__(kCgThreads) void k_cert_cg(
     const int* adj_ptr, const int* adj_idx, const double* adj_w, const double* deg,
     const double* b, int na, int max_it, double tol2, double* x, double* r, double* p,
     double* Ap, double* info) {
-  __shared__ double red[kCgThreads];
+  __shared__ double red[kCgThreads / 64];
   const int tid = threadIdx.x;
   double loc = 0;
   for (int J = tid; J < na; J += kCgThreads) {
