@@ -184,8 +184,10 @@ void dd_options_default(dd_options* opt);
 /* Create a problem (eq. "Problem", Algorithm 2 inputs).
  * mu, nu: H x W row-major FP64 probability images (host pointers unless
  *   opt->inputs_on_device); copied, the caller keeps ownership.
- * basic_cell: s (only 4 is supported by the GPU kernels); H and W must be
- *   divisible by 2*s*2^(n_levels-1).
+ * basic_cell: s, 2 or 4 (a composite cell of 2s x 2s pixels is solved in a
+ *   virtual 8x8 block, so s = 2 leaves three quarters of it empty); H and W
+ *   must be divisible by 2*s*2^(n_levels-1).  The warm-start network and the
+ *   cell features of include/dd_mlp.h need s = 4.
  * schedule: n_stages >= 1 rows, copied; schedule[0].eps is the initial eps.
  * The state starts on level 0 with the product coupling nu_i = |mu_i| nu and
  * zero potentials (Sec. 6.4).  Rejects with DD_EINVAL: non-finite or

@@ -37,7 +37,8 @@ __global__ void k_cert_fill(unsigned long long* M, double* S, long long npx, dou
 // pass 1: S(y) += sum over x in X_i of exp(that - M(y)).
 template <int PASS>
 __global__ void k_cert_y(const int64_t* row_off, const int* row_len, const int* col,
-                         const double* alpha_hat, const double* mu, int W, int bw, int n_basic,
+                         const double* alpha_hat, const double* mu, int bs, int W, int bw,
+                         int n_basic,
                          double inv_eps, double hp, double half_p, unsigned long long* M,
                          double* S) {
   const int lane = threadIdx.x & 63;
@@ -52,9 +53,9 @@ __global__ void k_cert_y(const int64_t* row_off, const int* row_len, const int* 
       const int yr = y / W, yc = y % W;
       const double m = PASS == 1 ? dunkey(M[y]) : 0.0;
       double acc = PASS == 0 ? -INFINITY : 0.0;
-      for (int i = 0; i < kS; i++)
-        for (int j = 0; j < kS; j++) {
-          const int xr = br * kS + i, xc = bc * kS + j;
+      for (int i = 0; i < bs; i++)
+        for (int j = 0; j < bs; j++) {
+          const int xr = br * bs + i, xc = bc * bs + j;
           const long long px = (long long)xr * W + xc;
           const double mx = mu[px];
           if (!(mx > 0)) continue;
@@ -223,8 +224,8 @@ void launch_cert_glue(const int* inc_ptr, const int* inc_e, const int* e_ia, con
 
 void launch_cert_y(const int64_t* row_off, const int* row_len, const int* col,
                    const double* alpha_hat, const double* mu, const double* nu, int H, int W,
-                   int bw, int n_basic, double eps, double h, double half_p, double* scratch,
-                   double* beta_hat, double* sums, hipStream_t st) {
+                   int bs, int bw, int n_basic, double eps, double h, double half_p,
+                   double* scratch, double* beta_hat, double* sums, hipStream_t st) {
   const long long npx = (long long)H * W;
   unsigned long long* M = (unsigned long long*)scratch;
   double* S = scratch + npx;
@@ -232,11 +233,11 @@ void launch_cert_y(const int64_t* row_off, const int* row_len, const int* col,
                      npx, sums);
   const unsigned blocks = (unsigned)((n_basic + 3) / 4 < 65535 ? (n_basic + 3) / 4 : 65535);
   hipLaunchKernelGGL(k_cert_y<0>, dim3(blocks), dim3(256), 0, st, row_off, row_len, col,
-                     alpha_hat, mu, W, bw, n_basic, 1.0 / eps, std::pow(h, 2.0 * half_p), half_p,
-                     M, S);
+                     alpha_hat, mu, bs, W, bw, n_basic, 1.0 / eps, std::pow(h, 2.0 * half_p),
+                     half_p, M, S);
   hipLaunchKernelGGL(k_cert_y<1>, dim3(blocks), dim3(256), 0, st, row_off, row_len, col,
-                     alpha_hat, mu, W, bw, n_basic, 1.0 / eps, std::pow(h, 2.0 * half_p), half_p,
-                     M, S);
+                     alpha_hat, mu, bs, W, bw, n_basic, 1.0 / eps, std::pow(h, 2.0 * half_p),
+                     half_p, M, S);
   hipLaunchKernelGGL(k_cert_sums, dim3(1024), dim3(256), 0, st, alpha_hat, mu, nu, M, S, npx,
                      eps, beta_hat, sums);
 }

@@ -6,8 +6,8 @@
 
 namespace ddk {
 
-constexpr int kS = 4;          // basic cell edge in pixels (the only supported value)
-constexpr int kCellPx = 64;    // a composite cell is a virtual 8x8 pixel block
+constexpr int kS = 4;          // default basic cell edge in pixels (s = 2 is also supported)
+constexpr int kCellPx = 64;    // a composite cell (2s x 2s pixels) sits in a virtual 8x8 block
 constexpr int kNRegBins = 5;   // register-resident solver bins: 1,2,4,8,16 waves
 constexpr int kRegMaxU = 1024; // largest Y-support kept in registers (16 waves x 64)
 constexpr int kStreamSlabs = 8;                // streamed solver: unions of up to 8 x 1024 points
@@ -21,6 +21,7 @@ constexpr double kWarmScale = 16.0;            // network output unit: 16 lam (h
 // Everything one sweep over one partition needs.  Device pointers.
 struct HalfParams {
   int H, W, bh, bw;
+  int s;                       // basic cell edge in pixels (2 or 4)
   int n_cells, n_basic;
   int part;
   double h, eps, lam;          // lam = h^p / eps (cost in units of eps per pixel^p)
@@ -93,6 +94,14 @@ __device__ __forceinline__ double cost_units(int dr, int dc, double half_p) {
   return d2 > 0 ? exp(half_p * log((double)d2)) : 0.0;
 }
 
+// Basic cell of pixel (i, j) of a composite cell's virtual 8x8 block: the
+// cell covers rows and columns [0, 2s) of the block as a 2x2 arrangement of
+// s x s basic cells (quadrant 2 * (i >= s) + (j >= s)); -1 outside it.
+__device__ __forceinline__ int block_quadrant(int i, int j, int s) {
+  if (i >= 2 * s || j >= 2 * s) return -1;
+  return (i >= s ? 2 : 0) + (j >= s ? 1 : 0);
+}
+
 // The solvers are compiled twice: QUAD for sweeps whose problems all have the
 // quadratic cost (integer |d|^2, no transcendental work), and a general
 // instantiation that forms every cost through cost_units.
@@ -148,7 +157,7 @@ void launch_stats(const HalfParams* P, int n_prob, IterStatsDev* out, hipStream_
                   hipEvent_t* ev2);
 size_t sweep_max_static_lds();
 
-void launch_validate(const double* mu, const double* nu, int H, int W, double* out4,
+void launch_validate(const double* mu, const double* nu, int s, int H, int W, double* out4,
                      hipStream_t st);
 void launch_pyramid(const double* fine, double* coarse, int Hc, int Wc, hipStream_t st);
 void launch_product_init(const int* ypos, int nzy, const double* nu, const double* bmass,
@@ -159,7 +168,7 @@ void launch_product_init(const int* ypos, int nzy, const double* nu, const doubl
 // scratch_px holds H*W + 3*kDiagBlocks doubles.
 constexpr int kDiagBlocks = 256;
 void launch_diag(const int64_t* row_off, const int* row_len, const int* col, const double* val,
-                 const double* mu, const double* nu, int H, int W, int bw, int n_basic,
+                 const double* mu, const double* nu, int s, int H, int W, int bw, int n_basic,
                  double* scratch_px, double* out3, hipStream_t st);
 
 // Export: dense CSR from the gapped rows.
@@ -180,6 +189,7 @@ void launch_collect(const HalfParams& p, const double* alpha_prev, float* X, flo
 
 // Refinement.
 struct RefineParams {
+  int s;                       // basic cell edge in pixels
   int Hc, Wc, bwc, Hf, Wf, bwf, n_basic_f;
   double eps;
   const double* mu_c; const double* nu_c; const double* mu_f; const double* nu_f;
@@ -210,7 +220,7 @@ void launch_cert_glue(const int* inc_ptr, const int* inc_e, const int* e_ia, con
                       double* work, double* V, double* info, hipStream_t st);
 void launch_cert_y(const int64_t* row_off, const int* row_len, const int* col,
                    const double* alpha_hat, const double* mu, const double* nu, int H, int W,
-                   int bw, int n_basic, double eps, double h, double half_p, double* scratch,
-                   double* beta_hat, double* sums, hipStream_t st);
+                   int bs, int bw, int n_basic, double eps, double h, double half_p,
+                   double* scratch, double* beta_hat, double* sums, hipStream_t st);
 
 }  // namespace ddk

@@ -686,7 +686,8 @@ struct RegShared {
 // the xor swizzle spreads the 8 support groups over the LDS banks.
 DEVI int tsw(int yg, int x, int t) { return yg * 64 + (((x ^ yg) & 7) << 3) + t; }
 
-DEVI void transpose_y(float* rd, int xg, int yg, const float v[8], float* top, float* bot) {
+DEVI void transpose_y(float* rd, int xg, int yg, const float v[8], float* top, float* bot,
+                      int split = 4) {
   wave_sync();
 #pragma unroll
   for (int t = 0; t < 8; t++) rd[tsw(yg, xg, t)] = v[t];
@@ -695,7 +696,7 @@ DEVI void transpose_y(float* rd, int xg, int yg, const float v[8], float* top, f
 #pragma unroll
   for (int k = 0; k < 8; k++) {
     const float x = rd[tsw(yg, k, xg)];
-    if (k < 4) a += x; else b += x;
+    if (k < split) a += x; else b += x;
   }
   *top = a;
   *bot = b;
@@ -788,8 +789,8 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
     // ---- pixel data (pixel k = 8i + j of the block)
     if (tid < 64) {
       const int i = tid >> 3, j = tid & 7;
-      const int qa = (i >> 2) * 2 + (j >> 2);
-      const int bq = qa == 0 ? g.bq[0] : qa == 1 ? g.bq[1] : qa == 2 ? g.bq[2] : g.bq[3];
+      const int qa = block_quadrant(i, j, p.s);
+      const int bq = qa < 0 ? -1 : qa == 0 ? g.bq[0] : qa == 1 ? g.bq[1] : qa == 2 ? g.bq[2] : g.bq[3];
       const int r = g.R0 + i, c = g.C0 + j;
       double mu = 0, F0 = 0;
       if (bq >= 0) {
@@ -814,7 +815,10 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
     __syncthreads();
     double massmu[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int k = 0; k < 64; k++) massmu[((k >> 3) >> 2) * 2 + ((k & 7) >> 2)] += sh.mu[k];
+    for (int k = 0; k < 64; k++) {
+      const int qa = block_quadrant(k >> 3, k & 7, p.s);
+      if (qa >= 0) massmu[qa] += sh.mu[k];
+    }
     const double muJ = (massmu[0] + massmu[1]) + (massmu[2] + massmu[3]);
     const double tol = p.err_tol * muJ;
     const double mux = sh.mu[lane];  // this lane's pixel in the X-update
@@ -1056,22 +1060,25 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
       float uu[8], v[8];
 #pragma unroll
       for (int j = 0; j < 8; j++) uu[j] = uw[xg * 8 + j];
+      // left / right basic cells: block columns j < s and j >= s (the block
+      // columns from 2s on carry no mass, u = 0 there)
+      const int sp = p.s;
 #pragma unroll
       for (int t = 0; t < 8; t++) {
         float s = 0.f;
 #pragma unroll
-        for (int j = 0; j < 4; j++) s = fmaf(P[j][t], uu[j], s);
+        for (int j = 0; j < 8; j++) s = fmaf(j < sp ? P[j][t] : 0.f, uu[j], s);
         v[t] = s;
       }
-      transpose_y(rd, xg, yg, v, &sl_t, &sl_b);
+      transpose_y(rd, xg, yg, v, &sl_t, &sl_b, sp);
 #pragma unroll
       for (int t = 0; t < 8; t++) {
         float s = 0.f;
 #pragma unroll
-        for (int j = 4; j < 8; j++) s = fmaf(P[j][t], uu[j], s);
+        for (int j = 0; j < 8; j++) s = fmaf(j < sp ? 0.f : P[j][t], uu[j], s);
         v[t] = s;
       }
-      transpose_y(rd, xg, yg, v, &sr_t, &sr_b);
+      transpose_y(rd, xg, yg, v, &sr_t, &sr_b, sp);
 #pragma unroll
       for (int t = 0; t < 8; t++) {
         const int yi = ybase + t;
@@ -1129,7 +1136,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
       p.r_err[cell] = err_last;
       p.r_loops[cell] = loops_all;
       p.r_status[cell] = status;
-      p.r_evals[cell] = (long long)loops_all * 16 * g.nq * U;
+      p.r_evals[cell] = (long long)loops_all * p.s * p.s * g.nq * U;
     }
     if (tid < 64 && sh.mu[tid] > 0) {
       const int i = tid >> 3, j = tid & 7;
@@ -1205,8 +1212,8 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
     double* mbuf = p.uni_G + ub;  // m(y) of the absorbed tile
     if (tid < 64) {
       const int i = tid >> 3, j = tid & 7;
-      const int qa = (i >> 2) * 2 + (j >> 2);
-      const int bq = qa == 0 ? g.bq[0] : qa == 1 ? g.bq[1] : qa == 2 ? g.bq[2] : g.bq[3];
+      const int qa = block_quadrant(i, j, p.s);
+      const int bq = qa < 0 ? -1 : qa == 0 ? g.bq[0] : qa == 1 ? g.bq[1] : qa == 2 ? g.bq[2] : g.bq[3];
       const int r = g.R0 + i, c = g.C0 + j;
       double mu = 0, F0 = 0;
       if (bq >= 0) {
@@ -1221,7 +1228,10 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
     __syncthreads();
     double massmu[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int k = 0; k < 64; k++) massmu[((k >> 3) >> 2) * 2 + ((k & 7) >> 2)] += sh.mu[k];
+    for (int k = 0; k < 64; k++) {
+      const int qa = block_quadrant(k >> 3, k & 7, p.s);
+      if (qa >= 0) massmu[qa] += sh.mu[k];
+    }
     const double muJ = (massmu[0] + massmu[1]) + (massmu[2] + massmu[3]);
     const double tol = p.err_tol * muJ;
 
@@ -1541,22 +1551,23 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
           P[j][4] = b.x; P[j][5] = b.y; P[j][6] = b.z; P[j][7] = b.w;
         }
         float sl_t, sl_b, sr_t, sr_b, c1, c2, v[8];
+        const int sp = p.s;  // left / right basic cells: block columns j < s, j >= s
 #pragma unroll
         for (int t = 0; t < 8; t++) {
           float s = 0.f;
 #pragma unroll
-          for (int j = 0; j < 4; j++) s = fmaf(P[j][t], uu[j], s);
+          for (int j = 0; j < 8; j++) s = fmaf(j < sp ? P[j][t] : 0.f, uu[j], s);
           v[t] = s;
         }
-        transpose_y(rd, xg, yg, v, &sl_t, &sl_b);
+        transpose_y(rd, xg, yg, v, &sl_t, &sl_b, sp);
 #pragma unroll
         for (int t = 0; t < 8; t++) {
           float s = 0.f;
 #pragma unroll
-          for (int j = 4; j < 8; j++) s = fmaf(P[j][t], uu[j], s);
+          for (int j = 0; j < 8; j++) s = fmaf(j < sp ? 0.f : P[j][t], uu[j], s);
           v[t] = s;
         }
-        transpose_y(rd, xg, yg, v, &sr_t, &sr_b);
+        transpose_y(rd, xg, yg, v, &sr_t, &sr_b, sp);
 #pragma unroll
         for (int t = 0; t < 8; t++) {
           const int yi = sl * kSlab + yoff + t;
@@ -1615,7 +1626,7 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
       p.r_err[cell] = sh.err;
       p.r_loops[cell] = loops_all;
       p.r_status[cell] = status;
-      p.r_evals[cell] = (long long)loops_all * 16 * g.nq * U;
+      p.r_evals[cell] = (long long)loops_all * p.s * p.s * g.nq * U;
     }
     if (tid < 64 && sh.mu[tid] > 0) {
       const int i = tid >> 3, j = tid & 7;
@@ -1790,10 +1801,10 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
     const int64_t obase = p.cell_ooff[cell];
     if (tid < 64) {
       const int i = tid >> 3, j = tid & 7;
-      const int qa = (i >> 2) * 2 + (j >> 2);
+      const int qa = block_quadrant(i, j, p.s);
       const int r = g.R0 + i, c = g.C0 + j;
       double mu = 0, F = 0, F0 = 0;
-      const int bq = qa == 0 ? g.bq[0] : qa == 1 ? g.bq[1] : qa == 2 ? g.bq[2] : g.bq[3];
+      const int bq = qa < 0 ? -1 : qa == 0 ? g.bq[0] : qa == 1 ? g.bq[1] : qa == 2 ? g.bq[2] : g.bq[3];
       if (bq >= 0) {
         mu = p.mu[(int64_t)r * p.W + c];
         F0 = p.alpha[(int64_t)r * p.W + c] / p.eps;
@@ -1813,7 +1824,10 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
     __syncthreads();
     double massmu[4] = {0, 0, 0, 0};
 #pragma unroll
-    for (int k = 0; k < 64; k++) massmu[((k >> 3) >> 2) * 2 + ((k & 7) >> 2)] += sh.mu[k];
+    for (int k = 0; k < 64; k++) {
+      const int qa = block_quadrant(k >> 3, k & 7, p.s);
+      if (qa >= 0) massmu[qa] += sh.mu[k];
+    }
     const double tol = p.err_tol * (massmu[0] + massmu[1] + massmu[2] + massmu[3]);
     const int n_act = sh.nact;
     double* G = p.uni_G + ub;
@@ -2143,7 +2157,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
           const double cu = cost_q<QUAD>(dr, dc, p.half_p);
           const double e = sh.Fmu[k] - lam * cu - m;
           const double v = ex(e, fp64);
-          const int qa = ((k >> 5) << 1) | ((k & 7) >> 2);
+          const int qa = block_quadrant(k >> 3, k & 7, p.s);
           sq[0] += qa == 0 ? v : 0.0;
           sq[1] += qa == 1 ? v : 0.0;
           sq[2] += qa == 2 ? v : 0.0;
@@ -2191,7 +2205,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
       p.r_loops[cell] = loops_all;
       p.r_status[cell] = status;
       int nx = 0;
-      _Pragma("unroll") for (int a = 0; a < 4; a++) nx += g.bq[a] >= 0 ? 16 : 0;
+      _Pragma("unroll") for (int a = 0; a < 4; a++) nx += g.bq[a] >= 0 ? p.s * p.s : 0;
       if (deferred) {
         // the solver that handed the cell over keeps its own loops; this
         // launch counts its passes over the support (loops and line-search
@@ -2246,8 +2260,8 @@ DEVI void cell_features(const HalfParams& p, const CellGeo& g, int U, int64_t ub
   int64_t px = 0;
   if (tid < 64) {
     const int i = tid >> 3, j = tid & 7;
-    const int qa = (i >> 2) * 2 + (j >> 2);
-    const int bq = qa == 0 ? g.bq[0] : qa == 1 ? g.bq[1] : qa == 2 ? g.bq[2] : g.bq[3];
+    const int qa = block_quadrant(i, j, p.s);
+    const int bq = qa < 0 ? -1 : qa == 0 ? g.bq[0] : qa == 1 ? g.bq[1] : qa == 2 ? g.bq[2] : g.bq[3];
     px = (int64_t)(g.R0 + i) * p.W + g.C0 + j;
     if (bq >= 0) {
       mu = p.mu[px];
@@ -2346,8 +2360,8 @@ __global__ __launch_bounds__(64) void k_warm_apply(HalfParams p, const float* Y,
   if (cell >= p.n_cells || p.cell_U[cell] > kWarmMaxU) return;  // uniform
   const CellGeo g = load_geo(p, cell);
   const int i = threadIdx.x >> 3, j = threadIdx.x & 7;
-  const int qa = (i >> 2) * 2 + (j >> 2);
-  const int bq = qa == 0 ? g.bq[0] : qa == 1 ? g.bq[1] : qa == 2 ? g.bq[2] : g.bq[3];
+  const int qa = block_quadrant(i, j, p.s);
+  const int bq = qa < 0 ? -1 : qa == 0 ? g.bq[0] : qa == 1 ? g.bq[1] : qa == 2 ? g.bq[2] : g.bq[3];
   const int64_t px = (int64_t)(g.R0 + i) * p.W + g.C0 + j;
   const bool act = bq >= 0 && p.mu[px] > 0;
   const double y = act ? (double)Y[(size_t)cell * 64 + threadIdx.x] : 0.0;
@@ -2625,7 +2639,7 @@ void launch_stats(const HalfParams* P, int n_prob, IterStatsDev* out, hipStream_
 
 // ------------------------------------------------------------ setup kernels
 
-__global__ __launch_bounds__(1024) void k_validate(const double* mu, const double* nu, int H,
+__global__ __launch_bounds__(1024) void k_validate(const double* mu, const double* nu, int S, int H,
                                                    int W, double* out4) {
   __shared__ double sh[16];
   double sm = 0, sn = 0, bad = 0;
@@ -2636,13 +2650,13 @@ __global__ __launch_bounds__(1024) void k_validate(const double* mu, const doubl
     sn += b;
   }
   // smallest basic-cell mass of mu
-  const int bh = H / kS, bw = W / kS;
+  const int bh = H / S, bw = W / S;
   double mn = INFINITY;
   for (int b = threadIdx.x; b < bh * bw; b += 1024) {
     int br = b / bw, bc = b % bw;
     double m = 0;
-    for (int i = 0; i < kS; i++)
-      for (int j = 0; j < kS; j++) m += mu[(long long)(br * kS + i) * W + bc * kS + j];
+    for (int i = 0; i < S; i++)
+      for (int j = 0; j < S; j++) m += mu[(long long)(br * S + i) * W + bc * S + j];
     mn = m < mn ? m : mn;
   }
   sm = block_sum_d(sm, sh);
@@ -2662,9 +2676,9 @@ __global__ __launch_bounds__(1024) void k_validate(const double* mu, const doubl
   }
 }
 
-void launch_validate(const double* mu, const double* nu, int H, int W, double* out4,
+void launch_validate(const double* mu, const double* nu, int s, int H, int W, double* out4,
                      hipStream_t st) {
-  hipLaunchKernelGGL(k_validate, dim3(1), dim3(1024), 0, st, mu, nu, H, W, out4);
+  hipLaunchKernelGGL(k_validate, dim3(1), dim3(1024), 0, st, mu, nu, s, H, W, out4);
 }
 
 __global__ void k_pyramid(const double* fine, double* coarse, int Hc, int Wc) {
@@ -2719,8 +2733,9 @@ __global__ void k_diag_scatter(const int64_t* row_off, const int* row_len, const
 // pixels and basic cells), then a fixed-order sum of the slots.
 __global__ __launch_bounds__(256) void k_diag_partial(const int64_t* row_off, const int* row_len,
                                                       const double* val, const double* mu,
-                                                      const double* nu, const double* acc, int H,
-                                                      int W, int bw, int n_basic, double* part) {
+                                                      const double* nu, const double* acc, int S,
+                                                      int H, int W, int bw, int n_basic,
+                                                      double* part) {
   __shared__ double sh[16];
   const long long stride = (long long)gridDim.x * blockDim.x;
   const long long t0 = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2731,8 +2746,8 @@ __global__ __launch_bounds__(256) void k_diag_partial(const int64_t* row_off, co
     const int64_t o = row_off[b];
     for (int k = 0; k < row_len[b]; k++) m += val[o + k];
     const int br = (int)(b / bw), bc = (int)(b % bw);
-    for (int i = 0; i < kS; i++)
-      for (int j = 0; j < kS; j++) mm += mu[(long long)(br * kS + i) * W + bc * kS + j];
+    for (int i = 0; i < S; i++)
+      for (int j = 0; j < S; j++) mm += mu[(long long)(br * S + i) * W + bc * S + j];
     dm += fabs(m - mm);
     nnz += row_len[b];
   }
@@ -2761,8 +2776,8 @@ __global__ void k_zero_d(double* p, long long n) {
 }
 
 void launch_diag(const int64_t* row_off, const int* row_len, const int* col, const double* val,
-                 const double* mu, const double* nu, int H, int W, int bw, int n_basic,
-                 double* scratch_px, double* out3, hipStream_t st) {
+                 const double* mu, const double* nu, int s, int H, int W, int bw,
+                 int n_basic, double* scratch_px, double* out3, hipStream_t st) {
   // the accumulator is cleared by a kernel (no memset node if a caller captures the launches)
   const long long npx = (long long)H * W;
   const unsigned zb = (unsigned)std::min<long long>((npx + 255) / 256, 4096);
@@ -2772,7 +2787,7 @@ void launch_diag(const int64_t* row_off, const int* row_len, const int* col, con
   // the slots live behind the H*W accumulator (scratch_px holds H*W + 3*kDiagBlocks)
   double* part = scratch_px + (size_t)H * W;
   hipLaunchKernelGGL(k_diag_partial, dim3(kDiagBlocks), dim3(256), 0, st, row_off, row_len, val,
-                     mu, nu, scratch_px, H, W, bw, n_basic, part);
+                     mu, nu, scratch_px, s, H, W, bw, n_basic, part);
   hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, st, part, kDiagBlocks, out3);
 }
 
@@ -2830,10 +2845,10 @@ __global__ __launch_bounds__(64) void k_refine_fill(RefineParams r) {
   const int P = (br >> 1) * r.bwc + (bc >> 1);
   const int pr = P / r.bwc, pc = P % r.bwc;
   double mi = 0, mP = 0;
-  for (int i = 0; i < kS; i++)
-    for (int j = 0; j < kS; j++) {
-      mi += r.mu_f[(long long)(br * kS + i) * r.Wf + bc * kS + j];
-      mP += r.mu_c[(long long)(pr * kS + i) * r.Wc + pc * kS + j];
+  for (int i = 0; i < r.s; i++)
+    for (int j = 0; j < r.s; j++) {
+      mi += r.mu_f[(long long)(br * r.s + i) * r.Wf + bc * r.s + j];
+      mP += r.mu_c[(long long)(pr * r.s + i) * r.Wc + pc * r.s + j];
     }
   const double ratio_mu = mi / mP;
   const int64_t po = r.row_off_c[P];
@@ -2886,24 +2901,24 @@ void launch_refine_rows(const RefineParams& r, hipStream_t st) {
 
 __global__ void k_glue_ratios(RefineParams r, double* out) {
   int b = blockIdx.x * blockDim.x + threadIdx.x;
-  const int bh = r.Hc / kS;
+  const int bh = r.Hc / r.s;
   if (b >= bh * r.bwc) return;
   const int br = b / r.bwc, bc = b % r.bwc;
   for (int sgn = 0; sgn < 2; sgn++) {
     const double sg = sgn == 0 ? 1.0 : -1.0;
     double m = -INFINITY;
-    for (int i = 0; i < kS; i++)
-      for (int j = 0; j < kS; j++) {
-        long long px = (long long)(br * kS + i) * r.Wc + bc * kS + j;
+    for (int i = 0; i < r.s; i++)
+      for (int j = 0; j < r.s; j++) {
+        long long px = (long long)(br * r.s + i) * r.Wc + bc * r.s + j;
         if (r.mu_c[px] > 0) {
           double v = sg * (r.alpha_a_c[px] - r.alpha_b_c[px]) / r.eps;
           m = v > m ? v : m;
         }
       }
     double acc = 0, tot = 0;
-    for (int i = 0; i < kS; i++)
-      for (int j = 0; j < kS; j++) {
-        long long px = (long long)(br * kS + i) * r.Wc + bc * kS + j;
+    for (int i = 0; i < r.s; i++)
+      for (int j = 0; j < r.s; j++) {
+        long long px = (long long)(br * r.s + i) * r.Wc + bc * r.s + j;
         if (r.mu_c[px] > 0) {
           acc += r.mu_c[px] * exp(sg * (r.alpha_a_c[px] - r.alpha_b_c[px]) / r.eps - m);
           tot += r.mu_c[px];
@@ -2914,7 +2929,7 @@ __global__ void k_glue_ratios(RefineParams r, double* out) {
 }
 
 void launch_glue_ratios(const RefineParams& r, double* out, hipStream_t st) {
-  int n = (r.Hc / kS) * r.bwc;
+  int n = (r.Hc / r.s) * r.bwc;
   hipLaunchKernelGGL(k_glue_ratios, dim3((n + 127) / 128), dim3(128), 0, st, r, out);
 }
 

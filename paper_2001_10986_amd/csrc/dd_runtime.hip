@@ -325,7 +325,8 @@ static dd_status fail(dd_ctx* c, dd_status s, const char* fmt, ...) {
 // cells {2a, 2a+1} in each direction, partition B {2g-1, 2g} (clipped at the
 // border), Sec. 7.1.  Quadrants are stored top-left, top-right, bottom-left,
 // bottom-right; absent ones are -1.
-static void build_cells(int bh, int bw, int part, std::vector<int4>& q, std::vector<int2>& org) {
+static void build_cells(int bh, int bw, int part, int s, std::vector<int4>& q,
+                        std::vector<int2>& org) {
   const int gr = part == 0 ? bh / 2 : bh / 2 + 1;
   const int gc = part == 0 ? bw / 2 : bw / 2 + 1;
   q.clear();
@@ -340,7 +341,7 @@ static void build_cells(int bh, int bw, int part, std::vector<int4>& q, std::vec
         id[a] = (br >= 0 && br < bh && bc >= 0 && bc < bw) ? br * bw + bc : -1;
       }
       q.push_back(make_int4(id[0], id[1], id[2], id[3]));
-      org.push_back(make_int2(r0 * kS, c0 * kS));
+      org.push_back(make_int2(r0 * s, c0 * s));
     }
 }
 
@@ -349,7 +350,7 @@ static dd_status upload_cells(dd_ctx* c) {
   for (int p = 0; p < 2; p++) {
     std::vector<int4> q;
     std::vector<int2> org;
-    build_cells(l.bh, l.bw, p, q, org);
+    build_cells(l.bh, l.bw, p, c->s, q, org);
     Cells& C = c->cells[p];
     hipFree(C.q);
     hipFree(C.org);
@@ -528,8 +529,8 @@ static dd_status init_level0(dd_ctx* c) {
   for (int b = 0; b < c->nb; b++) {
     const int br = b / l.bw, bc = b % l.bw;
     double m = 0;
-    for (int i = 0; i < kS; i++)
-      for (int j = 0; j < kS; j++) m += mu[(int64_t)(br * kS + i) * l.W + bc * kS + j];
+    for (int i = 0; i < c->s; i++)
+      for (int j = 0; j < c->s; j++) m += mu[(int64_t)(br * c->s + i) * l.W + bc * c->s + j];
     bm[b] = m;
   }
   const int nzy = (int)ypos.size();
@@ -595,7 +596,7 @@ extern "C" dd_status dd_init(const double* mu, const double* nu, int H, int W, i
   if (!out) return fail(nullptr, DD_EINVAL, "out is NULL");
   *out = nullptr;
   if (!mu || !nu) return fail(nullptr, DD_EINVAL, "mu/nu is NULL");
-  if (s != kS) return fail(nullptr, DD_EINVAL, "basic_cell must be %d", kS);
+  if (s != 2 && s != 4) return fail(nullptr, DD_EINVAL, "basic_cell must be 2 or 4 (got %d)", s);
   if (nlev < 1 || nlev > 16) return fail(nullptr, DD_EINVAL, "n_levels out of range");
   if (opt && !(opt->cost_p > 1.0 && opt->cost_p <= 16.0))
     return fail(nullptr, DD_EINVAL, "cost exponent p must lie in (1, 16] (got %g)", opt->cost_p);
@@ -622,6 +623,7 @@ extern "C" dd_status dd_init(const double* mu, const double* nu, int H, int W, i
   }
   c->st = (hipStream_t)c->opt.stream;
   c->nlev = nlev;
+  c->s = s;
   c->sched.assign(schedule, schedule + n_stages);
   c->eps = schedule[0].eps;
   c->L.resize(nlev);
@@ -636,8 +638,8 @@ extern "C" dd_status dd_init(const double* mu, const double* nu, int H, int W, i
     const int f = nlev - 1 - i;
     l.H = H >> f;
     l.W = W >> f;
-    l.bh = l.H / kS;
-    l.bw = l.W / kS;
+    l.bh = l.H / s;
+    l.bw = l.W / s;
     l.h = (double)(1 << f) / mx;
     const size_t n = (size_t)l.H * l.W;
     if (dmalloc(&l.mu, n) != hipSuccess || dmalloc(&l.nu, n) != hipSuccess)
@@ -663,7 +665,7 @@ extern "C" dd_status dd_init(const double* mu, const double* nu, int H, int W, i
   // validation of the finest images
   {
     const Level& l = c->L[nlev - 1];
-    ddk::launch_validate(l.mu, l.nu, l.H, l.W, c->dscal, c->st);
+    ddk::launch_validate(l.mu, l.nu, c->s, l.H, l.W, c->dscal, c->st);
     if (hipMemcpyAsync(c->hscal, c->dscal, sizeof(double) * 4, hipMemcpyDeviceToHost, c->st) !=
             hipSuccess ||
         hipStreamSynchronize(c->st) != hipSuccess)
@@ -710,6 +712,7 @@ static HalfParams make_params(dd_ctx* c, int part) {
   const Level& l = c->L[c->lev];
   HalfParams p{};
   p.H = l.H;
+  p.s = c->s;
   p.W = l.W;
   p.bh = l.bh;
   p.bw = l.bw;
@@ -799,6 +802,7 @@ static dd_status warm_start(dd_ctx* c, const HalfParams& p) {
 extern "C" dd_status dd_set_warm_prediction(dd_ctx* c, const float* y_dev, float min_rms) {
   if (!c || !(min_rms >= 0)) return DD_EINVAL;
   if (c->in_batch) return fail(c, DD_ESTATE, "the context belongs to a batch");
+  if (c->s != 4) return fail(c, DD_EINVAL, "predicted starts assume 4x4 basic cells");
   c->warm_given = y_dev;
   c->warm_given_rms = min_rms;
   return DD_OK;
@@ -808,6 +812,8 @@ extern "C" dd_status dd_set_warm_start(dd_ctx* c, dd_mlp* net, int policy, float
   if (!c || policy < 0 || policy > 3 || !(min_rms >= 0)) return DD_EINVAL;
   if (net && c->opt.cost_p != 2.0)
     return fail(c, DD_EINVAL, "the warm-start network's features assume the quadratic cost");
+  if (net && c->s != 4)
+    return fail(c, DD_EINVAL, "the warm-start network's features assume 4x4 basic cells");
   if (net) {
     int n_in = 0, n_out = 0;
     dd_mlp_shape(net, &n_in, &n_out, nullptr, nullptr);
@@ -839,6 +845,7 @@ extern "C" dd_status dd_collect_cells(dd_ctx* c, float* x_dev, float* t_dev, flo
                                       int* cell_dev, int cap, int* n_out) {
   if (!c || !n_out || cap < 0 || (cap > 0 && (!x_dev || !t_dev || !mask_dev))) return DD_EINVAL;
   if (c->last_part < 0) return fail(c, DD_ESTATE, "no half-iteration on this level yet");
+  if (c->s != 4) return fail(c, DD_EINVAL, "cell features assume 4x4 basic cells");
   if (!c->prev_valid)
     return fail(c, DD_ESTATE, "the last sweep ran in a batch; its starting potentials are not kept");
   if (!c->dcount) HIPCHK(c, dmalloc(&c->dcount, 1));
@@ -1117,6 +1124,7 @@ static dd_status enqueue_glue(dd_ctx* c, GlueScratch& g, double* dV, double* inf
   up(g.deg, deg.data(), sizeof(double) * na);
   if (e != hipSuccess) return fail(c, DD_EHIP, "gluing upload: %s", hipGetErrorString(e));
   ddk::RefineParams R{};
+  R.s = c->s;
   R.Hc = l.H;
   R.Wc = l.W;
   R.bwc = l.bw;
@@ -1132,13 +1140,13 @@ static dd_status enqueue_glue(dd_ctx* c, GlueScratch& g, double* dV, double* inf
   return DD_OK;
 }
 
-__global__ void k_glue_apply(const double* aA, const double* V, double eps, int Hc, int Wc,
+__global__ void k_glue_apply(const double* aA, const double* V, double eps, int s, int Hc, int Wc,
                              double* out) {
   long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (i >= (long long)Hc * Wc) return;
   const int r = (int)(i / Wc), cc = (int)(i % Wc);
-  const int na_c = Wc / (2 * kS);
-  out[i] = aA[i] + eps * V[(r / (2 * kS)) * na_c + cc / (2 * kS)];
+  const int na_c = Wc / (2 * s);
+  out[i] = aA[i] + eps * V[(r / (2 * s)) * na_c + cc / (2 * s)];
 }
 
 extern "C" dd_status dd_refine(dd_ctx* c) {
@@ -1147,6 +1155,7 @@ extern "C" dd_status dd_refine(dd_ctx* c) {
   const Level& lc = c->L[c->lev];
   const Level& lf = c->L[c->lev + 1];
   ddk::RefineParams R{};
+  R.s = c->s;
   R.Hc = lc.H;
   R.Wc = lc.W;
   R.bwc = lc.bw;
@@ -1181,7 +1190,7 @@ extern "C" dd_status dd_refine(dd_ctx* c) {
     }
     long long n = (long long)lc.H * lc.W;
     hipLaunchKernelGGL(k_glue_apply, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->st,
-                       c->alpha[0], dV, c->eps, lc.H, lc.W, fg);
+                       c->alpha[0], dV, c->eps, c->s, lc.H, lc.W, fg);
     double hinfo[3] = {0, 0, 0};
     HIPCHK(c, hipMemcpyAsync(hinfo, dinfo, sizeof hinfo, hipMemcpyDeviceToHost, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));  // the scratch of gs is released after this
@@ -1281,7 +1290,7 @@ extern "C" dd_status dd_run_schedule(dd_ctx* c, dd_run_stats* out) {
 // doubles on the context's device).
 static dd_status cost_report(dd_ctx* c, double* scratch, dd_cost_report* r) {
   const Level& l = c->L[c->lev];
-  ddk::launch_diag(c->row_off, c->row_len, c->col, c->val, l.mu, l.nu, l.H, l.W, l.bw, c->nb,
+  ddk::launch_diag(c->row_off, c->row_len, c->col, c->val, l.mu, l.nu, c->s, l.H, l.W, l.bw, c->nb,
                    scratch, c->dscal, c->st);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipMemcpyAsync(c->hscal, c->dscal, sizeof(double) * 3, hipMemcpyDeviceToHost, c->st));
@@ -1356,8 +1365,8 @@ extern "C" dd_status dd_certificate(dd_ctx* c, dd_cert_report* r, double* alpha_
   }
   // 3. glued potential; 4. Y-iteration over the stored support and the sums
   hipLaunchKernelGGL(k_glue_apply, dim3((unsigned)((npx + 255) / 256)), dim3(256), 0, c->st,
-                     c->alpha[0], dV, c->eps, l.H, l.W, ah);
-  ddk::launch_cert_y(c->row_off, c->row_len, c->col, ah, l.mu, l.nu, l.H, l.W, l.bw, nb, c->eps,
+                     c->alpha[0], dV, c->eps, c->s, l.H, l.W, ah);
+  ddk::launch_cert_y(c->row_off, c->row_len, c->col, ah, l.mu, l.nu, l.H, l.W, c->s, l.bw, nb, c->eps,
                      l.h, 0.5 * c->opt.cost_p, scr, bh, sums, c->st);
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) e = hipMemcpyAsync(hs, sums, sizeof hs, hipMemcpyDeviceToHost, c->st);
