@@ -223,4 +223,28 @@ void launch_cert_y(const int64_t* row_off, const int* row_len, const int* col,
                    int bs, int bw, int n_basic, double eps, double h, double half_p,
                    double* scratch, double* beta_hat, double* sums, hipStream_t st);
 
+// Single sparse multi-scale Sinkhorn (dd_single.hip).  dir 0: X side (p an X
+// pixel, the other side Y), dir 1: Y side.
+void sg_launch_support(int dir, const double* pot_p, const double* pot_q, int H, int W,
+                       double hp, double half_p, double eps, double log_theta, int margin,
+                       int4* box, long long* counts, hipStream_t st);
+int sg_pass_blocks(int H, int W);
+void sg_launch_pass(int dir, const double* pot_p, const double* pot_q, const double* m_p,
+                    const double* m_q, double* scale_p, const double* scale_q, const int4* box,
+                    int H, int W, double hp, double half_p, double eps, double log_theta,
+                    int update, double* part, double* out5, hipStream_t st);
+void sg_launch_absorb(double* pot, double* scale, const double* m, long long n, double eps,
+                      hipStream_t st);
+void sg_launch_fill_box(int4* box, long long n, int4 v, hipStream_t st);
+void sg_launch_fill(double* a, long long n, double v, hipStream_t st);
+void sg_launch_widen(int4* box, long long n, int H, int W, int margin, hipStream_t st);
+void sg_launch_refine_box(const int4* cbox, int Wc, int4* fbox, int Hf, int Wf, int margin,
+                          hipStream_t st);
+void sg_launch_final(const double* alpha, const double* beta, const double* mu, const double* nu,
+                     const double* u, const double* v, const int4* xbox, int H, int W, double hp,
+                     double half_p, double eps, double log_theta, double* part, double* out5,
+                     hipStream_t st);
+void sg_launch_total(const double* pot, const double* scale, const double* m, long long n,
+                     double eps, double* out, hipStream_t st);
+
 }  // namespace ddk

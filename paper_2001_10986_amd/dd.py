@@ -27,7 +27,8 @@ EXPORTED = ["dd_options_default", "dd_init", "dd_half_iterate", "dd_set_eps", "d
             "dd_batch_info", "dd_batch_free", "dd_set_launch", "dd_batch_set_launch",
             "dd_autotune", "dd_batch_autotune", "dd_get_launch",
             "dd_batch_last_error", "dd_certificate", "dd_cost_noalloc",
-            "dd_set_warm_prediction"]
+            "dd_set_warm_prediction", "dd_single_options_default", "dd_single_solve",
+            "dd_single_last_error"]
 
 DD_BATCH_GRAPH = 1
 DD_PREC_SPLIT, DD_PREC_FP64 = 0, 1
@@ -107,6 +108,25 @@ class CertReport(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class SingleOptions(C.Structure):
+    _fields_ = [("err_tol", C.c_double), ("err_norm", C.c_int), ("theta", C.c_double),
+                ("absorb", C.c_double), ("max_iter", C.c_int), ("check_every", C.c_int),
+                ("cost_p", C.c_double), ("stream", C.c_void_p)]
+
+
+class SingleReport(C.Structure):
+    _fields_ = [("n_stages", C.c_int), ("level", C.c_int), ("eps", C.c_double),
+                ("loops_total", C.c_int64), ("loops_max_stage", C.c_int), ("n_absorb", C.c_int),
+                ("entries_max", C.c_int64), ("entries_final", C.c_int64),
+                ("entry_evals", C.c_int64), ("err_x_l1", C.c_double), ("err_x_linf", C.c_double),
+                ("err_y_l1", C.c_double), ("cost", C.c_double), ("primal", C.c_double),
+                ("dual", C.c_double), ("plan_mass", C.c_double), ("ms", C.c_double),
+                ("failed", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class PlanView(C.Structure):
     _fields_ = [("level", C.c_int), ("H", C.c_int), ("W", C.c_int), ("eps", C.c_double),
                 ("n_basic", C.c_int64), ("nnz", C.c_int64), ("row_ptr", C.c_void_p),
@@ -137,6 +157,14 @@ def _load():
     lib.dd_refine.argtypes = [C.c_void_p]
     lib.dd_run_schedule.argtypes = [C.c_void_p, P(RunStats)]
     lib.dd_cost.argtypes = [C.c_void_p, P(CostReport)]
+    lib.dd_single_options_default.argtypes = [P(SingleOptions)]
+    lib.dd_single_options_default.restype = None
+    lib.dd_single_solve.argtypes = [C.c_void_p, C.c_void_p, C.c_int, C.c_int, C.c_int,
+                                    C.c_void_p, C.c_int, P(SingleOptions), P(SingleReport),
+                                    C.c_void_p, C.c_void_p]
+    lib.dd_single_solve.restype = C.c_int
+    lib.dd_single_last_error.argtypes = []
+    lib.dd_single_last_error.restype = C.c_char_p
     lib.dd_cost_noalloc.argtypes = [C.c_void_p, P(CostReport)]
     lib.dd_certificate.argtypes = [C.c_void_p, P(CertReport), C.c_void_p, C.c_void_p]
     lib.dd_export_plan.argtypes = [C.c_void_p, P(PlanView)]
@@ -485,3 +513,44 @@ class Batch:
         a, b, c = C.c_int(), C.c_longlong(), C.c_int()
         self._chk(lib.dd_batch_info(self._h, C.byref(a), C.byref(b), C.byref(c)), "dd_batch_info")
         return {"n_problems": a.value, "n_sweeps": b.value, "n_captures": c.value}
+
+
+DD_SINGLE_LINF, DD_SINGLE_L1 = 0, 1
+
+
+def single_solve(mu, nu, schedule, n_levels=1, err_tol=1e-7, err_norm=DD_SINGLE_LINF,
+                 theta=1e-10, absorb=30.0, max_iter=200000, check_every=16, cost_p=2.0,
+                 potentials=False, stream=None):
+    """Single sparse multi-scale Sinkhorn on the whole grid (dd_single_solve,
+    include/dd_single.h): host images mu, nu (H x W float64), stages
+    (level, eps[, n]).  Returns the report as a dict (status included); with
+    potentials=True also the total potentials alpha, beta of the last level."""
+    mu_c = np.ascontiguousarray(mu, dtype=np.float64)
+    nu_c = np.ascontiguousarray(nu, dtype=np.float64)
+    H, W = mu_c.shape
+    opt = SingleOptions()
+    lib.dd_single_options_default(C.byref(opt))
+    opt.err_tol, opt.err_norm, opt.theta, opt.absorb = err_tol, err_norm, theta, absorb
+    opt.max_iter, opt.check_every, opt.cost_p = max_iter, check_every, cost_p
+    if stream is not None:
+        opt.stream = stream
+    arr = (Stage * len(schedule))(*[Stage(int(x[0]), float(x[1]), int(x[2]) if len(x) > 2 else 0)
+                                    for x in schedule])
+    rep = SingleReport()
+    lev = max(int(x[0]) for x in schedule)
+    f = n_levels - 1 - lev
+    a = b = None
+    if potentials:
+        a = np.empty((H >> f) * (W >> f))
+        b = np.empty_like(a)
+    rc = lib.dd_single_solve(_p(mu_c), _p(nu_c), H, W, n_levels, arr, len(schedule),
+                             C.byref(opt), C.byref(rep), None if a is None else _p(a),
+                             None if b is None else _p(b))
+    if rc < 0:
+        raise DDError(f"dd_single_solve: {lib.dd_single_last_error().decode()} ({rc})")
+    out = rep.as_dict()
+    out["status"] = rc
+    if potentials:
+        out["alpha"] = a.reshape(H >> f, W >> f)
+        out["beta"] = b.reshape(H >> f, W >> f)
+    return out

@@ -11,7 +11,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     names = set()
-    for h in ("dd.h", "dd_mlp.h"):
+    for h in ("dd.h", "dd_mlp.h", "dd_single.h"):
         text = open(os.path.join(ROOT, "include", h)).read()
         text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
         names |= set(re.findall(r"\b(dd_[a-z0-9_]+)\s*\(", text))
@@ -31,6 +31,14 @@ def test_library_exports_every_declared_symbol():
     missing = [n for n in _declared() if not hasattr(lib, n)]
     assert not missing, missing
     assert set(dd.EXPORTED) <= set(_declared())
+
+
+def test_single_options_default_without_gpu():
+    from paper_2001_10986_amd import dd
+    o = dd.SingleOptions()
+    dd.lib.dd_single_options_default(ctypes.byref(o))
+    assert o.err_tol == 1e-7 and o.theta == 1e-10 and o.err_norm == dd.DD_SINGLE_LINF
+    assert o.cost_p == 2.0 and o.check_every == 16
 
 
 def test_options_default_without_gpu():

@@ -1,0 +1,80 @@
+"""Single sparse multi-scale Sinkhorn (the comparison method of Sec. 7.4) on
+the GPU.  It approximates the unique entropic optimum (Proposition "Optimal
+entropic transport couplings" (i)) directly, so the reference is that optimum
+computed densely by the FP64 dense solver; the differences come from the
+stopping tolerance, the kernel truncation (entries of the stabilised kernel
+below theta) and the FP32 exponentials of the passes (relative error of a
+kernel entry about 1e-7, which moves the fixed point by as much)."""
+import numpy as np
+import pytest
+
+from paper_2001_10986_amd import datagen
+
+pytestmark = pytest.mark.gpu
+
+
+def _schedule(N, coarsest, final):
+    stages, nlev = datagen.paper_schedule(N, coarsest=coarsest, final_factor=final)
+    return stages, nlev
+
+
+@pytest.mark.parametrize("cost_p", [2.0, 1.5])
+def test_matches_dense_entropic_optimum(cost_p):
+    from oracle import dense
+    from paper_2001_10986_amd import dd
+    N = 32
+    mu, nu = datagen.small_pair(N, 4, seed=7)
+    stages, nlev = _schedule(N, 8, 1.0)
+    eps = stages[-1][1]
+    r = dd.single_solve(mu, nu, stages, n_levels=nlev, err_tol=1e-13, cost_p=cost_p,
+                        potentials=True)
+    C = dense.grid_cost(N, N, 1.0 / N, p=cost_p)
+    P = dense.entropic_ot(C, mu.ravel(), nu.ravel(), eps)
+    a, b = r["alpha"].ravel(), r["beta"].ravel()
+    Q = np.exp((a[:, None] + b[None, :] - C) / eps) * np.outer(mu.ravel(), nu.ravel())
+    opt_cost = float((C * P).sum())
+    print(f"p={cost_p}: loops {r['loops_total']}, entries max {r['entries_max']}, "
+          f"cost {r['cost']:.12g} vs {opt_cost:.12g}, plan diff {np.abs(Q - P).max():.3e}",
+          flush=True)
+    assert r["status"] == 0 and r["failed"] == 0 and r["level"] == nlev - 1
+    assert r["err_x_linf"] <= 1e-13 and r["err_y_l1"] <= 1e-12
+    assert abs(r["cost"] - opt_cost) <= 1e-6 * opt_cost
+    assert np.abs(Q - P).max() <= 1e-6 * P.max()
+    # weak duality around the optimum's score
+    from oracle import certificate as cert
+    opt_score = cert.primal_score(P, C, mu.ravel(), nu.ravel(), eps)
+    assert r["dual"] <= opt_score + 1e-6 * abs(opt_score)
+    assert abs(r["primal"] - opt_score) <= 1e-6 * abs(opt_score)
+    assert abs(r["dual"] - opt_score) <= 1e-6 * abs(opt_score)
+
+
+def test_larger_instance_against_the_decomposition():
+    # 128x128 on the paper's protocol; the single Sinkhorn stops on the
+    # L-infinity X-marginal error 1e-7 of Sec. 7.4, the decomposition on its
+    # L1 error 1e-4.  Both approximate the same entropic optimum: its dual
+    # score bounds the DD primal score from below (weak duality), its
+    # Y-marginal is exact, its L1 X-error is at most the pixel count times the
+    # L-infinity tolerance (the paper's summary table lists 3.1e-4 at this
+    # size; measured 3.1e-4), and its transport cost differs from the DD cost
+    # by at most the DD's own distance to the optimum (its relative PD gap)
+    # plus what moving its X-marginal error costs at most (the L1 error times
+    # the largest cost on the unit square, 2).
+    from paper_2001_10986_amd import dd
+    N = 128
+    mu, nu, _ = datagen.config3_pair(N=N)
+    stages, nlev = _schedule(N, 8, 0.25)
+    r = dd.single_solve(mu, nu, stages, n_levels=nlev, err_tol=1e-7, max_iter=50000)
+    g = dd.Problem(mu, nu, stages, s=4, n_levels=nlev, err_tol=1e-4)
+    g.run_schedule()
+    c = g.cost()
+    pd = g.certificate()
+    print(f"128^2: single loops {r['loops_total']}, entries max {r['entries_max']} final "
+          f"{r['entries_final']}, {r['ms']:.1f} ms, cost {r['cost']:.10g}, L1 X {r['err_x_l1']:.2e}; "
+          f"DD cost {c['cost']:.10g}, nnz {c['nnz']}, gap {pd['rel_gap']:.2e}; "
+          f"rel dual score {(r['dual'] - pd['dual']) / pd['dual']:.3e}",
+          flush=True)
+    assert r["status"] == 0 and r["failed"] == 0
+    assert r["err_x_linf"] <= 1e-7 and r["err_x_l1"] <= N * N * 1e-7 and r["err_y_l1"] <= 1e-10
+    assert r["dual"] <= pd["primal"]
+    assert r["err_x_l1"] >= 1e-6  # the L-infinity stop leaves a sizeable L1 error
+    assert abs(r["cost"] - c["cost"]) <= 10 * pd["rel_gap"] * c["cost"] + 2.0 * r["err_x_l1"]
