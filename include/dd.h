@@ -94,6 +94,12 @@ typedef struct {
                               convex (Sec. 7.1, Sec. 8; Monge setting of Sec. 5); default 2,
                               the quadratic cost of the paper's experiments.  eps is in units
                               of that cost (h^p per pixel^p on the unit square) */
+  int safeguard_after;     /* >0: a cell not converged after this many loops counts as failing
+                              and goes to the safeguard (at most max_sinkhorn_iter); 0: only
+                              at max_sinkhorn_iter.  Default 1024: past the Newton budget a
+                              cell that has not converged is one whose couplings have nearly
+                              vanished (its whole support far from the block), which the
+                              doubled eps resolves in a few hundred loops */
 } dd_options;
 
 /* Kernels of one sweep (indices of the ms_kernel arrays): 0 cell sizes scan,

@@ -642,13 +642,19 @@ static void solve_cell(const ddo_ctx* c, int part, const cell_t* C, cell_out_t* 
   double tol = c->opt.err_tol * muJ, err = 0;
   int loops = 0;
   int used = 0;
-  int rc = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nuJ, lam, cp, tol, c->opt.max_iter,
+  /* A cell fails when it is not converged after the safeguard trigger (the
+   * loop cap, or safeguard_after loops when that is set and smaller). */
+  int cap0 = c->opt.max_iter;
+  if (c->opt.safeguard && c->opt.safeguard_after > 0 && c->opt.safeguard_after < cap0)
+    cap0 = c->opt.safeguard_after;
+  int rc = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nuJ, lam, cp, tol, cap0,
                         c->opt.accel, c->opt.newton_after, F, G, Fh, &loops, &err, &used);
   o->loops = loops;
   if (rc != 0 && c->opt.safeguard) {
     /* Safeguard of Sec. 7.4: solve the failing cell at a temporarily larger
      * eps (2 eps, same f), then return to eps from there.  READING: one
-     * doubling, warm-started from the stored potential. */
+     * doubling, warm-started from the stored potential; each of the two
+     * solves may take up to max_iter loops. */
     int l2 = 0, l3 = 0;
     for (int k = 0; k < nx; k++) F[k] = F0[k] * 0.5;
     int r2 = sinkhorn_log(nx, xr, xc, mu, ny, yr, yc, nuJ, lam * 0.5, cp, tol, c->opt.max_iter,
@@ -802,7 +808,7 @@ int ddo_init(const double* mu, const double* nu, int H, int W, int s, int nlev, 
     sn += nu[p];
   }
   if (fabs(sm - 1) > 1e-9 || fabs(sn - 1) > 1e-9) return -1;
-  if (!(opt->cost_p == 0 || opt->cost_p > 1)) return -1;
+  if (!(opt->cost_p == 0 || opt->cost_p > 1) || opt->safeguard_after < 0) return -1;
   ddo_ctx* c = calloc(1, sizeof(ddo_ctx));
   if (!c) return -2;
   c->nlev = nlev;

@@ -45,6 +45,8 @@ typedef struct {
   int accel;         /* 1: Chebyshev-accelerated X-iteration, 0: plain Sinkhorn */
   int newton_after;  /* >0: switch a cell to Newton steps after this many loops; 0: never */
   double cost_p;     /* c(x,y) = |x-y|^p, p > 1 (Sec. 7.1: h(x-y), h strictly convex); 0 = 2 */
+  int safeguard_after; /* >0: a cell not converged after this many loops counts as failing
+                          and goes to the safeguard (capped by max_iter); 0: at max_iter */
 } ddo_opts;
 
 typedef struct {

@@ -16,7 +16,7 @@ _lib = None
 class Opts(C.Structure):
     _fields_ = [("err_tol", C.c_double), ("trunc", C.c_double), ("max_iter", C.c_int),
                 ("n_threads", C.c_int), ("safeguard", C.c_int), ("accel", C.c_int),
-                ("newton_after", C.c_int), ("cost_p", C.c_double)]
+                ("newton_after", C.c_int), ("cost_p", C.c_double), ("safeguard_after", C.c_int)]
 
 
 class Stage(C.Structure):
@@ -87,13 +87,19 @@ class Oracle:
 
     def __init__(self, mu, nu, s=4, n_levels=1, eps=1.0, err_tol=1e-5, trunc=1e-15,
                  max_iter=50000, n_threads=0, safeguard=1, accel=1, newton_after=384,
-                 cost_p=2.0):
+                 cost_p=2.0, safeguard_after=None):
+        # safeguard_after: loops after which an unconverged cell goes to the
+        # safeguard; default 1024 with the Newton fallback, else the loop cap
+        # (so that the plain iteration keeps the safeguard at its cap)
         mu = np.ascontiguousarray(mu, dtype=np.float64)
         nu = np.ascontiguousarray(nu, dtype=np.float64)
         assert mu.shape == nu.shape and mu.ndim == 2
         self.H, self.W = mu.shape
         self.s, self.n_levels = s, n_levels
-        o = Opts(err_tol, trunc, max_iter, n_threads, safeguard, accel, newton_after, cost_p)
+        if safeguard_after is None:
+            safeguard_after = 1024 if newton_after > 0 else 0
+        o = Opts(err_tol, trunc, max_iter, n_threads, safeguard, accel, newton_after, cost_p,
+                 safeguard_after)
         h = C.c_void_p()
         rc = lib().ddo_init(_dp(mu), _dp(nu), self.H, self.W, s, n_levels, eps, C.byref(o),
                             C.byref(h))

@@ -28,6 +28,7 @@ struct HalfParams {
   double half_p, hp;           // cost c = |x-y|^p: p/2 (1 for the quadratic cost) and h^p
   double err_tol, trunc;
   int max_iter, safeguard, accel;
+  int cap0;                    // loop cap of the first solve (safeguard trigger), <= max_iter
   int newton_after;            // >0: hand a cell to Newton steps after this many loops
   int fp64;                    // 1: every cell on the log-domain solver, FP64 exponentials
   const double* mu;            // level mu, H*W

@@ -834,6 +834,9 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
     const int xr = g.R0 + xg;  // pixel row of the lane's 8 pixels
 
     for (int phase = 0; phase < phases; phase++) {
+      // the first solve stops at the safeguard trigger, the safeguard's two
+      // solves at the loop cap
+      const int cap = phase == 0 ? p.cap0 : p.max_iter;
       if (phase == 1) {  // safeguard: 2*eps from the stored potential
         lam = p.lam * 0.5;
         if (tid < 64) sh.F0[tid] = sh.F0orig[tid] * 0.5;
@@ -934,7 +937,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
 #pragma unroll
         for (int w = 0; w < NW; w++) r += wred[w][lane];
         float unew;
-        const XUpdate xu = x_update(r, mux, uw[lane], &lup, &unew, tol, it, p.max_iter, p.accel,
+        const XUpdate xu = x_update(r, mux, uw[lane], &lup, &unew, tol, it, cap, p.accel,
                                     sh.cheb[wave], lane);
         err_last = xu.err;
         r_last = r;
@@ -1243,6 +1246,7 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
     const int xr = g.R0 + xg;
 
     for (int phase = 0; phase < phases; phase++) {
+      const int cap = phase == 0 ? p.cap0 : p.max_iter;  // safeguard trigger, then loop cap
       if (phase == 1) {
         lam = p.lam * 0.5;
         if (tid < 64) sh.F0[tid] = sh.F0orig[tid] * 0.5;
@@ -1366,7 +1370,7 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
           double e = mu > 0 ? fabs((double)u * (double)r - mu) : 0.0;
           e = wave_sum(e);
           sh.r[lane] = r;
-          const bool go_on = !(e <= tol) && it < p.max_iter && (e == e);
+          const bool go_on = !(e <= tol) && it < cap && (e == e);
           if (lane == 0) {
             double a0 = 0, b0 = 1, d0 = 0;
             const bool acc0 = go_on && p.accel && cheb_next(sh.cheb, it, e, &a0, &b0, &d0);
@@ -1403,7 +1407,7 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
           converged = true;
           break;
         }
-        if (!(err == err) || it >= p.max_iter) break;
+        if (!(err == err) || it >= cap) break;
         if (sh.flag) {
           // exact X-iteration in the log domain over all slabs:
           //   F0(x) = -LSE_y[G(y) + log nu_J(y) - C(x,y)],  G(y) = -(m(y) + log S(y))
@@ -1841,6 +1845,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
     constexpr bool quad = QUAD;  // quadratic cost: row and column parts separate
     const int phases = p.safeguard ? 3 : 1;
     for (int phase = 0; phase < phases; phase++) {
+      const int cap = phase == 0 ? p.cap0 : p.max_iter;  // safeguard trigger, then loop cap
       if (phase == 1) {
         lam = p.lam * 0.5;
         if (tid < 64) sh.F[tid] = sh.F0orig[tid] * 0.5;
@@ -1913,7 +1918,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
           e = wave_sum(e);
           if (lane == 0) {
             double a0 = 0, b0 = 1, d0 = 0;
-            const bool go_on = !(e <= tol) && it < p.max_iter && (e == e);
+            const bool go_on = !(e <= tol) && it < cap && (e == e);
             sh.cacc = go_on && p.accel && cheb_next(sh.cheb, it, e, &a0, &b0, &d0);
             sh.ca = a0;
             sh.cb = b0;
@@ -1927,7 +1932,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
           converged = true;
           break;
         }
-        if (!(err == err) || it >= p.max_iter) break;
+        if (!(err == err) || it >= cap) break;
         if (tid < 64 && sh.mu[tid] > 0) {
           const double F = sh.F[tid];
           const double Fn = sh.cacc ? sh.ca * F + sh.cb * sh.Fh[tid] + sh.cd * sh.Fp[tid] : sh.Fh[tid];
@@ -2014,7 +2019,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_big(const HalfParams* __restr
             converged = true;
             break;
           }
-          if (!(err == err) || it >= p.max_iter) break;
+          if (!(err == err) || it >= cap) break;
           bool step = false;
           double t = 1.0;
           if (build_w) {

@@ -464,6 +464,7 @@ extern "C" void dd_options_default(dd_options* o) {
   o->timing = 0;
   o->stream = nullptr;
   o->cost_p = 2.0;
+  o->safeguard_after = 1024;
 }
 
 extern "C" void dd_free(dd_ctx* c) {
@@ -600,6 +601,8 @@ extern "C" dd_status dd_init(const double* mu, const double* nu, int H, int W, i
   if (nlev < 1 || nlev > 16) return fail(nullptr, DD_EINVAL, "n_levels out of range");
   if (opt && !(opt->cost_p > 1.0 && opt->cost_p <= 16.0))
     return fail(nullptr, DD_EINVAL, "cost exponent p must lie in (1, 16] (got %g)", opt->cost_p);
+  if (opt && opt->safeguard_after < 0)
+    return fail(nullptr, DD_EINVAL, "safeguard_after must be >= 0 (got %d)", opt->safeguard_after);
   if (H <= 0 || W <= 0 || W > 65536) return fail(nullptr, DD_EINVAL, "bad size");
   const int div = (2 * s) << (nlev - 1);
   if (H % div || W % div)
@@ -728,6 +731,9 @@ static HalfParams make_params(dd_ctx* c, int part) {
   p.trunc = c->opt.trunc_threshold;
   p.max_iter = c->opt.max_sinkhorn_iter;
   p.safeguard = c->opt.safeguard;
+  p.cap0 = p.max_iter;
+  if (p.safeguard && c->opt.safeguard_after > 0 && c->opt.safeguard_after < p.cap0)
+    p.cap0 = c->opt.safeguard_after;
   p.accel = c->opt.accel;
   p.newton_after = c->opt.newton_after;
   p.fp64 = c->opt.precision == DD_PREC_FP64;

@@ -42,7 +42,8 @@ class Options(C.Structure):
     _fields_ = [("err_tol", C.c_double), ("trunc_threshold", C.c_double),
                 ("max_sinkhorn_iter", C.c_int), ("safeguard", C.c_int), ("accel", C.c_int),
                 ("newton_after", C.c_int), ("precision", C.c_int), ("inputs_on_device", C.c_int),
-                ("timing", C.c_int), ("stream", C.c_void_p), ("cost_p", C.c_double)]
+                ("timing", C.c_int), ("stream", C.c_void_p), ("cost_p", C.c_double),
+                ("safeguard_after", C.c_int)]
 
 
 N_KERNELS, N_BINS = 12, 7
@@ -239,7 +240,9 @@ class Problem:
 
     def __init__(self, mu, nu, schedule, s=4, n_levels=1, err_tol=1e-5, trunc=1e-15,
                  max_iter=50000, safeguard=1, stream=None, timing=False, accel=1,
-                 newton_after=384, precision=DD_PREC_SPLIT, cost_p=2.0):
+                 newton_after=384, precision=DD_PREC_SPLIT, cost_p=2.0, safeguard_after=None):
+        # safeguard_after None: 1024 with the Newton fallback, else the loop
+        # cap (the plain iteration keeps the safeguard at its cap)
         opt = Options()
         lib.dd_options_default(C.byref(opt))
         opt.err_tol, opt.trunc_threshold = err_tol, trunc
@@ -249,6 +252,9 @@ class Problem:
         opt.newton_after = int(newton_after)
         opt.precision = int(precision)
         opt.cost_p = float(cost_p)
+        if safeguard_after is None:
+            safeguard_after = 1024 if newton_after > 0 else 0
+        opt.safeguard_after = int(safeguard_after)
         on_dev = hasattr(mu, "data_ptr") and getattr(mu, "is_cuda", False)
         if on_dev:
             import torch

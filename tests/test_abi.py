@@ -47,7 +47,7 @@ def test_options_default_without_gpu():
     dd.lib.dd_options_default(ctypes.byref(o))
     assert o.err_tol == 1e-5 and o.trunc_threshold == 1e-15 and o.max_sinkhorn_iter == 50000
     assert o.safeguard == 1 and o.inputs_on_device == 0 and o.accel == 1 and o.newton_after == 384
-    assert o.precision == dd.DD_PREC_SPLIT
+    assert o.precision == dd.DD_PREC_SPLIT and o.cost_p == 2.0 and o.safeguard_after == 1024
 
 
 def test_schedule_recipe():
