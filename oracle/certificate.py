@@ -160,7 +160,12 @@ def certificate(alpha_a, alpha_b, obj, C, mu, nu, eps, basic, cells_a, cells_b, 
         for i in cell:
             alpha_hat[basic[i]] += eps * V[J]
     beta_hat = y_iteration(alpha_hat, C, mu, eps, support=support)
-    dual = float(np.dot(alpha_hat, mu) / eps + np.dot(beta_hat, nu) / eps - nu.sum())
+    # <alpha, mu> and <beta, nu> are integrals against the marginals: pixels
+    # of zero mass contribute nothing (there beta_hat may be infinite, when no
+    # stored pair reaches the pixel)
+    xm, ym = mu > 0, nu > 0
+    dual = float(np.dot(alpha_hat[xm], mu[xm]) / eps + np.dot(beta_hat[ym], nu[ym]) / eps
+                 - nu.sum())
     primal = obj / eps
     return {"V": V, "alpha_hat": alpha_hat, "beta_hat": beta_hat, "dual": dual,
             "primal": primal, "gap": primal - dual, "rel_gap": (primal - dual) / primal,
