@@ -18,8 +18,11 @@ struct Epilogue {
 
 constexpr int kMseBlocks = 256;
 
+constexpr int kMaxSplitK = 8;  // K splits of a GEMM at most (workspace: kMaxSplitK * M * N floats)
+int gemm_splits(int M, int N, int K);
+// part: split-K workspace of kMaxSplitK * M * N floats, or nullptr (no split)
 void launch_gemm(bool ta, bool tb, const unsigned short* a, int lda, const unsigned short* b,
-                 int ldb, int M, int N, int K, const Epilogue& ep, hipStream_t st);
+                 int ldb, int M, int N, int K, const Epilogue& ep, float* part, hipStream_t st);
 void launch_to_bf16_pad(const float* x, int n_rows, int n_cols, int rows, int ld,
                         unsigned short* y, hipStream_t st);
 void launch_mse(const float* y, const float* t, const float* mask, int n, int rows, int d,

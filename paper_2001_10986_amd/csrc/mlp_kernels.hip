@@ -25,27 +25,36 @@ __device__ __forceinline__ float bf16_float(unsigned short b) {
 // a[k*lda + m] when TA), B(k,n) = b[k*ldb + n] (or b[n*ldb + k] when TB), BF16.
 // M, N multiples of 64, K multiple of 32 (callers pad).  A block computes one
 // 64x64 tile with 4 waves, one 32x32 quadrant each; K advances by 32 through
-// LDS.  Matrix-core operand layout: lane l holds rows/cols (l%32) and k
+// LDS, the tiles loaded along the contiguous index of each operand's layout.
+// Matrix-core operand layout: lane l holds rows/cols (l%32) and k
 // (4(l/32) .. +3); the result element (i, j) of register v is
-// i = 8(v/4) + 4(l/32) + v%4, j = l%32.
+// i = 8(v/4) + 4(l/32) + v%4, j = l%32.  Split K (gridDim.z > 1): block z
+// takes K-range z of gridDim.z equal ones and writes its raw partial tile to
+// part + z*M*N; k_splitk_reduce then sums the partials in order of z and
+// applies the epilogue (the same result for every launch).
 template <bool TA, bool TB>
 __global__ __launch_bounds__(256) void k_gemm(const unsigned short* __restrict__ a, int lda,
                                               const unsigned short* __restrict__ b, int ldb,
-                                              int M, int N, int K, Epilogue ep) {
+                                              int M, int N, int K, Epilogue ep,
+                                              float* __restrict__ part) {
   __shared__ unsigned short As[64][32 + 4];
   __shared__ unsigned short Bs[32][64 + 4];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int qi = wave >> 1, qj = wave & 1;
+  const int kc = K / (int)gridDim.z;  // a multiple of 32 (checked by the launcher)
+  const int kb = (int)blockIdx.z * kc, ke = kb + kc;
   floatx16 acc = {};
-  for (int k0 = 0; k0 < K; k0 += 32) {
+  for (int k0 = kb; k0 < ke; k0 += 32) {
     for (int e = tid; e < 64 * 32; e += 256) {
-      const int r = e >> 5, k = e & 31;  // A tile element (r, k)
+      int r, k;  // A tile element (r, k), consecutive threads on contiguous addresses
+      if (TA) { k = e >> 6; r = e & 63; } else { r = e >> 5; k = e & 31; }
       const int gm = m0 + r, gk = k0 + k;
       As[r][k] = TA ? a[(size_t)gk * lda + gm] : a[(size_t)gm * lda + gk];
     }
     for (int e = tid; e < 32 * 64; e += 256) {
-      const int k = e >> 6, c = e & 63;  // B tile element (k, c)
+      int k, c;  // B tile element (k, c)
+      if (TB) { c = e >> 5; k = e & 31; } else { k = e >> 6; c = e & 63; }
       const int gk = k0 + k, gn = n0 + c;
       Bs[k][c] = TB ? b[(size_t)gn * ldb + gk] : b[(size_t)gk * ldb + gn];
     }
@@ -62,12 +71,17 @@ __global__ __launch_bounds__(256) void k_gemm(const unsigned short* __restrict__
     }
     __syncthreads();
   }
+  float* pz = gridDim.z > 1 ? part + (size_t)blockIdx.z * M * N : nullptr;
 #pragma unroll
   for (int v = 0; v < 16; v++) {
     const int i = m0 + 32 * qi + 8 * (v >> 2) + 4 * (lane >> 5) + (v & 3);
     const int j = n0 + 32 * qj + (lane & 31);
     float x = acc[v];
     const size_t at = (size_t)i * N + j;
+    if (pz) {
+      pz[at] = x;
+      continue;
+    }
     if (ep.bias) x += ep.bias[j];
     if (ep.out_f32) ep.out_f32[at] = x;             // pre-activation / plain output
     if (ep.relu) x = x > 0.f ? x : 0.f;
@@ -76,13 +90,39 @@ __global__ __launch_bounds__(256) void k_gemm(const unsigned short* __restrict__
   }
 }
 
+__global__ void k_splitk_reduce(const float* __restrict__ part, int nz, int M, int N,
+                                Epilogue ep) {
+  const size_t MN = (size_t)M * N;
+  for (size_t at = (size_t)blockIdx.x * blockDim.x + threadIdx.x; at < MN;
+       at += (size_t)gridDim.x * blockDim.x) {
+    float x = 0.f;
+    for (int z = 0; z < nz; z++) x += part[(size_t)z * MN + at];
+    const int j = (int)(at % N);
+    if (ep.bias) x += ep.bias[j];
+    if (ep.out_f32) ep.out_f32[at] = x;
+    if (ep.relu) x = x > 0.f ? x : 0.f;
+    if (ep.out_bf16) ep.out_bf16[at] = bf16_bits(x);
+    if (ep.accum_f32) ep.accum_f32[at] += x;
+  }
+}
+
+int gemm_splits(int M, int N, int K) {
+  // split K when the output has fewer tiles than compute units and K is long
+  const int tiles = (M / 64) * (N / 64);
+  int z = 1;
+  while (z < kMaxSplitK && tiles * z < 256 && K % (64 * z) == 0 && K / (2 * z) >= 256) z *= 2;
+  return z;
+}
+
 void launch_gemm(bool ta, bool tb, const unsigned short* a, int lda, const unsigned short* b,
-                 int ldb, int M, int N, int K, const Epilogue& ep, hipStream_t st) {
-  dim3 grid(N / 64, M / 64);
-  if (!ta && !tb) hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, a, lda, b, ldb, M, N, K, ep);
-  else if (ta && !tb) hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, a, lda, b, ldb, M, N, K, ep);
-  else if (!ta && tb) hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, a, lda, b, ldb, M, N, K, ep);
-  else hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, a, lda, b, ldb, M, N, K, ep);
+                 int ldb, int M, int N, int K, const Epilogue& ep, float* part, hipStream_t st) {
+  const int z = part ? gemm_splits(M, N, K) : 1;
+  dim3 grid(N / 64, M / 64, z);
+  if (!ta && !tb) hipLaunchKernelGGL((k_gemm<false, false>), grid, dim3(256), 0, st, a, lda, b, ldb, M, N, K, ep, part);
+  else if (ta && !tb) hipLaunchKernelGGL((k_gemm<true, false>), grid, dim3(256), 0, st, a, lda, b, ldb, M, N, K, ep, part);
+  else if (!ta && tb) hipLaunchKernelGGL((k_gemm<false, true>), grid, dim3(256), 0, st, a, lda, b, ldb, M, N, K, ep, part);
+  else hipLaunchKernelGGL((k_gemm<true, true>), grid, dim3(256), 0, st, a, lda, b, ldb, M, N, K, ep, part);
+  if (z > 1) hipLaunchKernelGGL(k_splitk_reduce, dim3(256), dim3(256), 0, st, part, z, M, N, ep);
 }
 
 // FP32 -> BF16 copy of an n_rows x n_cols matrix into a zero-padded
@@ -131,18 +171,27 @@ __global__ __launch_bounds__(256) void k_mse(const float* __restrict__ y, const 
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 // 1 / sum(mask) over the first n rows (one block, fixed order)
-__global__ __launch_bounds__(256) void k_mask_count(const float* __restrict__ mask, size_t ne,
-                                                    float* out) {
-  __shared__ float sh[256];
+// 1 / (number of masked entries); the mask holds 0/1, so the FP32 sum of
+// fewer than 2^24 of them is exact in any order
+__global__ __launch_bounds__(1024) void k_mask_count(const float* __restrict__ mask, size_t ne,
+                                                     float* out) {
+  __shared__ float sh[16];
   float acc = 0.f;
-  for (size_t e = threadIdx.x; e < ne; e += 256) acc += mask[e];
-  sh[threadIdx.x] = acc;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
-    __syncthreads();
+  const size_t n4 = ne / 4;
+  const float4* m4 = reinterpret_cast<const float4*>(mask);
+  for (size_t e = threadIdx.x; e < n4; e += 1024) {
+    const float4 v = m4[e];
+    acc += (v.x + v.y) + (v.z + v.w);
   }
-  if (threadIdx.x == 0) out[0] = sh[0] > 0.f ? 1.f / sh[0] : 0.f;
+  for (size_t e = 4 * n4 + threadIdx.x; e < ne; e += 1024) acc += mask[e];
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float s = 0.f;
+    for (int w = 0; w < 16; w++) s += sh[w];
+    out[0] = s > 0.f ? 1.f / s : 0.f;
+  }
 }
 __global__ void k_sum_parts(const float* part, int n, const float* inv_count, float* out) {
   if (threadIdx.x == 0) {
@@ -153,7 +202,7 @@ __global__ void k_sum_parts(const float* part, int n, const float* inv_count, fl
 }
 void launch_mse(const float* y, const float* t, const float* mask, int n, int rows, int d,
                 unsigned short* g, float* part, float* scal, hipStream_t st) {
-  hipLaunchKernelGGL(k_mask_count, dim3(1), dim3(256), 0, st, mask, (size_t)n * d, scal + 1);
+  hipLaunchKernelGGL(k_mask_count, dim3(1), dim3(1024), 0, st, mask, (size_t)n * d, scal + 1);
   hipLaunchKernelGGL(k_mse, dim3(kMseBlocks), dim3(256), 0, st, y, t, mask, n, rows, d, scal + 1,
                      g, part);
   hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, st, part, kMseBlocks, scal + 1, scal);
@@ -171,17 +220,27 @@ void launch_relu_back(const float* dh, const float* z, size_t n, unsigned short*
   hipLaunchKernelGGL(k_relu_back, dim3(512), dim3(256), 0, st, dh, z, n, dz);
 }
 
-// db[j] = sum_r g[r][j] (BF16 gradient rows), one thread per column, fixed order
-__global__ void k_bias_grad(const unsigned short* __restrict__ g, int rows, int d,
-                            float* __restrict__ db) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= d) return;
+// db[j] = sum_r g[r][j] (BF16 gradient rows): a block of 64 columns x 16
+// row lanes (coalesced 128-byte row segments), each lane summing every 16th
+// row, the 16 lane sums added in lane order
+__global__ __launch_bounds__(1024) void k_bias_grad(const unsigned short* __restrict__ g, int rows,
+                                                    int d, float* __restrict__ db) {
+  __shared__ float sh[16][64];
+  const int c = threadIdx.x & 63, rl = threadIdx.x >> 6;
+  const int j = blockIdx.x * 64 + c;
   float s = 0.f;
-  for (int r = 0; r < rows; r++) s += bf16_float(g[(size_t)r * d + j]);
-  db[j] = s;
+  if (j < d)
+    for (int r = rl; r < rows; r += 16) s += bf16_float(g[(size_t)r * d + j]);
+  sh[rl][c] = s;
+  __syncthreads();
+  if (rl == 0 && j < d) {
+    float t = 0.f;
+    for (int k = 0; k < 16; k++) t += sh[k][c];
+    db[j] = t;
+  }
 }
 void launch_bias_grad(const unsigned short* g, int rows, int d, float* db, hipStream_t st) {
-  hipLaunchKernelGGL(k_bias_grad, dim3((d + 255) / 256), dim3(256), 0, st, g, rows, d, db);
+  hipLaunchKernelGGL(k_bias_grad, dim3((d + 63) / 64), dim3(1024), 0, st, g, rows, d, db);
 }
 
 // Adam on the FP32 master weights, then their BF16 copy

@@ -2,6 +2,7 @@
 // masked-MSE gradients and Adam steps, all enqueued on the network's stream.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -28,6 +29,7 @@ struct dd_mlp {
   unsigned short *xb = nullptr, *hb[3] = {}, *gy = nullptr, *dz = nullptr;
   float *z[3] = {}, *y = nullptr, *dh = nullptr;
   float* part = nullptr;
+  float* ksplit = nullptr; // split-K partial tiles of the weight-gradient GEMMs
   float* scal = nullptr;   // [0] loss, [1] 1/count
   float* hscal = nullptr;  // pinned
   std::string err;
@@ -47,6 +49,13 @@ template <typename T>
 static hipError_t dm(T** p, size_t n) {
   *p = nullptr;
   return hipMalloc((void**)p, sizeof(T) * (n ? n : 1));
+}
+
+// split-K workspace: the largest weight matrix, kMaxSplitK times
+static size_t ksplit_floats(const int* d) {
+  size_t mx = 0;
+  for (int l = 0; l < 4; l++) mx = std::max(mx, (size_t)d[l] * d[l + 1]);
+  return mx * mlpk::kMaxSplitK;
 }
 
 static void free_act(dd_mlp* n) {
@@ -106,7 +115,7 @@ extern "C" dd_status dd_mlp_create(int n_in, int n_out, int width, unsigned long
   n->n_params = off;
   n->st = (hipStream_t)stream;
   if (dm(&n->w, off) || dm(&n->g, off) || dm(&n->m, off) || dm(&n->v, off) || dm(&n->wb, off) ||
-      dm(&n->part, mlpk::kMseBlocks) || dm(&n->scal, 4) ||
+      dm(&n->part, mlpk::kMseBlocks) || dm(&n->scal, 4) || dm(&n->ksplit, ksplit_floats(d)) ||
       hipHostMalloc((void**)&n->hscal, sizeof(float) * 4) != hipSuccess) {
     dd_mlp_free(n);
     return DD_ENOMEM;
@@ -139,6 +148,7 @@ extern "C" void dd_mlp_free(dd_mlp* n) {
   hipFree(n->v);
   hipFree(n->wb);
   hipFree(n->part);
+  hipFree(n->ksplit);
   hipFree(n->scal);
   if (n->hscal) hipHostFree(n->hscal);
   delete n;
@@ -192,7 +202,7 @@ static void forward_padded(dd_mlp* n, int R) {
       ep.out_f32 = n->y;
     }
     mlpk::launch_gemm(false, false, in, n->dims[l], n->wb + n->off_w[l], n->dims[l + 1], R,
-                      n->dims[l + 1], n->dims[l], ep, n->st);
+                      n->dims[l + 1], n->dims[l], ep, nullptr, n->st);
     if (l < 3) in = n->hb[l];
   }
 }
@@ -242,12 +252,13 @@ static dd_status loss_grad(dd_mlp* n, const float* x_dev, const float* t_dev,
     const int din = n->dims[l], dout = n->dims[l + 1];
     mlpk::Epilogue ew{};
     ew.out_f32 = n->g + n->off_w[l];  // dW = act^T gl  (din x dout)
-    mlpk::launch_gemm(true, false, act[l], din, gl, dout, din, dout, R, ew, n->st);
+    mlpk::launch_gemm(true, false, act[l], din, gl, dout, din, dout, R, ew, n->ksplit, n->st);
     mlpk::launch_bias_grad(gl, R, dout, n->g + n->off_b[l], n->st);
     if (l > 0) {
       mlpk::Epilogue eh{};
       eh.out_f32 = n->dh;  // dh = gl W^T  (R x din)
-      mlpk::launch_gemm(false, true, gl, dout, n->wb + n->off_w[l], dout, R, din, dout, eh, n->st);
+      mlpk::launch_gemm(false, true, gl, dout, n->wb + n->off_w[l], dout, R, din, dout, eh,
+                        nullptr, n->st);
       mlpk::launch_relu_back(n->dh, n->z[l - 1], (size_t)R * din, n->dz, n->st);
       gl = n->dz;
     }
