@@ -65,7 +65,8 @@ void* dd_mlp_get_stream(const dd_mlp* net);
  * Output (64): the
  * change of that centred potential which the solve makes, in the same units;
  * a zero output gives back the plain warm start.  Only cells whose Y-support
- * has at most 512 points are eligible; the others keep the plain start.
+ * has at most 8192 points (the register and streamed solvers' cells) are
+ * eligible; the others keep the plain start.
  *
  * dd_set_warm_start: attach a network (n_in 768, n_out 64) or detach it
  * (net NULL).  policy 1: predict the start of every eligible cell on the
@@ -92,7 +93,7 @@ dd_status dd_set_warm_start(dd_ctx* ctx, dd_mlp* net, int policy, float min_rms)
  * cell of that sweep's partition (cells numbered row-major), in the
  * network's output units (the change of the centred potential, units of
  * 16 h^2/eps); it is applied by the same kernel and eligibility rule as the
- * network's output (Y-support of at most 512 points, RMS of the change at
+ * network's output (Y-support of at most 8192 points, RMS of the change at
  * least min_rms), and replaces the network on that sweep.  The device buffer
  * stays the caller's and must live until that sweep has run. */
 dd_status dd_set_warm_prediction(dd_ctx* ctx, const float* y_dev, float min_rms);

@@ -15,7 +15,7 @@ constexpr int kStreamMaxU = kStreamSlabs * 1024;  // (processed in slabs of 512,
 constexpr size_t kStreamTileFloats = (size_t)kStreamMaxU * 64;  // tile buffer per workgroup
 constexpr int kNBins = kNRegBins + 2;          // + streamed solver + log-domain solver
 constexpr int kFeatIn = 768;                   // warm-start network input width
-constexpr int kWarmMaxU = 512;                 // cells with larger unions keep the plain start
+constexpr int kWarmMaxU = 8192;                // cells with larger unions keep the plain start
 constexpr double kWarmScale = 16.0;            // network output unit: 16 lam (h^2/eps)
 
 // Everything one sweep over one partition needs.  Device pointers.

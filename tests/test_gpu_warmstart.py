@@ -96,7 +96,7 @@ def test_collected_samples_match_cpu_recompute(torch):
         ids = torch.zeros(cap, dtype=torch.int32, device="cuda")
         n = g.collect_cells(X, T, M, ids)
         r = g.cell_results()
-        # every converged cell whose union has at most 512 points, once
+        # every converged cell whose union has at most 8192 points, once
         rp, col = prev["row_ptr"], prev["col"]
         cb = o.cells(part)
 
@@ -104,7 +104,7 @@ def test_collected_samples_match_cpu_recompute(torch):
             bs = [b for b in cb[k] if b >= 0]
             return len(set(np.concatenate([col[rp[b]:rp[b + 1]] for b in bs]).tolist()))
         exp_cells = {k for k in range(len(r["status"]))
-                     if r["status"][k] == 0 and union_size(k) <= 512}
+                     if r["status"][k] == 0 and union_size(k) <= 8192}
         idn = ids[:n].cpu().numpy()
         assert n > 0 and len(idn) == len(set(idn.tolist())) and set(idn.tolist()) == exp_cells
         Xc, Tc, Mc = _cpu_rows(prev, after, mu, N, N, 1.0 / N, eps, o.cells(part), part, idn)
@@ -157,7 +157,7 @@ def test_prediction_of_the_converged_change_restarts_at_the_solution(torch):
     from paper_2001_10986_amd import dd
     N = 64
     mu, nu = datagen.small_pair(N, 4, seed=29)
-    # two levels down to eps = 2 h^2 (most unions <= 512 points), then the
+    # two levels down to eps = 2 h^2 (unions <= 8192 points), then the
     # change to eps = h^2: the next sweep's cells are away from their solution
     sched = datagen.eps_schedule(N, 2)
     eps = sched[-1][1]
