@@ -702,6 +702,54 @@ DEVI void transpose_y(float* rd, int xg, int yg, const float v[8], float* top, f
   *bot = b;
 }
 
+template <int CTRL>
+DEVI float dpp_f(float v) {
+  return __builtin_bit_cast(float, dpp_mov0<CTRL>(__builtin_bit_cast(int, v)));
+}
+
+// Sum over the 8 lanes of an 8-lane group (lane bits 0-2 = block row xg) of
+// the per-lane partials v[t], t = 0..7: lane xg receives the total for t = xg.
+// Recursive halving in registers (no LDS): half-row mirror (partner 7 - xg),
+// quad mirror (partner with the other bit 1), quad swap (partner xg ^ 1);
+// each step keeps the half of the values that the lane's bit selects.
+DEVI float reduce8_t(const float v[8], int xg) {
+  const bool b2 = (xg & 4) != 0, b1 = (xg & 2) != 0, b0 = (xg & 1) != 0;
+  float a[4], b[2];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const float send = b2 ? v[k] : v[4 + k];
+    a[k] = (b2 ? v[4 + k] : v[k]) + dpp_f<0x141>(send);  // row_half_mirror
+  }
+#pragma unroll
+  for (int m = 0; m < 2; m++) {
+    const float send = b1 ? a[m] : a[2 + m];
+    b[m] = (b1 ? a[2 + m] : a[m]) + dpp_f<0x1b>(send);  // quad_perm [3,2,1,0]
+  }
+  const float send = b0 ? b[0] : b[1];
+  return (b0 ? b[1] : b[0]) + dpp_f<0xb1>(send);  // quad_perm [1,0,3,2]
+}
+
+// Sum over the 8 lanes that share a block row (lane bits 3-5 = yg) of the
+// per-lane partials v[j], j = 0..7 (block columns): lane yg receives the total
+// for j = yg.  Recursive halving: lane ^ 8 (row_ror:8 within a 16-lane row),
+// then lane ^ 16 and lane ^ 32 (cross-row permutes).
+DEVI float reduce8_j(const float v[8], int yg) {
+  const bool c0 = (yg & 1) != 0, c1 = (yg & 2) != 0, c2 = (yg & 4) != 0;
+  float a[4], b[2];
+#pragma unroll
+  for (int k = 0; k < 4; k++) {
+    const float send = c0 ? v[2 * k] : v[2 * k + 1];
+    a[k] = (c0 ? v[2 * k + 1] : v[2 * k]) + dpp_f<0x128>(send);  // row_ror:8
+  }
+#pragma unroll
+  for (int m = 0; m < 2; m++) {
+    const float send = c1 ? a[2 * m] : a[2 * m + 1];
+    b[m] = (c1 ? a[2 * m + 1] : a[2 * m]) + __shfl_xor(send, 16, 64);
+  }
+  const float send = c2 ? b[0] : b[1];
+  return (c2 ? b[1] : b[0]) + __shfl_xor(send, 32, 64);
+}
+
 DEVI double readlane0_d(double v) {
   const long long q = __builtin_bit_cast(long long, v);
   const int lo = __builtin_amdgcn_readlane((int)(q & 0xffffffffll), 0);
@@ -901,9 +949,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
             for (int j = 0; j < 8; j++) s = fmaf(P[j][t], uu[j], s);
             Sp[t] = s;
           }
-          float a, b;
-          transpose_y(rd, xg, yg, Sp, &a, &b);
-          const float s = a + b;
+          const float s = reduce8_t(Sp, xg);
           const int yi = ybase + xg;
           sh.w[yi] = s > 0.f ? sh.nuf[yi] * __builtin_amdgcn_rcpf(s) : 0.f;
         }
@@ -920,14 +966,7 @@ __global__ __launch_bounds__(NW * 64) void k_solve_reg(const HalfParams* __restr
             for (int t = 0; t < 8; t++) s = fmaf(P[j][t], wv[t], s);
             rx[j] = s;
           }
-          wave_sync();
-#pragma unroll
-          for (int j = 0; j < 8; j++) rd[tsw(xg, yg, j)] = rx[j];
-          wave_sync();
-          float s = 0.f;
-#pragma unroll
-          for (int k = 0; k < 8; k++) s += rd[tsw(xg, k, yg)];
-          wred[wave][xg * 8 + yg] = s;
+          wred[wave][xg * 8 + yg] = reduce8_j(rx, yg);
         }
         __syncthreads();
         // ---- X-update in every wave: plain u = mu/r, or the accelerated
@@ -1334,10 +1373,8 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
             for (int j = 0; j < 8; j++) s = fmaf(P[j][t], uu[j], s);
             Sp[t] = s;
           }
-          float a, b;
-          transpose_y(rd, xg, yg, Sp, &a, &b);
           const int yi = sl * kSlab + yoff + xg;
-          const float S = a + b;
+          const float S = reduce8_t(Sp, xg);
           const float w = (yi < U && S > 0.f) ? nug[yi] * __builtin_amdgcn_rcpf(S) : 0.f;
           Sg[yi] = S;
           sh.wl[wave][yg * 8 + xg] = w;
@@ -1351,15 +1388,7 @@ __global__ __launch_bounds__(kSlab) void k_solve_stream(const HalfParams* __rest
             for (int t = 0; t < 8; t++) rx[j] = fmaf(P[j][t], wv[t], rx[j]);
           wave_sync();
         }
-#pragma unroll
-        for (int j = 0; j < 8; j++) rd[tsw(xg, yg, j)] = rx[j];
-        wave_sync();
-        {
-          float s = 0.f;
-#pragma unroll
-          for (int k = 0; k < 8; k++) s += rd[tsw(xg, k, yg)];
-          sh.wred[wave][xg * 8 + yg] = s;
-        }
+        sh.wred[wave][xg * 8 + yg] = reduce8_j(rx, yg);
         __syncthreads();
         if (wave == 0) {
           float r = 0.f;
