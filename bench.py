@@ -36,13 +36,13 @@ NEWTON_KERNEL = 10
 # 2.0 and WRITE by 1.0, the factors a plain 256 MiB device copy gives); the
 # summary is kept under profiles/.  Valid only for the kernel source the
 # counters were taken on, identified by its hash.
-TRAFFIC_KERNEL_SHA256 = "701b96d3e3c083026edbcddc32cfd30c16fbc18d0e00a8027bd228c40f7f9c32"
+TRAFFIC_KERNEL_SHA256 = "0b4872afb89485030b495222b0e64e43e647c0f966640377016a2a8208fcf20b"
 TRAFFIC_BYTES_PER_LAUNCH = {
-    "solve_stream": (2.0 * 2320630 + 247923) * 1024,
-    "solve_reg_16w": (2.0 * 77392 + 237663) * 1024,
-    "solve_reg_8w": (2.0 * 7944 + 15297) * 1024,
-    "solve_reg_4w": (2.0 * 2921 + 5010) * 1024,
-    "solve_newton": (2.0 * 989 + 50619) * 1024,
+    "solve_stream": (2.0 * 2305326 + 247836) * 1024,
+    "solve_reg_16w": (2.0 * 52112 + 165241) * 1024,
+    "solve_reg_8w": (2.0 * 7955 + 15297) * 1024,
+    "solve_reg_4w": (2.0 * 2926 + 5011) * 1024,
+    "solve_newton": (2.0 * 983 + 50682) * 1024,
 }
 
 
