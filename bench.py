@@ -678,18 +678,15 @@ def main():
         devp = [(torch.from_numpy(m).cuda(), torch.from_numpy(v).cuda(), cf) for m, v, cf in pairs]
         torch.cuda.synchronize()
 
+        # default launch sizes: the ones tuned on the 1024x1024 finest sweep
+        # (one Newton workgroup per compute unit, 64 streamed workgroups) fit
+        # that sweep, not a batch whose late sweeps are Newton-bound
         def mk():
-            ps = [dd.Problem(m, v, cf["stages"], s=cf["s"], n_levels=cf["n_levels"])
-                  for m, v, cf in devp]
-            if launch is not None:
-                for q in ps:
-                    q.set_launch(**launch)
-            return ps
+            return [dd.Problem(m, v, cf["stages"], s=cf["s"], n_levels=cf["n_levels"])
+                    for m, v, cf in devp]
 
         ps = mk()
         bt = dd.Batch(ps, graph=True)
-        if launch is not None:
-            bt.set_launch(**launch)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         nsol = nfail = nnewt = step_no = 0
