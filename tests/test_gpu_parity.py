@@ -243,6 +243,34 @@ def test_iteration_cap_and_safeguard(dd, ddo):
     _valid_state(g)
 
 
+@pytest.mark.parametrize("N,trigger", [(32, 44), (64, 61)])
+def test_early_safeguard_matches_oracle(dd, ddo, N, trigger):
+    # safeguard_after = trigger: cells not converged after that many loops are
+    # re-solved at 2 eps from their stored potential, then at eps (Sec. 7.4
+    # safeguard).  One half-iteration from the product coupling on the
+    # register solvers (32x32) and the streamed solver (64x64, U = 4096),
+    # against the oracle with the same trigger.  The triggers sit in gaps of
+    # the oracle's per-cell loop counts without the early safeguard (32x32:
+    # none between 38 and 51; 64x64: none between 59 and 63), so both sides
+    # send the same cells through the safeguard.
+    mu, nu = datagen.small_pair(N, 3, seed=5)
+    eps = 4.0 / N ** 2
+    g = dd.Problem(mu, nu, [(0, eps, 1)], s=4, n_levels=1, safeguard_after=trigger)
+    o = ddo.Oracle(mu, nu, s=4, n_levels=1, eps=eps, safeguard_after=trigger)
+    sg = g.half_iterate(0)
+    so = o.half_iterate(0)
+    print(N, "safeguard", sg["n_safeguard"], so["n_safeguard"], "loops", sg["loops_total"],
+          so["loops_total"], flush=True)
+    assert sg["n_failed"] == 0 and so["n_failed"] == 0
+    assert sg["n_safeguard"] == so["n_safeguard"] > 0
+    assert abs(sg["cost"] - so["cost"]) <= 1e-7 * so["cost"]
+    assert abs(sg["loops_total"] - so["loops_total"]) <= 0.02 * so["loops_total"] + 2
+    bg, bo = g.basic_marginals(), o.basic_marginals()
+    assert np.abs(bg - bo).max() < 1e-6 * bg.sum(axis=1).max()
+    rg, ro = g.cell_results(), o.cell_results(0)
+    assert np.array_equal((rg["status"] & 4) != 0, (ro["status"] & 4) != 0)
+
+
 def test_invalid_inputs_rejected(dd):
     mu, nu = datagen.small_pair(32, 3, seed=5)
     with pytest.raises(dd.DDError):
