@@ -206,6 +206,88 @@ __global__ __launch_bounds__(kCgThreads) void k_cert_cg(
   }
 }
 
+// The same iteration for na <= ROWS * kCgThreads with the search direction p
+// in LDS (read by every thread in the Laplacian product) and x, r, Ap in
+// registers: the same operations in the same order as k_cert_cg, so the same
+// result, without the global-memory round trips of p on every step.
+template <int ROWS>
+__global__ __launch_bounds__(kCgThreads) void k_cert_cg_lds(
+    const int* adj_ptr, const int* adj_idx, const double* adj_w, const double* deg,
+    const double* b, int na, int max_it, double tol2, double* x_out, double* info) {
+  __shared__ double red[kCgThreads / 64];
+  __shared__ double ps[ROWS * kCgThreads];
+  const int tid = threadIdx.x;
+  double x[ROWS], r[ROWS], ap[ROWS];
+  double loc = 0;
+#pragma unroll
+  for (int q = 0; q < ROWS; q++) {
+    const int J = tid + q * kCgThreads;
+    const double bj = J < na ? b[J] : 0.0;
+    x[q] = 0;
+    r[q] = bj;
+    ap[q] = 0;
+    ps[J] = bj;
+    if (J < na) loc += bj * bj;
+  }
+  double rr = cg_reduce(loc, red);
+  const double bb = rr;
+  __syncthreads();
+  int it = 0;
+  while (it < max_it && rr > tol2 * bb && rr > 0) {
+    loc = 0;
+#pragma unroll
+    for (int q = 0; q < ROWS; q++) {
+      const int J = tid + q * kCgThreads;
+      if (J < na) {
+        double v = deg[J] * ps[J];
+        for (int k = adj_ptr[J]; k < adj_ptr[J + 1]; k++) v -= adj_w[k] * ps[adj_idx[k]];
+        ap[q] = v;
+        loc += ps[J] * v;
+      }
+    }
+    const double pAp = cg_reduce(loc, red);
+    if (!(pAp > 0)) break;
+    const double a = rr / pAp;
+    loc = 0;
+#pragma unroll
+    for (int q = 0; q < ROWS; q++) {
+      const int J = tid + q * kCgThreads;
+      if (J < na) {
+        x[q] += a * ps[J];
+        r[q] -= a * ap[q];
+        loc += r[q] * r[q];
+      }
+    }
+    const double rr2 = cg_reduce(loc, red);
+    const double beta = rr2 / rr;
+    rr = rr2;
+#pragma unroll
+    for (int q = 0; q < ROWS; q++) {
+      const int J = tid + q * kCgThreads;
+      if (J < na) ps[J] = r[q] + beta * ps[J];
+    }
+    __syncthreads();
+    it++;
+  }
+  loc = 0;
+#pragma unroll
+  for (int q = 0; q < ROWS; q++)
+    if (tid + q * kCgThreads < na) loc += x[q];
+  const double mean = cg_reduce(loc, red) / (na > 0 ? na : 1);
+#pragma unroll
+  for (int q = 0; q < ROWS; q++) {
+    const int J = tid + q * kCgThreads;
+    if (J < na) x_out[J] = x[q] - mean;
+  }
+  if (tid == 0) {
+    info[0] = it;
+    info[1] = rr;
+    info[2] = bb;
+  }
+}
+
+constexpr int kCgLdsRows = 4;  // p in LDS up to 4096 unknowns (32 KiB)
+
 }  // namespace
 
 void launch_cert_glue(const int* inc_ptr, const int* inc_e, const int* e_ia, const int* e_ib,
@@ -218,8 +300,12 @@ void launch_cert_glue(const int* inc_ptr, const int* inc_e, const int* e_ia, con
   double* Ap = work + 3 * (size_t)na;
   hipLaunchKernelGGL(k_cert_rhs, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, st, inc_ptr,
                      inc_e, e_ia, e_ib, q, na, rhs);
-  hipLaunchKernelGGL(k_cert_cg, dim3(1), dim3(kCgThreads), 0, st, adj_ptr, adj_idx, adj_w, deg,
-                     rhs, na, max_it, tol2, V, r, p, Ap, info);
+  if (na <= kCgLdsRows * kCgThreads)
+    hipLaunchKernelGGL((k_cert_cg_lds<kCgLdsRows>), dim3(1), dim3(kCgThreads), 0, st, adj_ptr,
+                       adj_idx, adj_w, deg, rhs, na, max_it, tol2, V, info);
+  else
+    hipLaunchKernelGGL(k_cert_cg, dim3(1), dim3(kCgThreads), 0, st, adj_ptr, adj_idx, adj_w, deg,
+                       rhs, na, max_it, tol2, V, r, p, Ap, info);
 }
 
 void launch_cert_y(const int64_t* row_off, const int* row_len, const int* col,
