@@ -48,6 +48,31 @@ def test_matches_dense_entropic_optimum(cost_p):
     assert abs(r["dual"] - opt_score) <= 1e-6 * abs(opt_score)
 
 
+def test_rectangular_grid_matches_dense_entropic_optimum():
+    # a 16x32 pair (h = 1/32, two levels): the same checks as above on a
+    # grid whose rows and columns differ
+    from oracle import dense
+    from paper_2001_10986_amd import dd
+    H, W = 16, 32
+    mu = datagen.blob_image(H, W, 4, 41)
+    nu = datagen.blob_image(H, W, 4, 42)
+    h = 1.0 / W
+    stages = [(0, 8 * h * h, 1), (1, 4 * h * h, 1), (1, 2 * h * h, 1)]
+    eps = stages[-1][1]
+    r = dd.single_solve(mu, nu, stages, n_levels=2, err_tol=1e-13, potentials=True)
+    C = dense.grid_cost(H, W, h)
+    P = dense.entropic_ot(C, mu.ravel(), nu.ravel(), eps)
+    a, b = r["alpha"].ravel(), r["beta"].ravel()
+    Q = np.exp((a[:, None] + b[None, :] - C) / eps) * np.outer(mu.ravel(), nu.ravel())
+    opt_cost = float((C * P).sum())
+    print(f"16x32: loops {r['loops_total']}, cost {r['cost']:.12g} vs {opt_cost:.12g}, "
+          f"plan diff {np.abs(Q - P).max():.3e}", flush=True)
+    assert r["status"] == 0 and r["failed"] == 0 and r["level"] == 1
+    assert r["alpha"].shape == (H, W)
+    assert abs(r["cost"] - opt_cost) <= 1e-6 * opt_cost
+    assert np.abs(Q - P).max() <= 1e-6 * P.max()
+
+
 def test_larger_instance_against_the_decomposition():
     # 128x128 on the paper's protocol; the single Sinkhorn stops on the
     # L-infinity X-marginal error 1e-7 of Sec. 7.4, the decomposition on its
