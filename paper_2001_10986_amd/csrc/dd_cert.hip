@@ -142,14 +142,15 @@ __device__ double cg_reduce(double v, double* red) {
 }
 
 // Conjugate gradients for L V = rhs in one workgroup, L the graph Laplacian
-// of the A-cell graph (deg on the diagonal, -w for each neighbour); L is
+// of the A-cell graph (deg on the diagonal, -w for each neighbour, the
+// neighbour lists in ELL form with zero-weight padding); L is
 // singular on constants and rhs sums to zero, so the iterates stay in the
 // complement; V is shifted to mean zero at the end.  Each thread owns the
 // rows J = tid + k*1024 of x, r and Ap; p is read across threads, through
 // agent-scope loads after a release fence and the barrier.  The loop ends
 // for all waves at the same step (every test reads workgroup-reduced values).
 __global__ __launch_bounds__(kCgThreads) void k_cert_cg(
-    const int* adj_ptr, const int* adj_idx, const double* adj_w, const double* deg,
+    const int* ell_idx, const double* ell_w, int ell_k, const double* deg,
     const double* b, int na, int max_it, double tol2, double* x, double* r, double* p,
     double* Ap, double* info) {
   __shared__ double red[kCgThreads / 64];
@@ -171,9 +172,18 @@ __global__ __launch_bounds__(kCgThreads) void k_cert_cg(
     loc = 0;
     for (int J = tid; J < na; J += kCgThreads) {
       double v = deg[J] * p[J];
-      for (int k = adj_ptr[J]; k < adj_ptr[J + 1]; k++)
-        v -= adj_w[k] * __hip_atomic_load(&p[adj_idx[k]], __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
+      for (int k0 = 0; k0 < ell_k; k0 += 8) {
+        int idx[8];
+        double w[8];
+#pragma unroll
+        for (int k = 0; k < 8; k++) {
+          idx[k] = ell_idx[(size_t)(k0 + k) * na + J];
+          w[k] = ell_w[(size_t)(k0 + k) * na + J];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; k++)
+          v -= w[k] * __hip_atomic_load(&p[idx[k]], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
       Ap[J] = v;
       loc += p[J] * v;
     }
@@ -212,7 +222,7 @@ __global__ __launch_bounds__(kCgThreads) void k_cert_cg(
 // result, without the global-memory round trips of p on every step.
 template <int ROWS>
 __global__ __launch_bounds__(kCgThreads) void k_cert_cg_lds(
-    const int* adj_ptr, const int* adj_idx, const double* adj_w, const double* deg,
+    const int* ell_idx, const double* ell_w, int ell_k, const double* deg,
     const double* b, int na, int max_it, double tol2, double* x_out, double* info) {
   __shared__ double red[kCgThreads / 64];
   __shared__ double ps[ROWS * kCgThreads];
@@ -240,7 +250,17 @@ __global__ __launch_bounds__(kCgThreads) void k_cert_cg_lds(
       const int J = tid + q * kCgThreads;
       if (J < na) {
         double v = deg[J] * ps[J];
-        for (int k = adj_ptr[J]; k < adj_ptr[J + 1]; k++) v -= adj_w[k] * ps[adj_idx[k]];
+        for (int k0 = 0; k0 < ell_k; k0 += 8) {
+          int idx[8];
+          double w[8];
+#pragma unroll
+          for (int k = 0; k < 8; k++) {
+            idx[k] = ell_idx[(size_t)(k0 + k) * na + J];
+            w[k] = ell_w[(size_t)(k0 + k) * na + J];
+          }
+#pragma unroll
+          for (int k = 0; k < 8; k++) v -= w[k] * ps[idx[k]];
+        }
         ap[q] = v;
         loc += ps[J] * v;
       }
@@ -291,9 +311,9 @@ constexpr int kCgLdsRows = 4;  // p in LDS up to 4096 unknowns (32 KiB)
 }  // namespace
 
 void launch_cert_glue(const int* inc_ptr, const int* inc_e, const int* e_ia, const int* e_ib,
-                      const double* q, const int* adj_ptr, const int* adj_idx,
-                      const double* adj_w, const double* deg, int na, int max_it, double tol2,
-                      double* work, double* V, double* info, hipStream_t st) {
+                      const double* q, const int* ell_idx, const double* ell_w, int ell_k,
+                      const double* deg, int na, int max_it, double tol2, double* work,
+                      double* V, double* info, hipStream_t st) {
   double* rhs = work;
   double* r = work + na;
   double* p = work + 2 * (size_t)na;
@@ -301,10 +321,10 @@ void launch_cert_glue(const int* inc_ptr, const int* inc_e, const int* e_ia, con
   hipLaunchKernelGGL(k_cert_rhs, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, st, inc_ptr,
                      inc_e, e_ia, e_ib, q, na, rhs);
   if (na <= kCgLdsRows * kCgThreads)
-    hipLaunchKernelGGL((k_cert_cg_lds<kCgLdsRows>), dim3(1), dim3(kCgThreads), 0, st, adj_ptr,
-                       adj_idx, adj_w, deg, rhs, na, max_it, tol2, V, info);
+    hipLaunchKernelGGL((k_cert_cg_lds<kCgLdsRows>), dim3(1), dim3(kCgThreads), 0, st, ell_idx,
+                       ell_w, ell_k, deg, rhs, na, max_it, tol2, V, info);
   else
-    hipLaunchKernelGGL(k_cert_cg, dim3(1), dim3(kCgThreads), 0, st, adj_ptr, adj_idx, adj_w, deg,
+    hipLaunchKernelGGL(k_cert_cg, dim3(1), dim3(kCgThreads), 0, st, ell_idx, ell_w, ell_k, deg,
                        rhs, na, max_it, tol2, V, r, p, Ap, info);
 }
 

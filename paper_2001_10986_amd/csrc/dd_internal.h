@@ -215,10 +215,12 @@ void launch_interp(const double* fglued_c, int Hc, int Wc, double* fa, double* f
 // conjugate gradients on the A-cell Laplacian (adj_* neighbours with edge
 // counts, deg the diagonal) in one workgroup, mean zero.  work holds 4*na
 // doubles; info[0..2] = (iterations, final r.r, initial r.r).
+// ell_idx / ell_w: the neighbours of A-cell J and the edge counts at k*na + J,
+// k < ell_k (a multiple of 8; padding: J itself with weight 0)
 void launch_cert_glue(const int* inc_ptr, const int* inc_e, const int* e_ia, const int* e_ib,
-                      const double* q, const int* adj_ptr, const int* adj_idx,
-                      const double* adj_w, const double* deg, int na, int max_it, double tol2,
-                      double* work, double* V, double* info, hipStream_t st);
+                      const double* q, const int* ell_idx, const double* ell_w, int ell_k,
+                      const double* deg, int na, int max_it, double tol2, double* work,
+                      double* V, double* info, hipStream_t st);
 void launch_cert_y(const int64_t* row_off, const int* row_len, const int* col,
                    const double* alpha_hat, const double* mu, const double* nu, int H, int W,
                    int bs, int bw, int n_basic, double eps, double h, double half_p,

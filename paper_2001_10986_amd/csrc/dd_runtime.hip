@@ -1026,21 +1026,19 @@ extern "C" dd_status dd_half_iterate(dd_ctx* c, int part, dd_iter_stats* out) {
 // the geometry of the graph.
 namespace {
 struct GlueScratch {
-  double *dq = nullptr, *work = nullptr, *adjw = nullptr, *deg = nullptr;
-  int *ia = nullptr, *ib = nullptr, *incp = nullptr, *ince = nullptr, *adjp = nullptr,
-      *adji = nullptr;
-  int na = 0, ne = 0, max_it = 0;
+  double *dq = nullptr, *work = nullptr, *ellw = nullptr, *deg = nullptr;
+  int *ia = nullptr, *ib = nullptr, *incp = nullptr, *ince = nullptr, *elli = nullptr;
+  int na = 0, ne = 0, max_it = 0, ellk = 0;
   ~GlueScratch() {
     hipFree(dq);
     hipFree(work);
-    hipFree(adjw);
+    hipFree(ellw);
     hipFree(deg);
     hipFree(ia);
     hipFree(ib);
     hipFree(incp);
     hipFree(ince);
-    hipFree(adjp);
-    hipFree(adji);
+    hipFree(elli);
   }
 };
 }  // namespace
@@ -1105,15 +1103,30 @@ static dd_status enqueue_glue(dd_ctx* c, GlueScratch& g, double* dV, double* inf
     }
     adj_ptr[J + 1] = (int)adj_idx.size();
   }
-  const size_t nadj = adj_idx.size();
+  // the neighbour lists in ELL form (entry k of row J at k*na + J, the CSR
+  // order kept, rows padded to a multiple of 8 with weight 0 on the row itself)
+  // so that the Laplacian product issues every load of a row at once
+  int kmax = 0;
+  for (int J = 0; J < na; J++) kmax = std::max(kmax, adj_ptr[J + 1] - adj_ptr[J]);
+  const int ellk = std::max(8, (kmax + 7) / 8 * 8);
+  std::vector<int> ell_idx((size_t)ellk * na);
+  std::vector<double> ell_w((size_t)ellk * na, 0.0);
+  for (int J = 0; J < na; J++)
+    for (int k = 0; k < ellk; k++) {
+      const int q = adj_ptr[J] + k;
+      const bool in = q < adj_ptr[J + 1];
+      ell_idx[(size_t)k * na + J] = in ? adj_idx[q] : J;
+      ell_w[(size_t)k * na + J] = in ? adj_w[q] : 0.0;
+    }
   g.na = na;
   g.ne = ne;
+  g.ellk = ellk;
   g.max_it = std::min(20 * na + 100, kGlueMaxIt);
   if (dmalloc(&g.dq, 2 * (size_t)nb) || dmalloc(&g.work, 4 * (size_t)na + 4) ||
-      dmalloc(&g.adjw, nadj + 1) || dmalloc(&g.deg, (size_t)na) || dmalloc(&g.ia, (size_t)ne + 1) ||
-      dmalloc(&g.ib, (size_t)ne + 1) || dmalloc(&g.incp, (size_t)na + 1) ||
-      dmalloc(&g.ince, 2 * (size_t)ne + 1) || dmalloc(&g.adjp, (size_t)na + 1) ||
-      dmalloc(&g.adji, nadj + 1))
+      dmalloc(&g.ellw, (size_t)ellk * na + 1) || dmalloc(&g.deg, (size_t)na) ||
+      dmalloc(&g.ia, (size_t)ne + 1) || dmalloc(&g.ib, (size_t)ne + 1) ||
+      dmalloc(&g.incp, (size_t)na + 1) || dmalloc(&g.ince, 2 * (size_t)ne + 1) ||
+      dmalloc(&g.elli, (size_t)ellk * na + 1))
     return fail(c, DD_ENOMEM, "gluing scratch");
   hipError_t e = hipSuccess;
   auto up = [&](void* dst, const void* src, size_t bytes) {
@@ -1124,9 +1137,8 @@ static dd_status enqueue_glue(dd_ctx* c, GlueScratch& g, double* dV, double* inf
   up(g.ib, e_ib.data(), sizeof(int) * ne);
   up(g.incp, inc_ptr.data(), sizeof(int) * (na + 1));
   up(g.ince, inc_e.data(), sizeof(int) * 2 * (size_t)ne);
-  up(g.adjp, adj_ptr.data(), sizeof(int) * (na + 1));
-  up(g.adji, adj_idx.data(), sizeof(int) * nadj);
-  up(g.adjw, adj_w.data(), sizeof(double) * nadj);
+  up(g.elli, ell_idx.data(), sizeof(int) * ell_idx.size());
+  up(g.ellw, ell_w.data(), sizeof(double) * ell_w.size());
   up(g.deg, deg.data(), sizeof(double) * na);
   if (e != hipSuccess) return fail(c, DD_EHIP, "gluing upload: %s", hipGetErrorString(e));
   ddk::RefineParams R{};
@@ -1139,7 +1151,7 @@ static dd_status enqueue_glue(dd_ctx* c, GlueScratch& g, double* dV, double* inf
   R.alpha_a_c = c->alpha[0];
   R.alpha_b_c = c->alpha[1];
   ddk::launch_glue_ratios(R, g.dq, c->st);
-  ddk::launch_cert_glue(g.incp, g.ince, g.ia, g.ib, g.dq, g.adjp, g.adji, g.adjw, g.deg, na,
+  ddk::launch_cert_glue(g.incp, g.ince, g.ia, g.ib, g.dq, g.elli, g.ellw, g.ellk, g.deg, na,
                         g.max_it, kGlueTol2, g.work, dV, info, c->st);
   e = hipGetLastError();
   if (e != hipSuccess) return fail(c, DD_EHIP, "gluing launch: %s", hipGetErrorString(e));
