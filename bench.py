@@ -119,6 +119,8 @@ def main():
                          "schedules in lockstep through one batch (0 skips it)")
     ap.add_argument("--batch-seq", action="store_true",
                     help="with --batch-pairs, also time the same pairs one after another")
+    ap.add_argument("--peak-probe", type=int, default=1,
+                    help="measure the FP32/FP64 FMA and FP32 exp rates on the device (0: skip)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (calibrates the HBM "
                          "byte counters of a profiler) and exit")
@@ -240,6 +242,24 @@ def main():
         if mfma > 0:
             ent["mfma_flops_per_launch"] = mfma / max(launches, 1)
         per_kernel[dd.KERNEL_NAMES[k]] = ent
+    # measured issue rates of the same arithmetic on this device (context
+    # beside the published peaks, which stay the roofline's denominator)
+    peaks = None
+    if args.peak_probe:
+        pk = dd.probe_peaks()
+        peaks = {"fp32_fma_tflops": pk["fp32_fma_tflops"], "fp64_fma_tflops": pk["fp64_fma_tflops"],
+                 "exp_f32_per_s": pk["exp_f32_per_s"], "compute_units": pk["compute_units"],
+                 "clock_mhz": pk["clock_mhz"],
+                 "published": {"fp32_tflops": PEAK_FP32_TFLOPS,
+                               "fp32_nonpacked_tflops": PEAK_FP32_NONPACKED_TFLOPS,
+                               "fp64_tflops": PEAK_FP64_TFLOPS},
+                 "note": "dd_probe_peaks: eight independent FMA (not packed) or v_exp_f32 "
+                         "chains per thread, 8 workgroups of 256 per compute unit, best of 3"}
+        for ent in per_kernel.values():
+            m = pk["fp32_fma_tflops"] if ent["precision"] == "fp32" else pk["fp64_fma_tflops"]
+            ent["frac_measured_peak"] = ent["achieved_tflops"] / m if m > 0 else None
+        progress(f"measured peaks: FP32 FMA {pk['fp32_fma_tflops']:.1f}, FP64 FMA "
+                 f"{pk['fp64_fma_tflops']:.1f} TFLOP/s, exp {pk['exp_f32_per_s']:.3g}/s")
     dom = max(SOLVER_KERNELS, key=lambda k: tot_ms[k])
     dname = dd.KERNEL_NAMES[dom]
     d = per_kernel[dname]
@@ -250,6 +270,8 @@ def main():
             "avg_launch_ms": d["avg_launch_ms"], "flops_per_launch": d["flops_per_launch"],
             "precision": d["precision"],
             "selection": "solver kernel with the most device time per step"}
+    if peaks:
+        roof["frac_measured_peak"] = d.get("frac_measured_peak")
     # the streamed solver keeps its cell's kernel tile (FP32) in memory and
     # reads it once per loop, each entry serving both half-steps from
     # registers: as a memory-bound kernel its algorithmic traffic is 4 B per
@@ -772,6 +794,7 @@ def main():
         "roofline_kernels": per_kernel,
         "roofline_mlp": mlp_roof,
         "roofline_memory_view": roof_mem,
+        "measured_peaks": peaks,
         "cpu_baseline": cpu,
         "parity_sample": parity,
     }

@@ -400,6 +400,29 @@ dd_status dd_autotune(dd_ctx* ctx, int partition, int reps, dd_tune_point* best,
 dd_status dd_batch_autotune(dd_batch* batch, int partition, int reps, dd_tune_point* best,
                             dd_tune_point* tried, int max_tried, int* n_tried);
 
+/* Measured arithmetic peaks of the current device: the issue rates of the
+ * operations the cell solvers are built from (the Sinkhorn loops are FP32
+ * multiply-adds on a stored kernel tile, the tile and the Newton steps take
+ * FP32 and FP64 exponentials; the roofline of the per-cell loop is the
+ * vector ALU, not HBM).  Each rate is the best of three launches of a kernel
+ * that runs eight independent dependency chains per thread, eight
+ * 256-thread workgroups per compute unit: FP32 fused multiply-adds (not
+ * packed; 2 flops each), FP64 fused multiply-adds and FP32 exponentials
+ * (v_exp_f32, results per second).  Runs on its own stream of the current
+ * device and allocates a small device buffer; returns DD_EINVAL for a null
+ * output, DD_EHIP on a HIP error (message: dd_probe_last_error). */
+typedef struct {
+  double fp32_fma_tflops;  /* FP32 FMA, TFLOP/s */
+  double fp64_fma_tflops;  /* FP64 FMA, TFLOP/s */
+  double exp_f32_per_s;    /* FP32 exponentials per second */
+  int compute_units;       /* of the device */
+  double clock_mhz;        /* peak engine clock the runtime reports */
+  double ms_fp32, ms_fp64, ms_exp; /* best launch times */
+} dd_peaks;
+
+dd_status dd_probe_peaks(dd_peaks* out);
+const char* dd_probe_last_error(void);
+
 /* Release the batch (not its contexts, which return to their own sweeps). */
 void dd_batch_free(dd_batch* batch);
 

@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 PKG = os.path.dirname(HERE)
 LIB = os.path.join(PKG, "libdd.so")
 SOURCES = ["dd_kernels.hip", "dd_runtime.hip", "dd_cert.hip", "dd_single.hip", "mlp_kernels.hip",
-           "mlp_runtime.hip"]
+           "mlp_runtime.hip", "dd_probe.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -128,6 +128,16 @@ class SingleReport(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class Peaks(C.Structure):
+    _fields_ = [("fp32_fma_tflops", C.c_double), ("fp64_fma_tflops", C.c_double),
+                ("exp_f32_per_s", C.c_double), ("compute_units", C.c_int),
+                ("clock_mhz", C.c_double), ("ms_fp32", C.c_double), ("ms_fp64", C.c_double),
+                ("ms_exp", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class PlanView(C.Structure):
     _fields_ = [("level", C.c_int), ("H", C.c_int), ("W", C.c_int), ("eps", C.c_double),
                 ("n_basic", C.c_int64), ("nnz", C.c_int64), ("row_ptr", C.c_void_p),
@@ -200,6 +210,10 @@ def _load():
     lib.dd_batch_free.restype = None
     lib.dd_batch_last_error.argtypes = [C.c_void_p]
     lib.dd_batch_last_error.restype = C.c_char_p
+    lib.dd_probe_peaks.argtypes = [P(Peaks)]
+    lib.dd_probe_peaks.restype = C.c_int
+    lib.dd_probe_last_error.argtypes = []
+    lib.dd_probe_last_error.restype = C.c_char_p
     for name in ("dd_set_warm_start", "dd_collect_cells", "dd_batch_create",
                  "dd_batch_half_iterate", "dd_batch_run_schedule", "dd_batch_schedule_step",
                  "dd_batch_info", "dd_set_launch", "dd_batch_set_launch", "dd_autotune",
@@ -229,6 +243,16 @@ def _autotune(fn, h, partition, reps, chk):
     n = C.c_int()
     chk(fn(h, partition, reps, C.byref(best), tried, 32, C.byref(n)), fn.__name__)
     return best.as_dict(), [tried[i].as_dict() for i in range(min(n.value, 32))]
+
+
+def probe_peaks():
+    """Measured FP32/FP64 multiply-add and FP32 exponential rates of the
+    current device (dd_probe_peaks)."""
+    out = Peaks()
+    st = lib.dd_probe_peaks(C.byref(out))
+    if st != 0:
+        raise DDError(f"dd_probe_peaks: status {st}: {lib.dd_probe_last_error().decode()}")
+    return out.as_dict()
 
 
 class Problem:
