@@ -126,7 +126,8 @@ def y_iteration(alpha, C, mu, eps, chunk=2048, support=None):
     """beta(y) = -eps log sum_x exp((alpha(x) - c(x,y))/eps) mu(x) (step 4);
     with a boolean support matrix the sum runs over its True entries only
     (the stored support of a truncated plan)."""
-    lmu = np.log(mu)
+    with np.errstate(divide="ignore"):  # log 0 = -inf: pixels without mass drop out
+        lmu = np.log(mu)
     out = np.empty(C.shape[1])
     for j0 in range(0, C.shape[1], chunk):
         t = (alpha[:, None] - C[:, j0:j0 + chunk]) / eps + lmu[:, None]
