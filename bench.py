@@ -241,6 +241,14 @@ def main():
             ent["frac_nonpacked_fp32"] = ach / PEAK_FP32_NONPACKED_TFLOPS
         if mfma > 0:
             ent["mfma_flops_per_launch"] = mfma / max(launches, 1)
+        if k == NEWTON_KERNEL:
+            # one slow cell per compute unit: a launch with n cells can
+            # occupy at most n of the device's compute units
+            cells = sum(r["n_newton"] for r, _ in runs) / max(launches, 1)
+            n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+            ent["cells_per_launch"] = cells
+            ent["frac_of_occupiable_cus"] = (ach / (peak * min(cells, n_cu) / n_cu)
+                                             if cells > 0 else None)
         per_kernel[dd.KERNEL_NAMES[k]] = ent
     # measured issue rates of the same arithmetic on this device (context
     # beside the published peaks, which stay the roofline's denominator)
@@ -272,6 +280,9 @@ def main():
             "selection": "solver kernel with the most device time per step"}
     if peaks:
         roof["frac_measured_peak"] = d.get("frac_measured_peak")
+    if "cells_per_launch" in d:
+        roof["cells_per_launch"] = d["cells_per_launch"]
+        roof["frac_of_occupiable_cus"] = d["frac_of_occupiable_cus"]
     # the streamed solver keeps its cell's kernel tile (FP32) in memory and
     # reads it once per loop, each entry serving both half-steps from
     # registers: as a memory-bound kernel its algorithmic traffic is 4 B per

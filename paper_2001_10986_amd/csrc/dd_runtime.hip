@@ -167,11 +167,24 @@ static hipError_t runner_reserve(Runner& r, int n_prob, int items) {
 // Tile buffers of the streamed solver: one per workgroup (2 MiB each).  The
 // workgroups loop over the bin's queue, so fewer of them than cells is still
 // correct; size for the bin's cells in the previous sweep plus a margin (64
-// before any sweep), at most two per compute unit.
-static int stream_limit(const Runner& r) { return r.stream_max > 0 ? r.stream_max : 2 * r.n_cu; }
+// before any sweep), at most two per compute unit.  The tuned cap keeps a
+// large bin's tiles from competing for the caches; a bin that held at most
+// kStreamOwnWg cells in the previous sweep (the coarse levels, where the
+// partitions alternate between, e.g., 64 and 81 such cells) gets up to
+// kStreamOwnWg workgroups, one per cell, instead of a second round.
+constexpr int kStreamOwnWg = 128;
+
+static bool stream_small(const Runner& r) {
+  return r.stream_prev >= 0 && r.stream_prev <= kStreamOwnWg;
+}
+
+static int stream_limit(const Runner& r) {
+  const int tuned = r.stream_max > 0 ? r.stream_max : 2 * r.n_cu;
+  return stream_small(r) ? std::max(tuned, kStreamOwnWg) : tuned;
+}
 
 static hipError_t runner_stream(Runner& r, int n_cells) {
-  const int prev = r.stream_prev >= 0 ? r.stream_prev + 16 : 64;
+  const int prev = stream_small(r) ? kStreamOwnWg : r.stream_prev >= 0 ? r.stream_prev + 16 : 64;
   const int want = std::min(std::min(n_cells, stream_limit(r)), prev);
   if (want <= r.stream_wgs) return hipSuccess;
   hipFree(r.stream_tile);
