@@ -28,7 +28,7 @@ EXPORTED = ["dd_options_default", "dd_init", "dd_half_iterate", "dd_set_eps", "d
             "dd_autotune", "dd_batch_autotune", "dd_get_launch",
             "dd_batch_last_error", "dd_certificate", "dd_cost_noalloc",
             "dd_set_warm_prediction", "dd_single_options_default", "dd_single_solve",
-            "dd_single_last_error"]
+            "dd_single_last_error", "dd_probe_peaks", "dd_probe_last_error"]
 
 DD_BATCH_GRAPH = 1
 DD_PREC_SPLIT, DD_PREC_FP64 = 0, 1

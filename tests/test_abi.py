@@ -50,6 +50,13 @@ def test_options_default_without_gpu():
     assert o.precision == dd.DD_PREC_SPLIT and o.cost_p == 2.0 and o.safeguard_after == 1024
 
 
+def test_probe_peaks_rejects_null_without_gpu():
+    # the argument check comes before any device call
+    from paper_2001_10986_amd import dd
+    assert dd.lib.dd_probe_peaks(None) == -1  # DD_EINVAL
+    assert dd.lib.dd_probe_last_error() == b"null output"
+
+
 def test_schedule_recipe():
     from paper_2001_10986_amd import datagen
     st = datagen.eps_schedule(256, 3)
