@@ -400,7 +400,9 @@ dd_status dd_autotune(dd_ctx* ctx, int partition, int reps, dd_tune_point* best,
 dd_status dd_batch_autotune(dd_batch* batch, int partition, int reps, dd_tune_point* best,
                             dd_tune_point* tried, int max_tried, int* n_tried);
 
-/* Measured arithmetic peaks of the current device: the issue rates of the
+/* Measured arithmetic peaks of the current device, the denominators of the
+ * roofline of the cell solves (the Sinkhorn iteration of the sub-problems,
+ * Remark "Sinkhorn algorithm" and Sec. 6.2): the issue rates of the
  * operations the cell solvers are built from (the Sinkhorn loops are FP32
  * multiply-adds on a stored kernel tile, the tile and the Newton steps take
  * FP32 and FP64 exponentials; the roofline of the per-cell loop is the
