@@ -76,7 +76,8 @@ def graph_edges(alpha_a, alpha_b, mu, eps, basic, cells_a, cells_b):
         parts = {J: np.concatenate(p) for J, p in pix_by_a.items()}
         lmean_ab, lmean_ba = {}, {}
         for J, xs in parts.items():
-            w = np.log(mu[xs]) - np.log(mu[xs].sum())
+            with np.errstate(divide="ignore"):  # pixels without mass: weight e^-inf = 0
+                w = np.log(mu[xs]) - np.log(mu[xs].sum())
             d = (alpha_a[xs] - alpha_b[xs]) / eps
             lmean_ab[J] = logsumexp(d + w)
             lmean_ba[J] = logsumexp(-d + w)

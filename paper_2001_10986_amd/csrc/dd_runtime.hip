@@ -8,8 +8,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/dd.h"
@@ -38,11 +40,109 @@ struct Cells {
   std::vector<int4> hq;
 };
 
+// Process-wide cache of device blocks: a schedule allocates and frees the
+// same buffers level by level, and the next solve repeats the sizes, so
+// freed blocks are kept and handed out again (a block of at least the asked
+// size and at most twice it, on the same device).  Taking a block back
+// synchronises the device first, as hipFree does, so no queued work can
+// still reach a block when it is handed out again.  At most kCacheMaxBytes
+// per device are kept; a failed allocation releases the device's cache and
+// tries once more.
+constexpr size_t kCacheMaxBytes = size_t(16) << 30;
+
+struct BlockCache {
+  std::mutex mu;
+  std::unordered_map<void*, std::pair<size_t, int>> live;  // block -> (bytes, device)
+  std::multimap<std::pair<int, size_t>, void*> idle;       // (device, bytes) -> block
+  std::unordered_map<int, size_t> idle_bytes;              // per device
+};
+
+BlockCache& block_cache() {
+  static BlockCache* bc = new BlockCache;  // never destroyed: blocks live until exit
+  return *bc;
+}
+
+hipError_t cache_malloc(void** p, size_t bytes) {
+  *p = nullptr;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  BlockCache& bc = block_cache();
+  {
+    std::lock_guard<std::mutex> lk(bc.mu);
+    auto it = bc.idle.lower_bound({dev, bytes});
+    if (it != bc.idle.end() && it->first.first == dev && it->first.second <= 2 * bytes) {
+      const size_t sz = it->first.second;
+      *p = it->second;
+      bc.idle.erase(it);
+      bc.idle_bytes[dev] -= sz;
+      bc.live[*p] = {sz, dev};
+      return hipSuccess;
+    }
+  }
+  e = hipMalloc(p, bytes);
+  if (e == hipErrorOutOfMemory) {
+    (void)hipGetLastError();
+    std::vector<void*> rel;
+    {
+      std::lock_guard<std::mutex> lk(bc.mu);
+      for (auto it = bc.idle.begin(); it != bc.idle.end();) {
+        if (it->first.first == dev) {
+          rel.push_back(it->second);
+          it = bc.idle.erase(it);
+        } else {
+          ++it;
+        }
+      }
+      bc.idle_bytes[dev] = 0;
+    }
+    for (void* q : rel) (void)hipFree(q);
+    e = hipMalloc(p, bytes);
+  }
+  if (e != hipSuccess) {
+    *p = nullptr;
+    return e;
+  }
+  std::lock_guard<std::mutex> lk(bc.mu);
+  bc.live[*p] = {bytes, dev};
+  return hipSuccess;
+}
+
+// Release a block of cache_malloc (or any device pointer, which goes to hipFree).
+void dfree(void* p) {
+  if (!p) return;
+  BlockCache& bc = block_cache();
+  size_t sz = 0;
+  int bdev = -1;
+  {
+    std::lock_guard<std::mutex> lk(bc.mu);
+    auto it = bc.live.find(p);
+    if (it != bc.live.end()) {
+      sz = it->second.first;
+      bdev = it->second.second;
+      bc.live.erase(it);
+    }
+  }
+  int dev = -1;
+  if (bdev < 0 || hipGetDevice(&dev) != hipSuccess || dev != bdev ||
+      hipDeviceSynchronize() != hipSuccess) {
+    (void)hipFree(p);
+    return;
+  }
+  std::lock_guard<std::mutex> lk(bc.mu);
+  if (bc.idle_bytes[dev] + sz > kCacheMaxBytes) {
+    (void)hipFree(p);  // synchronised above, so nothing queued reaches it
+    return;
+  }
+  bc.idle.insert({{dev, sz}, p});
+  bc.idle_bytes[dev] += sz;
+}
+
 template <typename T>
 hipError_t dmalloc(T** p, size_t n) {
   *p = nullptr;
   if (n == 0) n = 1;
-  return hipMalloc((void**)p, sizeof(T) * n);
+  return cache_malloc((void**)p, sizeof(T) * n);
 }
 
 // Work lists, streams and events through which the sweeps of one or more
@@ -89,18 +189,18 @@ static void runner_free(Runner& r) {
   if (r.ev1) (void)hipEventDestroy(r.ev1);
   for (auto& e : r.kev)
     if (e) (void)hipEventDestroy(e);
-  (void)hipFree(r.dP);
-  (void)hipFree(r.dstats);
+  (void)dfree(r.dP);
+  (void)dfree(r.dstats);
   if (r.hP) (void)hipHostFree(r.hP);
   if (r.hstats) (void)hipHostFree(r.hstats);
-  (void)hipFree(r.bin_count);
-  (void)hipFree(r.bin_list);
-  (void)hipFree(r.queue);
-  (void)hipFree(r.defer_count);
-  (void)hipFree(r.defer_list);
-  (void)hipFree(r.stream_tile);
-  (void)hipFree(r.stream_S);
-  (void)hipFree(r.stream_nu);
+  (void)dfree(r.bin_count);
+  (void)dfree(r.bin_list);
+  (void)dfree(r.queue);
+  (void)dfree(r.defer_count);
+  (void)dfree(r.defer_list);
+  (void)dfree(r.stream_tile);
+  (void)dfree(r.stream_S);
+  (void)dfree(r.stream_nu);
   r = Runner();
 }
 
@@ -135,8 +235,8 @@ static hipError_t runner_init(Runner& r, hipStream_t main, bool timing) {
 static hipError_t runner_reserve(Runner& r, int n_prob, int items) {
   hipError_t e;
   if (n_prob > r.n_cap) {
-    hipFree(r.dP);
-    hipFree(r.dstats);
+    dfree(r.dP);
+    dfree(r.dstats);
     if (r.hP) hipHostFree(r.hP);
     if (r.hstats) hipHostFree(r.hstats);
     r.dP = nullptr;
@@ -152,8 +252,8 @@ static hipError_t runner_reserve(Runner& r, int n_prob, int items) {
     r.n_cap = n_prob;
   }
   if (items > r.cap) {
-    hipFree(r.bin_list);
-    hipFree(r.defer_list);
+    dfree(r.bin_list);
+    dfree(r.defer_list);
     r.bin_list = nullptr;
     r.defer_list = nullptr;
     r.cap = 0;
@@ -187,9 +287,9 @@ static hipError_t runner_stream(Runner& r, int n_cells) {
   const int prev = stream_small(r) ? kStreamOwnWg : r.stream_prev >= 0 ? r.stream_prev + 16 : 64;
   const int want = std::min(std::min(n_cells, stream_limit(r)), prev);
   if (want <= r.stream_wgs) return hipSuccess;
-  hipFree(r.stream_tile);
-  hipFree(r.stream_S);
-  hipFree(r.stream_nu);
+  dfree(r.stream_tile);
+  dfree(r.stream_S);
+  dfree(r.stream_nu);
   r.stream_tile = nullptr;
   r.stream_S = nullptr;
   r.stream_nu = nullptr;
@@ -365,8 +465,8 @@ static dd_status upload_cells(dd_ctx* c) {
     std::vector<int2> org;
     build_cells(l.bh, l.bw, p, c->s, q, org);
     Cells& C = c->cells[p];
-    hipFree(C.q);
-    hipFree(C.org);
+    dfree(C.q);
+    dfree(C.org);
     C.q = nullptr;
     C.org = nullptr;
     C.n = (int)q.size();
@@ -380,17 +480,17 @@ static dd_status upload_cells(dd_ctx* c) {
   }
   const int need = std::max(c->cells[0].n, c->cells[1].n);
   if (need > c->cell_cap) {
-    hipFree(c->cell_toff);
-    hipFree(c->cell_U);
-    hipFree(c->cell_ooff);
-    hipFree(c->bin_list);
-    hipFree(c->r_cost);
-    hipFree(c->r_obj);
-    hipFree(c->r_err);
-    hipFree(c->r_loops);
-    hipFree(c->r_status);
-    hipFree(c->r_evals);
-    hipFree(c->defer_F);
+    dfree(c->cell_toff);
+    dfree(c->cell_U);
+    dfree(c->cell_ooff);
+    dfree(c->bin_list);
+    dfree(c->r_cost);
+    dfree(c->r_obj);
+    dfree(c->r_err);
+    dfree(c->r_loops);
+    dfree(c->r_status);
+    dfree(c->r_evals);
+    dfree(c->defer_F);
     HIPCHK(c, dmalloc(&c->cell_toff, need));
     HIPCHK(c, dmalloc(&c->cell_U, need));
     HIPCHK(c, dmalloc(&c->cell_ooff, need));
@@ -420,8 +520,8 @@ static dd_status ensure_entries(dd_ctx* c, int64_t need) {
     HIPCHK(c, hipMemcpyAsync(val, c->val, sizeof(double) * c->capE, hipMemcpyDeviceToDevice, c->st));
     HIPCHK(c, hipStreamSynchronize(c->st));
   }
-  hipFree(c->col);
-  hipFree(c->val);
+  dfree(c->col);
+  dfree(c->val);
   c->col = col;
   c->val = val;
   c->capE = cap;
@@ -431,9 +531,9 @@ static dd_status ensure_entries(dd_ctx* c, int64_t need) {
 static dd_status ensure_union(dd_ctx* c, int64_t need) {
   if (need <= c->capU) return DD_OK;
   int64_t cap = need + need / 4 + 4096;
-  hipFree(c->uni_key);
-  hipFree(c->uni_nu);
-  hipFree(c->uni_G);
+  dfree(c->uni_key);
+  dfree(c->uni_nu);
+  dfree(c->uni_G);
   HIPCHK(c, dmalloc(&c->uni_key, cap));
   HIPCHK(c, dmalloc(&c->uni_nu, cap));
   HIPCHK(c, dmalloc(&c->uni_G, cap));
@@ -443,19 +543,19 @@ static dd_status ensure_union(dd_ctx* c, int64_t need) {
 
 static dd_status ensure_px(dd_ctx* c, int64_t n) {
   if (n <= c->px_cap) return DD_OK;
-  hipFree(c->px_scratch);
+  dfree(c->px_scratch);
   HIPCHK(c, dmalloc(&c->px_scratch, n));
   c->px_cap = n;
   return DD_OK;
 }
 
 static void free_state(dd_ctx* c) {
-  hipFree(c->row_off);
-  hipFree(c->row_len);
-  hipFree(c->col);
-  hipFree(c->val);
-  hipFree(c->alpha[0]);
-  hipFree(c->alpha[1]);
+  dfree(c->row_off);
+  dfree(c->row_len);
+  dfree(c->col);
+  dfree(c->val);
+  dfree(c->alpha[0]);
+  dfree(c->alpha[1]);
   c->row_off = nullptr;
   c->row_len = nullptr;
   c->col = nullptr;
@@ -485,36 +585,36 @@ extern "C" void dd_free(dd_ctx* c) {
   if (c->st) hipStreamSynchronize(c->st);
   free_state(c);
   for (auto& l : c->L) {
-    hipFree(l.mu);
-    hipFree(l.nu);
+    dfree(l.mu);
+    dfree(l.nu);
   }
   for (int p = 0; p < 2; p++) {
-    hipFree(c->cells[p].q);
-    hipFree(c->cells[p].org);
+    dfree(c->cells[p].q);
+    dfree(c->cells[p].org);
   }
-  hipFree(c->cell_toff);
-  hipFree(c->cell_U);
-  hipFree(c->cell_ooff);
-  hipFree(c->bin_count);
-  hipFree(c->bin_list);
-  hipFree(c->r_cost);
-  hipFree(c->r_obj);
-  hipFree(c->r_err);
-  hipFree(c->r_loops);
-  hipFree(c->r_status);
-  hipFree(c->r_evals);
-  hipFree(c->defer_F);
-  hipFree(c->misc);
-  hipFree(c->warm_X);
-  hipFree(c->warm_Y);
-  hipFree(c->warm_count);
-  hipFree(c->alpha_prev);
-  hipFree(c->dcount);
-  hipFree(c->uni_key);
-  hipFree(c->uni_nu);
-  hipFree(c->uni_G);
-  hipFree(c->dscal);
-  hipFree(c->px_scratch);
+  dfree(c->cell_toff);
+  dfree(c->cell_U);
+  dfree(c->cell_ooff);
+  dfree(c->bin_count);
+  dfree(c->bin_list);
+  dfree(c->r_cost);
+  dfree(c->r_obj);
+  dfree(c->r_err);
+  dfree(c->r_loops);
+  dfree(c->r_status);
+  dfree(c->r_evals);
+  dfree(c->defer_F);
+  dfree(c->misc);
+  dfree(c->warm_X);
+  dfree(c->warm_Y);
+  dfree(c->warm_count);
+  dfree(c->alpha_prev);
+  dfree(c->dcount);
+  dfree(c->uni_key);
+  dfree(c->uni_nu);
+  dfree(c->uni_G);
+  dfree(c->dscal);
+  dfree(c->px_scratch);
   if (c->hscal) hipHostFree(c->hscal);
   runner_free(c->run);
   for (auto& e : c->warm_ev)
@@ -567,8 +667,8 @@ static dd_status init_level0(dd_ctx* c) {
     HIPCHK(c, hipMemsetAsync(c->alpha[p], 0, sizeof(double) * npx, c->st));
   }
   HIPCHK(c, hipStreamSynchronize(c->st));
-  hipFree(dy);
-  hipFree(dbm);
+  dfree(dy);
+  dfree(dbm);
   return upload_cells(c);
 }
 
@@ -787,8 +887,8 @@ static HalfParams make_params(dd_ctx* c, int part) {
 static dd_status warm_start(dd_ctx* c, const HalfParams& p) {
   const int rows = (p.n_cells + 63) / 64 * 64;
   if (rows > c->warm_rows) {
-    hipFree(c->warm_X);
-    hipFree(c->warm_Y);
+    dfree(c->warm_X);
+    dfree(c->warm_Y);
     c->warm_X = nullptr;
     c->warm_Y = nullptr;
     c->warm_rows = 0;
@@ -897,7 +997,7 @@ static dd_status sweep_begin(dd_ctx* c, int part, bool keep_prev, HalfParams* p)
   const Level& l = c->L[c->lev];
   const int64_t npx = (int64_t)l.H * l.W;
   if (npx > c->alpha_prev_cap) {
-    hipFree(c->alpha_prev);
+    dfree(c->alpha_prev);
     c->alpha_prev = nullptr;
     c->alpha_prev_cap = 0;
     HIPCHK(c, dmalloc(&c->alpha_prev, npx));
@@ -1043,15 +1143,15 @@ struct GlueScratch {
   int *ia = nullptr, *ib = nullptr, *incp = nullptr, *ince = nullptr, *elli = nullptr;
   int na = 0, ne = 0, max_it = 0, ellk = 0;
   ~GlueScratch() {
-    hipFree(dq);
-    hipFree(work);
-    hipFree(ellw);
-    hipFree(deg);
-    hipFree(ia);
-    hipFree(ib);
-    hipFree(incp);
-    hipFree(ince);
-    hipFree(elli);
+    dfree(dq);
+    dfree(work);
+    dfree(ellw);
+    dfree(deg);
+    dfree(ia);
+    dfree(ib);
+    dfree(incp);
+    dfree(ince);
+    dfree(elli);
   }
 };
 }  // namespace
@@ -1214,9 +1314,9 @@ extern "C" dd_status dd_refine(dd_ctx* c) {
     GlueScratch gs;
     dd_status gst = enqueue_glue(c, gs, dV, dinfo);
     if (gst != DD_OK) {
-      hipFree(dV);
-      hipFree(fg);
-      hipFree(dinfo);
+      dfree(dV);
+      dfree(fg);
+      dfree(dinfo);
       return gst;
     }
     long long n = (long long)lc.H * lc.W;
@@ -1228,7 +1328,7 @@ extern "C" dd_status dd_refine(dd_ctx* c) {
     c->refine_glue_iters = (int)hinfo[0];
     c->refine_glue_resid = hinfo[2] > 0 ? std::sqrt(hinfo[1] / hinfo[2]) : 0.0;
   }
-  hipFree(dinfo);
+  dfree(dinfo);
   // 2. fine potentials
   double *fa = nullptr, *fb = nullptr;
   const size_t nf = (size_t)lf.H * lf.W;
@@ -1254,8 +1354,8 @@ extern "C" dd_status dd_refine(dd_ctx* c) {
   ddk::launch_refine_rows(R, c->st);
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->st));
-  hipFree(dV);
-  hipFree(fg);
+  dfree(dV);
+  dfree(fg);
   free_state(c);
   c->row_off = roff;
   c->row_len = rlen;
@@ -1375,11 +1475,11 @@ extern "C" dd_status dd_certificate(dd_ctx* c, dd_cert_report* r, double* alpha_
   const long long npx = (long long)l.H * l.W;
   double *dV = nullptr, *ah = nullptr, *bh = nullptr, *scr = nullptr, *sums = nullptr;
   auto release = [&]() {
-    hipFree(dV);
-    hipFree(ah);
-    hipFree(bh);
-    hipFree(scr);
-    hipFree(sums);
+    dfree(dV);
+    dfree(ah);
+    dfree(bh);
+    dfree(scr);
+    dfree(sums);
   };
   if (dmalloc(&dV, (size_t)c->cells[0].n) || dmalloc(&ah, (size_t)npx) ||
       dmalloc(&bh, (size_t)npx) || dmalloc(&scr, 2 * (size_t)npx) || dmalloc(&sums, 8)) {
@@ -1468,9 +1568,9 @@ extern "C" dd_status dd_export_plan(dd_ctx* c, dd_plan_view* v) {
   if (v->alpha_b)
     HIPCHK(c, hipMemcpyAsync(v->alpha_b, c->alpha[1], sizeof(double) * npx, hipMemcpyDeviceToHost, c->st));
   HIPCHK(c, hipStreamSynchronize(c->st));
-  hipFree(rp);
-  hipFree(col);
-  hipFree(val);
+  dfree(rp);
+  dfree(col);
+  dfree(val);
   return DD_OK;
 }
 
@@ -1516,7 +1616,7 @@ extern "C" dd_status dd_import_state(dd_ctx* c, const dd_plan_view* v) {
                              hipMemcpyHostToDevice, c->st));
   }
   HIPCHK(c, hipStreamSynchronize(c->st));
-  hipFree(rp);
+  dfree(rp);
   c->last_part = -1;
   return upload_cells(c);
 }
@@ -1921,11 +2021,11 @@ const int kTuneCells[] = {0, 1, 2, 4};             // 0: persistent workgroups
 }  // namespace
 
 static void snap_free(Snapshot& s) {
-  (void)hipFree(s.row_off);
-  (void)hipFree(s.row_len);
-  (void)hipFree(s.col);
-  (void)hipFree(s.val);
-  (void)hipFree(s.alpha);
+  (void)dfree(s.row_off);
+  (void)dfree(s.row_len);
+  (void)dfree(s.col);
+  (void)dfree(s.val);
+  (void)dfree(s.alpha);
   s = Snapshot();
 }
 
