@@ -34,6 +34,13 @@
  * dd_options.stream (a hipStream_t, NULL = default stream); calls that return
  * host values synchronise that stream.  A context is not thread-safe.
  *
+ * Device memory: the contexts' buffers come from a process-wide cache of
+ * device blocks.  A freed buffer (a level change, dd_free) is kept after a
+ * device synchronisation and handed out again to a later request of at
+ * least half its size on the same device; at most 16 GiB per device are
+ * kept, and they stay allocated until the process ends.  A failed
+ * allocation releases the device's cache and tries once more.
+ *
  * Errors: every call returns a dd_status; negative values are errors and
  * leave a message readable with dd_last_error(ctx).  No exception crosses the
  * ABI.  DD_ENOTCONV (positive) is a warning: some cell hit the Sinkhorn
