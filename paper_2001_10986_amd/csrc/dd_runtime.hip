@@ -172,6 +172,7 @@ struct Runner {
   int* defer_list = nullptr;
   int stream_wgs = 0;
   int stream_prev = -1;            // streamed-solver cells of the last sweep (-1: none yet)
+  int big_prev = -1;               // log-domain-bin cells of the last sweep (-1: unknown)
   float* stream_tile = nullptr;
   float* stream_S = nullptr;
   float* stream_nu = nullptr;
@@ -337,6 +338,10 @@ static ddk::SweepGrid plan_grid(const Runner& r, int total_cells, int max_cells,
   // the streamed solver's tiles (up to 2 MiB each) are re-read every loop:
   // fewer workgroups keep more of them in the last-level cache
   gr.bin[ddk::kNBins - 2] = std::min(g, stream_limit(r));
+  // the log-domain bin is usually empty, and an empty persistent grid still
+  // waits for compute units behind the other bins' workgroups: size it from
+  // the last sweep's count (kept unknown across refinements and growing eps)
+  if (r.big_prev >= 0) gr.bin[ddk::kNBins - 1] = std::min(g, std::max(32, r.big_prev + 16));
   gr.newton = std::max(1, std::min(total_cells, r.newton_per_cu * r.n_cu));
   gr.other = std::max(1, std::min(max_cells, std::max(64, 8 * r.n_cu / std::max(n_prob, 1))));
   return gr;
@@ -820,6 +825,7 @@ extern "C" dd_status dd_set_eps(dd_ctx* c, double eps) {
   if (!c) return DD_EINVAL;
   if (!(eps > 0)) return fail(c, DD_EINVAL, "eps must be positive");
   if (eps != c->eps) c->warm_fresh[0] = c->warm_fresh[1] = 1;
+  if (eps > c->eps) c->run.big_prev = -1;  // supports may grow past the last sweep's bins
   c->eps = eps;
   return DD_OK;
 }
@@ -1123,6 +1129,7 @@ extern "C" dd_status dd_half_iterate(dd_ctx* c, int part, dd_iter_stats* out) {
   double mk[3 * DD_N_KERNELS];
   if (kev) runner_kernel_ms(r, mk);
   r.stream_prev = r.hstats[0].cells_bin[ddk::kNBins - 2];
+  r.big_prev = r.hstats[0].cells_bin[ddk::kNBins - 1];
   return sweep_finish(c, part, r.hstats[0], ms, kev ? mk : nullptr, out);
 }
 
@@ -1366,6 +1373,7 @@ extern "C" dd_status dd_refine(dd_ctx* c) {
   c->alpha[1] = fb;
   c->nnz = nnzf;
   c->lev++;
+  c->run.big_prev = -1;
   c->nb = nbf;
   c->last_part = -1;
   c->warm_fresh[0] = c->warm_fresh[1] = 1;
